@@ -1,0 +1,66 @@
+"""Reference gradients of the circulant layer y = C(a) x (test infrastructure only).
+
+The layer is the f = 1 case of the product (Definition 2 with f = 1, a row-identified
+circulant): y_i = sum_k a_k x_((i+k) mod n), applied to each row of a batch with one
+shared a. Gradients follow PyTorch's conventions; for complex tensors the gradient of a
+real loss is the conjugate Wirtinger one (grad = M^H g for y = M x).
+
+Two independent references, both FP64 on the CPU:
+* ``dense_autograd``: the dense matrix built by index gather, differentiated by torch.
+* ``finite_differences``: central differences of the loss sum(g * y) for real data.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+
+def _dense(a: torch.Tensor) -> torch.Tensor:
+    n = a.shape[0]
+    i = torch.arange(n)[:, None]
+    j = torch.arange(n)[None, :]
+    return a[(j - i) % n]  # f = 1: A[i][j] = a[(j - i) mod n]
+
+
+def dense_forward(a, x):
+    """y (batch, n) = x @ A^T for each row of x, FP64/complex128 on the CPU."""
+    at = torch.as_tensor(np.asarray(a)).to(torch.complex128 if np.iscomplexobj(a) else torch.float64)
+    xt = torch.as_tensor(np.asarray(x)).to(at.dtype)
+    return (xt @ _dense(at).T).numpy()
+
+
+def dense_autograd(a, x, g):
+    """(y, grad_a, grad_x) of L = Re sum(conj(g) * y) via torch autograd on the dense matrix.
+
+    For real inputs this is L = sum(g * y), so grad_a = dL/da and grad_x = dL/dx.
+    """
+    cplx = np.iscomplexobj(a) or np.iscomplexobj(x) or np.iscomplexobj(g)
+    dt = torch.complex128 if cplx else torch.float64
+    at = torch.as_tensor(np.asarray(a)).to(dt).clone().requires_grad_(True)
+    xt = torch.as_tensor(np.asarray(x)).to(dt).clone().requires_grad_(True)
+    gt = torch.as_tensor(np.asarray(g)).to(dt)
+    y = xt @ _dense(at).T
+    y.backward(gt)
+    return y.detach().numpy(), at.grad.numpy(), xt.grad.numpy()
+
+
+def finite_differences(a, x, g, h: float = 1e-6):
+    """Central differences of L = sum(g * y(a, x)) for real a (n,), x (batch, n)."""
+    a = np.asarray(a, dtype=np.float64)
+    x = np.asarray(x, dtype=np.float64)
+    g = np.asarray(g, dtype=np.float64)
+
+    def loss(a_, x_):
+        return float((g * dense_forward(a_, x_)).sum())
+
+    ga = np.zeros_like(a)
+    for k in range(a.shape[0]):
+        e = np.zeros_like(a)
+        e[k] = h
+        ga[k] = (loss(a + e, x) - loss(a - e, x)) / (2 * h)
+    gx = np.zeros_like(x)
+    for idx in np.ndindex(*x.shape):
+        e = np.zeros_like(x)
+        e[idx] = h
+        gx[idx] = (loss(a, x + e) - loss(a, x - e)) / (2 * h)
+    return ga, gx

@@ -1,0 +1,103 @@
+"""Plant plausible mistakes in the oracle (on the CPU, via monkeypatch) and check that the
+pins catch every one of them: a dropped term, a wrong sign, a wrong index, a transposed
+operand, a wrong root."""
+import random
+
+import numpy as np
+import pytest
+
+from oracle import fcirc as O
+from oracle import ring
+
+P = 998244353
+
+
+def _pins_pass() -> bool:
+    """A compact re-run of the pins: closed form at n = 2, brute force and FFT at larger n."""
+    rng = random.Random(0)
+    try:
+        for _ in range(3):
+            a0, a1, x0, x1 = (rng.randrange(P) for _ in range(4))
+            f = pow(rng.randrange(2, P), 2, P)
+            want = [(a0 * x0 + a1 * x1) % P, (f * a1 * x0 + a0 * x1) % P]
+            if O.alg1_modp([a0, a1], [x0, x1], f, P) != want:
+                return False
+            if O.levels_matvec_modp([a0, a1], [x0, x1], f, P).tolist() != want:
+                return False
+        n = 16
+        a = [rng.randrange(64) for _ in range(n)]
+        x = [rng.randrange(64) for _ in range(n)]
+        cyc = [sum(a[k] * x[(i + k) % n] for k in range(n)) % P for i in range(n)]
+        neg = [sum(a[k] * x[(i + k) % n] * (-1 if i + k >= n else 1) for k in range(n)) % P
+               for i in range(n)]
+        for f, want in ((1, cyc), (P - 1, neg)):
+            if O.alg1_modp(a, x, f, P) != want:
+                return False
+            if O.levels_matvec_modp(a, x, f, P).tolist() != want:
+                return False
+            if O.dense_matvec_modp(a, x, f, P).tolist() != want:
+                return False
+        return O.fcirc_matrix([10, 100, 1000], 7) == [[10, 100, 1000], [7000, 10, 100], [700, 7000, 10]]
+    except (ValueError, AssertionError, ZeroDivisionError):
+        return False
+
+
+def test_unmutated_oracle_passes():
+    assert _pins_pass()
+
+
+def _mut_sub_is_add(mp):
+    mp.setattr(O.ModP, "sub", lambda self, u, v: (u + v) % self.p)
+
+
+def _mut_merge_drops_half(mp):
+    mp.setattr(O.ModP, "div", lambda self, u, v: u * ring.inv(v, self.p) % self.p if v != 2 else u)
+
+
+def _mut_wrong_root(mp):
+    real = ring.sqrt_mod
+    mp.setattr(ring, "sqrt_mod", lambda v, p, rng=None: real(v, p, rng) * 3 % p)
+
+
+def _mut_transposed_matrix(mp):
+    real = O.fcirc_matrix_np
+    mp.setattr(O, "fcirc_matrix_np", lambda a, f, p=None: real(a, f, p).T)
+
+
+def _mut_dense_drops_f(mp):
+    real = O.fcirc_matrix_np
+    mp.setattr(O, "fcirc_matrix_np", lambda a, f, p=None: real(a, 1, p))
+
+
+def _mut_levels_swapped_children(mp):
+    real = O.node_roots_modp
+
+    def swapped(n, f, p):
+        return [(p - g) % p if d == 1 else g for d, g in enumerate(real(n, f, p))]
+    mp.setattr(O, "node_roots_modp", swapped)
+
+
+def _mut_levels_inverse_wrong(mp):
+    mp.setattr(O, "_inv_vec", lambda v, p: v % p)
+
+
+def _mut_definition_shift_left(mp):
+    def bad(a, f, p=None):
+        n = len(a)
+        rows = [list(a)]
+        for _ in range(n - 1):
+            prev = rows[-1]
+            last = prev[0] * f
+            rows.append(prev[1:] + [last % p if p else last])
+        return [[int(v) % p for v in r] for r in rows] if p else rows
+    mp.setattr(O, "fcirc_matrix", bad)
+
+
+@pytest.mark.parametrize("mutation", [
+    _mut_sub_is_add, _mut_merge_drops_half, _mut_wrong_root, _mut_transposed_matrix,
+    _mut_dense_drops_f, _mut_levels_swapped_children, _mut_levels_inverse_wrong,
+    _mut_definition_shift_left,
+])
+def test_pins_catch_mutation(mutation, monkeypatch):
+    mutation(monkeypatch)
+    assert not _pins_pass()
