@@ -1,0 +1,162 @@
+/*
+ * libfcirc -- FFT-free f-circulant matrix-vector products on AMD Instinct MI355X (gfx950).
+ *
+ * The product follows A. Rosowski, "On Fast Computation of a Circulant Matrix-Vector
+ * Product" (arXiv 2103.02605):
+ *   - Definition 2 (section 1.2): an n x n matrix is f-circulant when each row is the
+ *     previous row shifted right by one place, the entry that wraps around to column 1
+ *     being multiplied by f. Section 1.2 identifies such a matrix by its FIRST ROW a, so
+ *     with 0-based indices A[i][j] = a[j-i] for j >= i and A[i][j] = f * a[n+j-i] for j < i.
+ *   - Theorem 1 (section 2): for n a power of two, in a ring holding an n-th root of f,
+ *     an n-th root of unity, 1/2 and 1/f, y = A x costs O(n log n) operations.
+ *   - Algorithm 1 (section 2): split A into a sqrt(f)- and a (-sqrt f)-circulant product
+ *     of half size, recurse down to scalars, merge the two halves back.
+ *
+ * All device work is asynchronous on the stream passed in (a hipStream_t, given here as
+ * void*; NULL means the null stream). Every entry point validates its arguments on the
+ * host first and returns an error without enqueueing anything when they are invalid.
+ * The caller owns every data buffer. The context owns plans, twiddle tables, workspaces
+ * and captured graphs, and frees them in fcirc_destroy.
+ *
+ * Threading: one context serves one host thread at a time (calls that share a context
+ * must be serialised by the caller). Output buffers must not overlap inputs.
+ */
+#ifndef FCIRC_H
+#define FCIRC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fcirc_ctx fcirc_ctx;
+
+/* The ring R of Theorem 1. */
+typedef enum {
+  FCIRC_ZP_998244353 = 0, /* Z/p, p = 119*2^23 + 1: data uint32 in [0,p), n <= 2^23     */
+  FCIRC_ZP_469762049 = 1, /* Z/p, p =   7*2^26 + 1: data uint32 in [0,p), n <= 2^26     */
+  FCIRC_ZP_167772161 = 2, /* Z/p, p =   5*2^25 + 1: data uint32 in [0,p), n <= 2^25     */
+  FCIRC_C64 = 3,          /* complex numbers: data interleaved complex64 (float re, im)   */
+  FCIRC_R32 = 4           /* real data float32; complex arithmetic inside; f real         */
+} fcirc_ring;
+
+typedef enum {
+  FCIRC_OK = 0,
+  FCIRC_EINVAL = 1,  /* null pointer, unknown ring, bad item list, overlapping buffers    */
+  FCIRC_ESIZE = 2,   /* n not a power of two, n = 0, or n above the ring's limit          */
+  FCIRC_ENOROOT = 3, /* f is zero or has no n-th root in the ring (Theorem 1's condition) */
+  FCIRC_ERANGE = 4,  /* a product coefficient fell outside the exactly representable range
+                        (reported by fcirc_check after the work has run)                  */
+  FCIRC_ENOMEM = 5,  /* device allocation failed or exceeded FCIRC_WORKSPACE_LIMIT        */
+  FCIRC_EDEVICE = 6  /* no usable gfx950 device, or a HIP call failed                     */
+} fcirc_status;
+
+/* Create a context on HIP device `hip_device` (must be gfx950). */
+fcirc_status fcirc_create(fcirc_ctx **ctx, int hip_device);
+/* Synchronise the device and free everything the context owns. NULL is allowed. */
+void fcirc_destroy(fcirc_ctx *ctx);
+const char *fcirc_strerror(fcirc_status s);
+
+/*
+ * y = A(a, f) x: one f-circulant product of size n (Definition 2, Theorem 1, Algorithm 1).
+ *   a : device, n elements, the FIRST ROW of A (section 1.2's row convention).
+ *   x : device, n elements.  y : device, n elements (written; must not overlap a or x).
+ *   f : host pointer to ONE ring element: uint32_t in [0,p) for Z/p, double[2] (re, im)
+ *       for FCIRC_C64, double for FCIRC_R32.
+ *   Z/p elements must be canonical (in [0,p)); outputs are canonical.
+ * Errors: EINVAL (null pointer), ESIZE (n not a power of two, or n above 2^23 / 2^26 /
+ * 2^25 for the three primes and 2^26 for the complex rings), ENOROOT (f = 0 or f has no
+ * n-th root in Z/p). Complex rings accept any nonzero f; the accuracy statement (relative
+ * L2 error near 1e-6 for n <= 2^16) holds for |f| = 1.
+ */
+fcirc_status fcirc_matvec(fcirc_ctx *ctx, const void *a, const void *x, void *y, uint64_t n,
+                          const void *f, fcirc_ring ring, void *stream);
+
+/*
+ * `count` independent products of the same size n and the same f, stored back to back
+ * (instance k at element offset k*n of a, x and y). Same rules as fcirc_matvec.
+ */
+fcirc_status fcirc_matvec_many(fcirc_ctx *ctx, const void *a, const void *x, void *y, uint64_t n,
+                               uint32_t count, const void *f, fcirc_ring ring, void *stream);
+
+/*
+ * Exact product of two integer polynomials (section 3.1: a polynomial product is a
+ * circulant product after filling up to a power of two).
+ *   a : device int32[na], b : device int32[nb], coefficients of degree 0 first.
+ *   c : device int64[na+nb-1], written with the exact coefficients.
+ * The cyclic length N is the smallest power of two >= na+nb-1 (N <= 2^23). The product
+ * is computed modulo 998244353, 469762049 and 167772161 and combined by the Chinese
+ * remainder theorem. It is exact when every |c_k| < 998244353*469762049 (about 4.7e17);
+ * a coefficient outside that range is written as 0 and makes fcirc_check return ERANGE.
+ */
+fcirc_status fcirc_polymul_i64(fcirc_ctx *ctx, const int32_t *a, uint64_t na, const int32_t *b,
+                               uint64_t nb, int64_t *c, void *stream);
+
+/*
+ * Exact product of two non-negative integers given as little-endian 16-bit limbs
+ * (section 3.2 applies Algorithm 1 to large integers).
+ *   a : device uint16[na], b : device uint16[nb], c : device uint16[na+nb] (written).
+ * Requires N = smallest power of two >= na+nb-1 to be <= 2^23 and min(na,nb) <= 2^20.
+ */
+fcirc_status fcirc_bigint_mul(fcirc_ctx *ctx, const uint16_t *a, uint64_t na, const uint16_t *b,
+                              uint64_t nb, uint16_t *c, void *stream);
+
+/*
+ * Many independent products of different power-of-two sizes in one persistent launch.
+ * items (host array of `count`) give each instance's element offsets into a_base,
+ * x_base and y_base and its log2 size (0 <= log2n <= 16). All instances share ring
+ * and f. The launch is captured in a HIP graph on first use of an item list and
+ * replayed when the same list (same pointers, offsets and sizes) comes again.
+ */
+typedef struct {
+  uint64_t a_off, x_off, y_off; /* element offsets */
+  uint32_t log2n;
+  uint32_t reserved;            /* must be 0 */
+} fcirc_item;
+
+fcirc_status fcirc_matvec_batched(fcirc_ctx *ctx, const void *a_base, const void *x_base,
+                                  void *y_base, const fcirc_item *items, uint32_t count,
+                                  const void *f, fcirc_ring ring, void *stream);
+
+/*
+ * Circulant layer over a batch with one shared row (f = 1; rings C64 or R32):
+ *   forward : y[b] = C(a) x[b] for b < batch (x, y: batch*n elements, row-major).
+ *   backward: gx[b] = C(a)^H gy[b] and ga = sum_b C(gy[b]) conj(x[b]), i.e. the
+ *             gradients of a real loss with upstream gradient gy (PyTorch's convention
+ *             for complex tensors; the conjugates drop out for real data).
+ * ga or gx may be NULL to skip that gradient.
+ */
+fcirc_status fcirc_matvec_fwd_shared(fcirc_ctx *ctx, const void *a, const void *x, void *y,
+                                     uint64_t n, uint32_t batch, fcirc_ring ring, void *stream);
+fcirc_status fcirc_matvec_backward(fcirc_ctx *ctx, const void *a, const void *x, const void *gy,
+                                   void *ga, void *gx, uint64_t n, uint32_t batch,
+                                   fcirc_ring ring, void *stream);
+
+/* Synchronise `stream` and return (then clear) the sticky device status (ERANGE). */
+fcirc_status fcirc_check(fcirc_ctx *ctx, void *stream);
+
+/*
+ * Per-kernel timing with HIP events recorded on the caller's stream around each kernel
+ * the library launches (for measurement; off by default). fcirc_stage_times
+ * synchronises, then writes up to `max` entries: the kernel name, the number of launches
+ * and the summed milliseconds since the last reset. Returns the number of kernel names.
+ */
+fcirc_status fcirc_set_timing(fcirc_ctx *ctx, int enable);
+int fcirc_stage_times(fcirc_ctx *ctx, const char **names, uint64_t *launches, double *ms, int max);
+
+/*
+ * Tuning. fcirc_tune times the candidate split points and tile shapes for one
+ * (ring, n) on scratch buffers and keeps the fastest for later calls with this context.
+ * fcirc_set_split forces the number of top levels streamed through HBM before the
+ * LDS-resident block (0 = single block kernel when it fits; -1 = back to automatic).
+ * fcirc_get_split reports the split that fcirc_matvec would use for (ring, n).
+ */
+fcirc_status fcirc_tune(fcirc_ctx *ctx, uint64_t n, fcirc_ring ring, void *stream);
+fcirc_status fcirc_set_split(fcirc_ctx *ctx, int top_levels);
+int fcirc_get_split(fcirc_ctx *ctx, uint64_t n, fcirc_ring ring);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FCIRC_H */

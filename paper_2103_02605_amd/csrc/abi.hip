@@ -1,0 +1,222 @@
+// C-ABI of libfcirc: argument validation, context management, dispatch.
+// The operations are defined in include/fcirc.h; validation happens on the host before
+// anything is enqueued, so an error return means nothing was written.
+#include <hip/hip_runtime.h>
+
+#include <cstdlib>
+#include <cstring>
+
+#include "host.hpp"
+
+using namespace fcirc;
+
+struct fcirc_ctx {
+  Ctx c;
+};
+
+namespace {
+
+bool is_pow2(uint64_t n) { return n && !(n & (n - 1)); }
+
+bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
+  const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+  return x < y + nb && y < x + na;
+}
+
+size_t elem_bytes(fcirc_ring r) {
+  switch (r) {
+    case FCIRC_C64: return 8;
+    case FCIRC_R32: return 4;
+    default: return 4;
+  }
+}
+
+bool known_ring(int r) { return r >= FCIRC_ZP_998244353 && r <= FCIRC_R32; }
+
+// Common checks of a product of `count` instances of size n. Returns FCIRC_OK and L.
+fcirc_status check_product(fcirc_ctx* ctx, const void* a, const void* x, const void* y, uint64_t n, uint64_t count,
+                           const void* f, fcirc_ring ring, int* L) {
+  if (!ctx || !a || !x || !y || !f || !known_ring(ring)) return FCIRC_EINVAL;
+  if (!is_pow2(n)) return FCIRC_ESIZE;
+  const int l = ilog2(n);
+  if (ring <= FCIRC_ZP_167772161) {
+    const uint32_t p = zp_prime(ring);
+    if (l > zp_two_adic(p)) return FCIRC_ESIZE;
+    const uint32_t fv = *(const uint32_t*)f;
+    if (fv >= p) return FCIRC_EINVAL;
+    if (fv == 0) return FCIRC_ENOROOT;
+  } else {
+    if (l > 26) return FCIRC_ESIZE;
+    if (ring == FCIRC_C64) {
+      const double* fc = (const double*)f;
+      if (fc[0] == 0.0 && fc[1] == 0.0) return FCIRC_ENOROOT;
+    } else if (*(const double*)f == 0.0) {
+      return FCIRC_ENOROOT;
+    }
+  }
+  const size_t bytes = (size_t)n * count * elem_bytes(ring);
+  if (overlaps(y, bytes, a, bytes) || overlaps(y, bytes, x, bytes)) return FCIRC_EINVAL;
+  *L = l;
+  return FCIRC_OK;
+}
+
+fcirc_status dispatch(fcirc_ctx* ctx, const void* a, const void* x, void* y, int L, uint32_t count, const void* f,
+                      fcirc_ring ring, hipStream_t s) {
+  if (hipSetDevice(ctx->c.device) != hipSuccess) return FCIRC_EDEVICE;
+  if (ring <= FCIRC_ZP_167772161)
+    return zp_matvec(ctx->c, (const uint32_t*)a, (const uint32_t*)x, (uint32_t*)y, L, count, zp_prime(ring),
+                     *(const uint32_t*)f, s);
+  if (ring == FCIRC_C64) {
+    const double* fc = (const double*)f;
+    return c32_matvec(ctx->c, a, x, y, L, count, fc[0], fc[1], false, s);
+  }
+  return c32_matvec(ctx->c, a, x, y, L, count, *(const double*)f, 0.0, true, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* fcirc_strerror(fcirc_status s) {
+  switch (s) {
+    case FCIRC_OK: return "ok";
+    case FCIRC_EINVAL: return "invalid argument";
+    case FCIRC_ESIZE: return "size not a power of two or above the ring's limit";
+    case FCIRC_ENOROOT: return "f has no n-th root in the ring (or f is zero)";
+    case FCIRC_ERANGE: return "a result coefficient is outside the exactly representable range";
+    case FCIRC_ENOMEM: return "device memory allocation failed or exceeded the workspace limit";
+    case FCIRC_EDEVICE: return "no usable gfx950 device, or a HIP call failed";
+  }
+  return "unknown status";
+}
+
+fcirc_status fcirc_create(fcirc_ctx** out, int dev) {
+  if (!out) return FCIRC_EINVAL;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || dev < 0 || dev >= ndev) {
+    (void)hipGetLastError();
+    return FCIRC_EDEVICE;
+  }
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return FCIRC_EDEVICE;
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return FCIRC_EDEVICE;
+  if (hipSetDevice(dev) != hipSuccess) return FCIRC_EDEVICE;
+  fcirc_ctx* ctx = new fcirc_ctx;
+  ctx->c.device = dev;
+  ctx->c.prop = prop;
+  if (const char* lim = std::getenv("FCIRC_WORKSPACE_LIMIT")) ctx->c.ws_limit = (size_t)std::strtoull(lim, nullptr, 10);
+  if (const char* dbg = std::getenv("FCIRC_DEBUG_SYNC")) ctx->c.debug_sync = dbg[0] == '1';
+  if (hipMalloc(&ctx->c.d_status, sizeof(uint32_t)) != hipSuccess ||
+      hipMemset(ctx->c.d_status, 0, sizeof(uint32_t)) != hipSuccess) {
+    delete ctx;
+    return FCIRC_EDEVICE;
+  }
+  *out = ctx;
+  return FCIRC_OK;
+}
+
+void fcirc_destroy(fcirc_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->c.device);
+  (void)hipDeviceSynchronize();
+  for (auto& t : ctx->c.zp) {
+    (void)hipFree(t.tw);
+    (void)hipFree(t.twi);
+  }
+  for (auto& t : ctx->c.c32) {
+    (void)hipFree(t.tw);
+    (void)hipFree(t.twi);
+  }
+  release_graphs(ctx->c);
+  if (ctx->c.ws) (void)hipFree(ctx->c.ws);
+  if (ctx->c.d_status) (void)hipFree(ctx->c.d_status);
+  delete ctx;
+}
+
+fcirc_status fcirc_matvec(fcirc_ctx* ctx, const void* a, const void* x, void* y, uint64_t n, const void* f,
+                          fcirc_ring ring, void* stream) {
+  int L = 0;
+  fcirc_status st = check_product(ctx, a, x, y, n, 1, f, ring, &L);
+  if (st != FCIRC_OK) return st;
+  return dispatch(ctx, a, x, y, L, 1, f, ring, (hipStream_t)stream);
+}
+
+fcirc_status fcirc_matvec_many(fcirc_ctx* ctx, const void* a, const void* x, void* y, uint64_t n, uint32_t count,
+                               const void* f, fcirc_ring ring, void* stream) {
+  if (count == 0) return ctx && a && x && y && f ? FCIRC_OK : FCIRC_EINVAL;
+  int L = 0;
+  fcirc_status st = check_product(ctx, a, x, y, n, count, f, ring, &L);
+  if (st != FCIRC_OK) return st;
+  if ((uint64_t)count * (n >> 12 ? (n >> 12) : 1) * 2 > 0x7fffffffull) return FCIRC_ESIZE;  // grid limit
+  return dispatch(ctx, a, x, y, L, count, f, ring, (hipStream_t)stream);
+}
+
+fcirc_status fcirc_polymul_i64(fcirc_ctx* ctx, const int32_t* a, uint64_t na, const int32_t* b, uint64_t nb, int64_t* c,
+                               void* stream) {
+  if (!ctx || !a || !b || !c || na == 0 || nb == 0) return FCIRC_EINVAL;
+  const uint64_t nc = na + nb - 1;
+  if (nc > (1ull << 23)) return FCIRC_ESIZE;
+  if (overlaps(c, nc * 8, a, na * 4) || overlaps(c, nc * 8, b, nb * 4)) return FCIRC_EINVAL;
+  if (hipSetDevice(ctx->c.device) != hipSuccess) return FCIRC_EDEVICE;
+  return polymul_i64(ctx->c, a, na, b, nb, c, (hipStream_t)stream);
+}
+
+fcirc_status fcirc_bigint_mul(fcirc_ctx* ctx, const uint16_t* a, uint64_t na, const uint16_t* b, uint64_t nb, uint16_t* c,
+                              void* stream) {
+  if (!ctx || !a || !b || !c || na == 0 || nb == 0) return FCIRC_EINVAL;
+  const uint64_t nc = na + nb - 1;
+  if (nc > (1ull << 23) || (na < nb ? na : nb) > (1ull << 20)) return FCIRC_ESIZE;
+  if (overlaps(c, (nc + 1) * 2, a, na * 2) || overlaps(c, (nc + 1) * 2, b, nb * 2)) return FCIRC_EINVAL;
+  if (hipSetDevice(ctx->c.device) != hipSuccess) return FCIRC_EDEVICE;
+  return bigint_mul(ctx->c, a, na, b, nb, c, (hipStream_t)stream);
+}
+
+fcirc_status fcirc_check(fcirc_ctx* ctx, void* stream) {
+  if (!ctx) return FCIRC_EINVAL;
+  if (hipSetDevice(ctx->c.device) != hipSuccess) return FCIRC_EDEVICE;
+  if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return hip_status(hipGetLastError());
+  uint32_t st = 0;
+  if (hipMemcpy(&st, ctx->c.d_status, sizeof st, hipMemcpyDeviceToHost) != hipSuccess) return FCIRC_EDEVICE;
+  if (st) {
+    if (hipMemset(ctx->c.d_status, 0, sizeof(uint32_t)) != hipSuccess) return FCIRC_EDEVICE;
+    return FCIRC_ERANGE;
+  }
+  return FCIRC_OK;
+}
+
+fcirc_status fcirc_set_timing(fcirc_ctx* ctx, int enable) {
+  if (!ctx) return FCIRC_EINVAL;
+  ctx->c.timer.collect();
+  ctx->c.timer.enabled = enable != 0;
+  for (auto& v : ctx->c.timer.launches) v = 0;
+  for (auto& v : ctx->c.timer.ms) v = 0.0;
+  return FCIRC_OK;
+}
+
+int fcirc_stage_times(fcirc_ctx* ctx, const char** names, uint64_t* launches, double* ms, int max) {
+  if (!ctx) return -1;
+  ctx->c.timer.collect();
+  const int n = (int)ctx->c.timer.names.size();
+  for (int i = 0; i < n && i < max; ++i) {
+    if (names) names[i] = ctx->c.timer.names[i].c_str();
+    if (launches) launches[i] = ctx->c.timer.launches[i];
+    if (ms) ms[i] = ctx->c.timer.ms[i];
+  }
+  return n;
+}
+
+fcirc_status fcirc_set_split(fcirc_ctx* ctx, int top_levels) {
+  if (!ctx || top_levels < -1 || top_levels > 26) return FCIRC_EINVAL;
+  ctx->c.forced_top = top_levels;
+  return FCIRC_OK;
+}
+
+int fcirc_get_split(fcirc_ctx* ctx, uint64_t n, fcirc_ring ring) {
+  if (!ctx || !is_pow2(n) || !known_ring(ring)) return -1;
+  const int L = ilog2(n);
+  const Schedule S = make_schedule(L, ring == FCIRC_C64 || ring == FCIRC_R32 ? 3 : 2, effective_top(ctx->c, ring, L));
+  return L - S.block_levels;
+}
+
+}  // extern "C"

@@ -1,0 +1,299 @@
+// Applications of the f-circulant product (Rosowski, arXiv 2103.02605, section 3):
+// exact integer polynomial products (section 3.1) and large-integer products (the
+// application of section 3.2), through three Z/p products and the Chinese remainder
+// theorem.
+//
+// Section 3.1 fills both polynomials up to a power-of-two length N and multiplies them as
+// one circulant product. The cyclic convolution sum_j a_j b_((i-j) mod N) equals
+// (C(r) b)_i for the circulant whose first row is r_k = a_((-k) mod N), so the row loader
+// reads a in reversed index order and the vector loader reads b; both fill with zeros.
+// With N >= na + nb - 1 the cyclic and the plain product coincide.
+//
+// The CRT uses Garner's mixed-radix digits v1, v2, v3 (x = v1 + v2 p1 + v3 p1 p2) and
+// reads a signed result with |c| < p1 p2 as v3 = 0 (c >= 0) or v3 = p3 - 1 (c < 0);
+// any other v3 is a range error.
+#include <hip/hip_runtime.h>
+
+#include "host.hpp"
+
+namespace fcirc {
+
+namespace {
+
+constexpr uint32_t Q1 = 998244353u, Q2 = 469762049u, Q3 = 167772161u;
+
+template <class V>
+struct LdRowRev {  // r_k = a_((N - k) mod N), zero beyond na
+  const V* a;
+  uint64_t na, N;
+  __device__ __forceinline__ uint32_t operator()(const Zp& R, uint32_t, uint64_t k) const {
+    const uint64_t j = k == 0 ? 0 : N - k;
+    if (j >= na) return 0u;
+    if constexpr (sizeof(V) == 4) return R.from_i32((int32_t)a[j]);
+    else return (uint32_t)a[j];
+  }
+};
+template <class V>
+struct LdVecPad {  // b_k, zero beyond nb
+  const V* b;
+  uint64_t nb;
+  __device__ __forceinline__ uint32_t operator()(const Zp& R, uint32_t, uint64_t k) const {
+    if (k >= nb) return 0u;
+    if constexpr (sizeof(V) == 4) return R.from_i32((int32_t)b[k]);
+    else return (uint32_t)b[k];
+  }
+};
+
+struct CrtConsts {
+  ZpTw one2, one3;           // reductions mod p2, p3
+  ZpTw inv12, inv13, inv23;  // p1^-1 mod p2, p1^-1 mod p3, p2^-1 mod p3
+};
+
+__device__ __forceinline__ uint32_t shoup_mod(uint32_t v, ZpTw t, uint32_t p) {
+  uint32_t r = v * t.w - __umulhi(v, t.wp) * p;  // [0, 2p)
+  return min(r, r - p);
+}
+
+// Garner: residues (r1, r2, r3) -> digits; returns v3, writes c = v1 + v2 p1.
+__device__ __forceinline__ uint32_t garner(uint32_t r1, uint32_t r2, uint32_t r3, const CrtConsts& K, uint64_t* c) {
+  const uint32_t t2 = shoup_mod(r1, K.one2, Q2);
+  uint32_t d2 = r2 + Q2 - t2;
+  d2 = min(d2, d2 - Q2);
+  const uint32_t v2 = shoup_mod(d2, K.inv12, Q2);
+  const uint32_t t3 = shoup_mod(r1, K.one3, Q3);
+  uint32_t d3 = r3 + Q3 - t3;
+  d3 = min(d3, d3 - Q3);
+  uint32_t e3 = shoup_mod(d3, K.inv13, Q3);
+  const uint32_t w3 = shoup_mod(v2, K.one3, Q3);
+  e3 = e3 + Q3 - w3;
+  e3 = min(e3, e3 - Q3);
+  const uint32_t v3 = shoup_mod(e3, K.inv23, Q3);
+  *c = (uint64_t)r1 + (uint64_t)v2 * Q1;
+  return v3;
+}
+
+// c_k for k < nc from residues res[i * N + k]; signed int64 (polymul).
+__global__ void k_crt_i64(const uint32_t* __restrict__ res, uint64_t N, uint64_t nc, CrtConsts K, int64_t* __restrict__ out,
+                          uint32_t* status) {
+  const uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nc) return;
+  uint64_t c;
+  const uint32_t v3 = garner(res[k], res[N + k], res[2 * N + k], K, &c);
+  int64_t v;
+  if (v3 == 0) {
+    v = (int64_t)c;
+  } else if (v3 == Q3 - 1) {
+    v = (int64_t)c - (int64_t)((uint64_t)Q1 * Q2);
+  } else {
+    v = 0;
+    atomicOr(status, 1u);
+  }
+  out[k] = v;
+}
+
+// Unsigned coefficients (bigint): v3 must be 0.
+__global__ void k_crt_u64(const uint32_t* __restrict__ res, uint64_t N, uint64_t nc, CrtConsts K, uint64_t* __restrict__ out,
+                          uint32_t* status) {
+  const uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nc) return;
+  uint64_t c;
+  const uint32_t v3 = garner(res[k], res[N + k], res[2 * N + k], K, &c);
+  if (v3 != 0) {
+    c = 0;
+    atomicOr(status, 1u);
+  }
+  out[k] = c;
+}
+
+// Carries. The value is sum_k c_k 2^(16k) with c_k < 2^52. With digit_t(c) = 16-bit digit t,
+// s_j = sum_{t<4} digit_t(c_(j-t)) < 2^18 and u_j = (s_j mod 2^16) + floor(s_(j-1) / 2^16)
+// <= 2^16 + 2 keep the same value; then one carry-lookahead pass over u finishes it:
+// limb_j = (u_j + cin_j) mod 2^16 with cin_(j+1) = [u_j >= 2^16] or ([u_j = 2^16 - 1] and cin_j).
+constexpr int CARRY_PER_THREAD = 16;
+constexpr int CARRY_NT = 256;
+constexpr int CARRY_BLOCK = CARRY_PER_THREAD * CARRY_NT;  // limbs per workgroup
+
+__device__ __forceinline__ uint32_t digit(const uint64_t* c, int64_t k, uint64_t nc, int t) {
+  if (k < 0 || (uint64_t)k >= nc) return 0;
+  return (uint32_t)(c[k] >> (16 * t)) & 0xFFFFu;
+}
+__device__ __forceinline__ uint32_t s_at(const uint64_t* c, int64_t j, uint64_t nc) {
+  return digit(c, j, nc, 0) + digit(c, j - 1, nc, 1) + digit(c, j - 2, nc, 2) + digit(c, j - 3, nc, 3);
+}
+
+// (generate, propagate) composition: right = later limb.
+struct GP {
+  uint32_t g, p;
+};
+__device__ __forceinline__ GP gp_combine(GP first, GP later) { return GP{later.g | (later.p & first.g), later.p & first.p}; }
+
+// Pass 1: u_j into `u`, and each workgroup's (G, P) summary.
+__global__ void __launch_bounds__(CARRY_NT) k_carry_scan1(const uint64_t* __restrict__ c, uint64_t nc, uint64_t nl,
+                                                          uint32_t* __restrict__ u, uint32_t* __restrict__ summ) {
+  __shared__ uint32_t sg[CARRY_NT], sp[CARRY_NT];
+  const uint64_t j0 = (uint64_t)blockIdx.x * CARRY_BLOCK + threadIdx.x * CARRY_PER_THREAD;
+  GP acc{0u, 1u};
+  uint32_t sprev = j0 < nl ? s_at(c, (int64_t)j0 - 1, nc) : 0;
+  for (int i = 0; i < CARRY_PER_THREAD; ++i) {
+    const uint64_t j = j0 + i;
+    if (j >= nl) break;
+    const uint32_t s = s_at(c, (int64_t)j, nc);
+    const uint32_t uj = (s & 0xFFFFu) + (sprev >> 16);
+    sprev = s;
+    u[j] = uj;
+    acc = gp_combine(acc, GP{uj >= 0x10000u ? 1u : 0u, uj == 0xFFFFu ? 1u : 0u});
+  }
+  sg[threadIdx.x] = acc.g;
+  sp[threadIdx.x] = acc.p;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    GP b{0u, 1u};
+    for (int t = 0; t < CARRY_NT; ++t) b = gp_combine(b, GP{sg[t], sp[t]});
+    summ[2 * blockIdx.x] = b.g;
+    summ[2 * blockIdx.x + 1] = b.p;
+  }
+}
+
+// Pass 2: carry into each workgroup from all earlier summaries, then limbs.
+__global__ void __launch_bounds__(CARRY_NT) k_carry_scan2(const uint32_t* __restrict__ u, uint64_t nl,
+                                                          const uint32_t* __restrict__ summ, uint16_t* __restrict__ out) {
+  __shared__ uint32_t sg[CARRY_NT], sp[CARRY_NT];
+  __shared__ uint32_t cin_blk;
+  // Carry into this block: ordered reduction of the summaries of blocks [0, blockIdx.x).
+  GP part{0u, 1u};
+  const uint32_t nb = blockIdx.x;
+  const uint32_t per = (nb + CARRY_NT - 1) / CARRY_NT;
+  const uint32_t b0 = threadIdx.x * per;
+  for (uint32_t b = b0; b < b0 + per && b < nb; ++b) part = gp_combine(part, GP{summ[2 * b], summ[2 * b + 1]});
+  sg[threadIdx.x] = part.g;
+  sp[threadIdx.x] = part.p;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    GP b{0u, 1u};
+    for (int t = 0; t < CARRY_NT; ++t) b = gp_combine(b, GP{sg[t], sp[t]});
+    cin_blk = b.g;  // carry out of everything before (initial carry 0)
+  }
+  __syncthreads();
+  // Per-thread segment summaries, then an ordered exclusive scan by one thread.
+  const uint64_t j0 = (uint64_t)blockIdx.x * CARRY_BLOCK + threadIdx.x * CARRY_PER_THREAD;
+  GP acc{0u, 1u};
+  uint32_t uv[CARRY_PER_THREAD];
+  for (int i = 0; i < CARRY_PER_THREAD; ++i) {
+    const uint64_t j = j0 + i;
+    uv[i] = j < nl ? u[j] : 0u;
+    acc = gp_combine(acc, GP{uv[i] >= 0x10000u ? 1u : 0u, uv[i] == 0xFFFFu ? 1u : 0u});
+  }
+  __syncthreads();
+  sg[threadIdx.x] = acc.g;
+  sp[threadIdx.x] = acc.p;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t carry = cin_blk;
+    for (int t = 0; t < CARRY_NT; ++t) {
+      const uint32_t g = sg[t], p = sp[t];
+      sg[t] = carry;  // carry into segment t
+      carry = g | (p & carry);
+    }
+  }
+  __syncthreads();
+  uint32_t carry = sg[threadIdx.x];
+  for (int i = 0; i < CARRY_PER_THREAD; ++i) {
+    const uint64_t j = j0 + i;
+    if (j >= nl) break;
+    const uint32_t v = uv[i] + carry;
+    out[j] = (uint16_t)(v & 0xFFFFu);
+    carry = v >> 16;
+  }
+}
+
+uint32_t pw(uint64_t b, uint64_t e, uint32_t p) {
+  uint64_t r = 1;
+  b %= p;
+  while (e) {
+    if (e & 1) r = r * b % p;
+    b = b * b % p;
+    e >>= 1;
+  }
+  return (uint32_t)r;
+}
+ZpTw stw(uint32_t w, uint32_t p) { return ZpTw{w, (uint32_t)(((uint64_t)w << 32) / p)}; }
+
+CrtConsts crt_consts() {
+  CrtConsts K;
+  K.one2 = stw(1, Q2);
+  K.one3 = stw(1, Q3);
+  K.inv12 = stw(pw(Q1, Q2 - 2, Q2), Q2);
+  K.inv13 = stw(pw(Q1, Q3 - 2, Q3), Q3);
+  K.inv23 = stw(pw(Q2, Q3 - 2, Q3), Q3);
+  return K;
+}
+
+// Three cyclic products (one per prime) of length N = 2^L into res[3N].
+template <class V>
+fcirc_status three_prime_products(Ctx& c, const V* a, uint64_t na, const V* b, uint64_t nb, int L, uint32_t* res,
+                                  uint32_t* ws, hipStream_t s) {
+  const uint32_t ps[3] = {Q1, Q2, Q3};
+  ZpParams rp[3];
+  const ZpTw* tw[3];
+  const ZpTw* twi[3];
+  for (int i = 0; i < 3; ++i) {
+    const ZpTables* T = nullptr;
+    fcirc_status st = zp_tables(c, ps[i], 1u, L, &T);
+    if (st != FCIRC_OK) return st;
+    rp[i] = zp_params(ps[i], L);
+    tw[i] = T->tw;
+    twi[i] = T->twi;
+  }
+  const uint64_t N = (uint64_t)1 << L;
+  const Schedule S = make_schedule(L, 2, effective_top(c, 0, L));
+  return hip_status(run_product<Zp>(c, S, 3, rp, tw, twi, true, LdRowRev<V>{a, na, N}, LdVecPad<V>{b, nb},
+                                    StPlain<uint32_t>{res, N}, res, ws, s));
+}
+
+}  // namespace
+
+fcirc_status polymul_i64(Ctx& c, const int32_t* a, uint64_t na, const int32_t* b, uint64_t nb, int64_t* out, hipStream_t s) {
+  const uint64_t nc = na + nb - 1;
+  const int L = ilog2(nc);
+  const uint64_t N = (uint64_t)1 << L;
+  const Schedule S = make_schedule(L, 2, effective_top(c, 0, L));
+  const uint64_t wse = 3 * N + product_ws_elems(S, 3, false);
+  fcirc_status st = ws_reserve(c, wse * sizeof(uint32_t));
+  if (st != FCIRC_OK) return st;
+  uint32_t* res = (uint32_t*)c.ws;
+  st = three_prime_products<int32_t>(c, a, na, b, nb, L, res, res + 3 * N, s);
+  if (st != FCIRC_OK) return st;
+  const CrtConsts K = crt_consts();
+  const uint32_t grid = (uint32_t)((nc + 255) / 256);
+  return hip_status(launch(c, "fcirc_crt", s, [&] { hipLaunchKernelGGL(k_crt_i64, dim3(grid), dim3(256), 0, s, res, N, nc, K, out, c.d_status); }));
+}
+
+fcirc_status bigint_mul(Ctx& c, const uint16_t* a, uint64_t na, const uint16_t* b, uint64_t nb, uint16_t* out, hipStream_t s) {
+  const uint64_t nc = na + nb - 1, nl = na + nb;
+  const int L = ilog2(nc);
+  const uint64_t N = (uint64_t)1 << L;
+  const Schedule S = make_schedule(L, 2, effective_top(c, 0, L));
+  const uint64_t nblk = (nl + CARRY_BLOCK - 1) / CARRY_BLOCK;
+  // layout (uint32 units): res[3N] | coeffs u64[nc] | u[nl] | summaries[2 nblk] | product workspace
+  const uint64_t off_c = 3 * N, off_u = off_c + 2 * nc, off_s = off_u + nl, off_w = (off_s + 2 * nblk + 63) & ~63ull;
+  const uint64_t wse = off_w + product_ws_elems(S, 3, false);
+  fcirc_status st = ws_reserve(c, wse * sizeof(uint32_t));
+  if (st != FCIRC_OK) return st;
+  uint32_t* base = (uint32_t*)c.ws;
+  uint32_t* res = base;
+  uint64_t* coef = (uint64_t*)(base + off_c);
+  uint32_t* u = base + off_u;
+  uint32_t* summ = base + off_s;
+  st = three_prime_products<uint16_t>(c, a, na, b, nb, L, res, base + off_w, s);
+  if (st != FCIRC_OK) return st;
+  const CrtConsts K = crt_consts();
+  hipError_t e = launch(c, "fcirc_crt", s, [&] {
+    hipLaunchKernelGGL(k_crt_u64, dim3((uint32_t)((nc + 255) / 256)), dim3(256), 0, s, res, N, nc, K, coef, c.d_status);
+  });
+  if (e != hipSuccess) return hip_status(e);
+  e = launch(c, "fcirc_carry", s, [&] { hipLaunchKernelGGL(k_carry_scan1, dim3((uint32_t)nblk), dim3(CARRY_NT), 0, s, coef, nc, nl, u, summ); });
+  if (e != hipSuccess) return hip_status(e);
+  return hip_status(launch(c, "fcirc_carry", s, [&] { hipLaunchKernelGGL(k_carry_scan2, dim3((uint32_t)nblk), dim3(CARRY_NT), 0, s, u, nl, summ, out); }));
+}
+
+}  // namespace fcirc

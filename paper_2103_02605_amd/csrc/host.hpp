@@ -1,0 +1,393 @@
+// Host-side internals of libfcirc: context, twiddle plans, pass schedules, workspace,
+// per-kernel event timing, and the driver that enqueues one f-circulant product (or a
+// batch of equal-size products) as top split passes -> block pass -> top merge passes.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/fcirc.h"
+#include "ring.hpp"
+#include "tile.hpp"
+
+namespace fcirc {
+
+constexpr int LOGE = 4;  // radix of a register stage: 16 elements per thread-item
+
+// ----------------------------------------------------------------------------------------
+// Timing: HIP events around every kernel the library enqueues (opt-in).
+// ----------------------------------------------------------------------------------------
+struct Timer {
+  bool enabled = false;
+  struct Rec {
+    int name;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> pending;
+  std::vector<std::string> names;
+  std::vector<uint64_t> launches;
+  std::vector<double> ms;
+  std::vector<hipEvent_t> pool;
+
+  int name_id(const char* n) {
+    for (size_t i = 0; i < names.size(); ++i)
+      if (names[i] == n) return (int)i;
+    names.emplace_back(n);
+    launches.push_back(0);
+    ms.push_back(0.0);
+    return (int)names.size() - 1;
+  }
+  hipEvent_t get() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+  void collect() {
+    for (auto& r : pending) {
+      float t = 0.f;
+      if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&t, r.a, r.b) == hipSuccess) {
+        launches[r.name] += 1;
+        ms[r.name] += t;
+      }
+      pool.push_back(r.a);
+      pool.push_back(r.b);
+    }
+    pending.clear();
+  }
+  ~Timer() {
+    for (auto& r : pending) {
+      (void)hipEventDestroy(r.a);
+      (void)hipEventDestroy(r.b);
+    }
+    for (auto e : pool) (void)hipEventDestroy(e);
+  }
+};
+
+// ----------------------------------------------------------------------------------------
+// Twiddle tables (heap order, index 2^d + b) for one ring and one f.
+// ----------------------------------------------------------------------------------------
+struct ZpTables {
+  uint32_t p = 0, f = 0;
+  int levels = 0;  // covers depths d < levels
+  ZpTw* tw = nullptr;
+  ZpTw* twi = nullptr;
+};
+
+struct C32Tables {
+  double fre = 1.0, fim = 0.0;
+  int levels = 0;
+  float2* tw = nullptr;
+  float2* twi = nullptr;
+};
+
+// ----------------------------------------------------------------------------------------
+// Pass schedule of one product of size 2^L.
+// ----------------------------------------------------------------------------------------
+struct Schedule {
+  int L = 0;
+  int block_levels = 0;  // levels done in the LDS-resident block pass
+  int ntop = 0;          // HBM-streamed top passes
+  int top_d0[4] = {0, 0, 0, 0};
+  int top_r[4] = {0, 0, 0, 0};
+  int top_c[4] = {0, 0, 0, 0};  // log2 tile columns
+  int block_nt = 256;
+};
+
+struct TuneKey {
+  int ring, L;
+  bool operator<(const TuneKey& o) const { return ring != o.ring ? ring < o.ring : L < o.L; }
+};
+
+struct GraphEntry;  // batched launches captured in HIP graphs (batched.hip)
+
+struct Ctx {
+  int device = 0;
+  hipDeviceProp_t prop{};
+  std::vector<ZpTables> zp;
+  std::vector<C32Tables> c32;
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  size_t ws_limit = SIZE_MAX;
+  uint32_t* d_status = nullptr;
+  int forced_top = -1;
+  std::map<TuneKey, int> tuned_top;
+  Timer timer;
+  std::vector<GraphEntry*> graphs;  // owned; freed by release_graphs
+  bool debug_sync = false;
+};
+
+// Launch wrapper: optional events on the stream, error check, optional debug sync.
+template <class F>
+inline hipError_t launch(Ctx& c, const char* name, hipStream_t s, F&& fn) {
+  hipEvent_t a = nullptr, b = nullptr;
+  if (c.timer.enabled) {
+    a = c.timer.get();
+    b = c.timer.get();
+    if (a) (void)hipEventRecord(a, s);
+  }
+  fn();
+  hipError_t e = hipGetLastError();
+  if (c.timer.enabled && a && b) {
+    (void)hipEventRecord(b, s);
+    c.timer.pending.push_back({c.timer.name_id(name), a, b});
+  }
+  if (e == hipSuccess && c.debug_sync) e = hipStreamSynchronize(s);
+  return e;
+}
+
+// Workspace: grows on demand, never shrinks while the context lives. Callers must have
+// synchronised nothing: growth frees the old buffer only after a device synchronise.
+inline fcirc_status ws_reserve(Ctx& c, size_t bytes) {
+  if (bytes <= c.ws_bytes) return FCIRC_OK;
+  if (bytes > c.ws_limit) return FCIRC_ENOMEM;
+  if (c.ws) {
+    if (hipDeviceSynchronize() != hipSuccess) return FCIRC_EDEVICE;
+    (void)hipFree(c.ws);
+    c.ws = nullptr;
+    c.ws_bytes = 0;
+  }
+  size_t want = bytes + bytes / 4;
+  if (want > c.ws_limit) want = bytes;
+  if (hipMalloc(&c.ws, want) != hipSuccess) {
+    (void)hipGetLastError();
+    return FCIRC_ENOMEM;
+  }
+  c.ws_bytes = want;
+  return FCIRC_OK;
+}
+
+// ----------------------------------------------------------------------------------------
+// Elementwise global access functors used by the tile kernels.
+// ----------------------------------------------------------------------------------------
+template <class T>
+struct LdPlain {
+  const T* p;
+  uint64_t stride;
+  template <class R>
+  __device__ __forceinline__ T operator()(const R&, uint32_t inst, uint64_t i) const {
+    return p[(uint64_t)inst * stride + i];
+  }
+};
+template <class T>
+struct StPlain {
+  T* p;
+  uint64_t stride;
+  __device__ __forceinline__ void operator()(uint32_t inst, uint64_t i, T v) const { p[(uint64_t)inst * stride + i] = v; }
+};
+struct LdR32 {  // real data promoted to complex
+  const float* p;
+  uint64_t stride;
+  template <class R>
+  __device__ __forceinline__ float2 operator()(const R&, uint32_t inst, uint64_t i) const {
+    return make_float2(p[(uint64_t)inst * stride + i], 0.f);
+  }
+};
+struct StR32 {  // real part of a complex result
+  float* p;
+  uint64_t stride;
+  __device__ __forceinline__ void operator()(uint32_t inst, uint64_t i, float2 v) const { p[(uint64_t)inst * stride + i] = v.x; }
+};
+
+// ----------------------------------------------------------------------------------------
+// Schedules.
+// ----------------------------------------------------------------------------------------
+inline int ilog2(uint64_t v) {
+  int l = 0;
+  while ((1ull << l) < v) ++l;
+  return l;
+}
+
+// elem_log: log2 bytes per element (2 for uint32, 3 for complex64).
+// top_levels < 0: default split.
+inline Schedule make_schedule(int L, int elem_log, int top_levels) {
+  Schedule s;
+  s.L = L;
+  const int block_max = elem_log == 2 ? 12 : 11;  // 32 KiB of LDS for row + vector
+  const int tile_log = elem_log == 2 ? 14 : 13;   // 64 KiB tile in a top pass
+  const int top_max = 10;
+  int T = top_levels >= 0 ? top_levels : (L > block_max ? L - block_max : 0);
+  if (T > L) T = L;
+  if (L - T > 13 - (elem_log - 2)) T = L - (13 - (elem_log - 2));  // block must fit LDS
+  s.block_levels = L - T;
+  s.ntop = T == 0 ? 0 : (T + top_max - 1) / top_max;
+  int d0 = 0;
+  for (int i = 0; i < s.ntop; ++i) {
+    const int r = (T - d0) / (s.ntop - i);
+    s.top_d0[i] = d0;
+    s.top_r[i] = r;
+    const int cols_log = L - d0 - r;
+    int c = tile_log - r;
+    if (c > 5) c = 5;
+    if (c > cols_log) c = cols_log;
+    if (c < 0) c = 0;
+    s.top_c[i] = c;
+    d0 += r;
+  }
+  const int bl = s.block_levels;
+  s.block_nt = bl >= 12 ? 256 : (bl >= 11 ? 128 : 64);
+  return s;
+}
+
+// Dynamic LDS above the 64 KiB default needs an explicit opt-in per kernel.
+template <class K>
+inline void allow_lds(K kernel, size_t bytes) {
+  if (bytes > 65536) (void)hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+// ----------------------------------------------------------------------------------------
+// The product driver.
+//   count instances (grid dimension), ring parameters rp[3] / tables tw[3], twi[3]
+//   (instance z uses index z % 3 when ring_per_inst).
+//   srca/srcx read the inputs, dst receives the final (canonical) values.
+//   ws must hold 2 * count * n elements of Ring::T when the schedule has top passes,
+//   plus count * n more when `wy` is null (result kept in workspace before the last
+//   merge pass writes through dst).
+// ----------------------------------------------------------------------------------------
+template <class Ring, class SrcA, class SrcX, class Dst, int NT>
+inline hipError_t launch_block(Ctx& c, const PassArgs<Ring>& A, const typename Ring::Params* rp, SrcA sa, SrcX sx, Dst d,
+                               uint32_t grid, hipStream_t s) {
+  const size_t lds = 2 * ((size_t)1 << A.logr) * sizeof(typename Ring::T);
+  auto k = k_block<Ring, LOGE, NT, SrcA, SrcX, Dst>;
+  allow_lds(k, lds);
+  return launch(c, "fcirc_block", s, [&] { hipLaunchKernelGGL(k, dim3(grid), dim3(NT), lds, s, A, rp[0], rp[1], rp[2], sa, sx, d); });
+}
+
+template <class Ring, class SrcA, class SrcX, class Dst>
+inline hipError_t launch_block_nt(Ctx& c, int nt, const PassArgs<Ring>& A, const typename Ring::Params* rp, SrcA sa,
+                                  SrcX sx, Dst d, uint32_t grid, hipStream_t s) {
+  if (nt == 256) return launch_block<Ring, SrcA, SrcX, Dst, 256>(c, A, rp, sa, sx, d, grid, s);
+  if (nt == 128) return launch_block<Ring, SrcA, SrcX, Dst, 128>(c, A, rp, sa, sx, d, grid, s);
+  return launch_block<Ring, SrcA, SrcX, Dst, 64>(c, A, rp, sa, sx, d, grid, s);
+}
+
+template <class Ring, class SrcA, class SrcX, class Dst>
+inline hipError_t run_product(Ctx& c, const Schedule& S, uint32_t count, const typename Ring::Params* rp,
+                              typename Ring::Tw const* const* tw, typename Ring::Tw const* const* twi,
+                              bool ring_per_inst, SrcA srca, SrcX srcx, Dst dst, typename Ring::T* wy,
+                              typename Ring::T* ws, hipStream_t s) {
+  using T = typename Ring::T;
+  const int L = S.L;
+  const uint64_t n = (uint64_t)1 << L;
+  PassArgs<Ring> A{};
+  for (int i = 0; i < 3; ++i) {
+    A.tw[i] = tw[i];
+    A.twi[i] = twi[i];
+  }
+  A.logn = L;
+  A.ring_per_inst = ring_per_inst ? 1 : 0;
+  hipError_t e;
+  if (S.ntop == 0) {
+    A.d0 = 0;
+    A.logr = L;
+    A.logc = 0;
+    A.tiles = 1;
+    A.narr = 1;
+    A.final_store = 1;
+    return launch_block_nt<Ring>(c, S.block_nt, A, rp, srca, srcx, dst, count, s);
+  }
+  T* wa = ws;
+  T* wx = ws + (uint64_t)count * n;
+  if (!wy) wy = ws + 2 * (uint64_t)count * n;
+  const LdPlain<T> lwa{wa, n}, lwx{wx, n}, lwy{wy, n};
+  const StPlain<T> swa{wa, n}, swx{wx, n}, swy{wy, n};
+  for (int i = 0; i < S.ntop; ++i) {
+    A.d0 = S.top_d0[i];
+    A.logr = S.top_r[i];
+    A.logc = S.top_c[i];
+    A.tiles = (uint32_t)(n >> (A.logr + A.logc));
+    A.narr = 2;
+    A.final_store = 0;
+    const size_t lds = ((size_t)1 << (A.logr + A.logc)) * sizeof(T);
+    const uint32_t grid = A.tiles * 2 * count;
+    if (i == 0) {
+      auto k = k_split<Ring, LOGE, 256, SrcA, SrcX, StPlain<T>>;
+      allow_lds(k, lds);
+      e = launch(c, "fcirc_top_split", s, [&] { hipLaunchKernelGGL(k, dim3(grid), dim3(256), lds, s, A, rp[0], rp[1], rp[2], srca, srcx, swa, swx); });
+    } else {
+      auto k = k_split<Ring, LOGE, 256, LdPlain<T>, LdPlain<T>, StPlain<T>>;
+      allow_lds(k, lds);
+      e = launch(c, "fcirc_top_split", s, [&] { hipLaunchKernelGGL(k, dim3(grid), dim3(256), lds, s, A, rp[0], rp[1], rp[2], lwa, lwx, swa, swx); });
+    }
+    if (e != hipSuccess) return e;
+  }
+  A.d0 = L - S.block_levels;
+  A.logr = S.block_levels;
+  A.logc = 0;
+  A.tiles = 1u << A.d0;
+  A.narr = 1;
+  A.final_store = 0;
+  e = launch_block_nt<Ring>(c, S.block_nt, A, rp, lwa, lwx, swy, A.tiles * count, s);
+  if (e != hipSuccess) return e;
+  for (int i = S.ntop - 1; i >= 0; --i) {
+    A.d0 = S.top_d0[i];
+    A.logr = S.top_r[i];
+    A.logc = S.top_c[i];
+    A.tiles = (uint32_t)(n >> (A.logr + A.logc));
+    A.narr = 1;
+    A.final_store = i == 0 ? 1 : 0;
+    const size_t lds = ((size_t)1 << (A.logr + A.logc)) * sizeof(T);
+    const uint32_t grid = A.tiles * count;
+    if (i == 0) {
+      auto k = k_merge<Ring, LOGE, 256, LdPlain<T>, Dst>;
+      allow_lds(k, lds);
+      e = launch(c, "fcirc_top_merge", s, [&] { hipLaunchKernelGGL(k, dim3(grid), dim3(256), lds, s, A, rp[0], rp[1], rp[2], lwy, dst); });
+    } else {
+      auto k = k_merge<Ring, LOGE, 256, LdPlain<T>, StPlain<T>>;
+      allow_lds(k, lds);
+      e = launch(c, "fcirc_top_merge", s, [&] { hipLaunchKernelGGL(k, dim3(grid), dim3(256), lds, s, A, rp[0], rp[1], rp[2], lwy, swy); });
+    }
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// Workspace elements run_product needs (Ring::T units).
+inline uint64_t product_ws_elems(const Schedule& S, uint32_t count, bool need_wy) {
+  if (S.ntop == 0) return 0;
+  const uint64_t n = (uint64_t)1 << S.L;
+  return (uint64_t)count * n * (need_wy ? 3 : 2);
+}
+
+// ----------------------------------------------------------------------------------------
+// Plans (zp.hip, c32.hip) and helpers shared by the entry points.
+// ----------------------------------------------------------------------------------------
+uint32_t zp_prime(fcirc_ring r);
+int zp_two_adic(uint32_t p);
+// Tables for (p, f) covering at least L levels; ENOROOT if f has no 2^L-th root.
+fcirc_status zp_tables(Ctx& c, uint32_t p, uint32_t f, int L, const ZpTables** out);
+ZpParams zp_params(uint32_t p, int L);
+fcirc_status c32_tables(Ctx& c, double fre, double fim, int L, hipStream_t s, const C32Tables** out);
+
+fcirc_status zp_matvec(Ctx& c, const uint32_t* a, const uint32_t* x, uint32_t* y, int L, uint32_t count, uint32_t p,
+                       uint32_t f, hipStream_t s);
+fcirc_status c32_matvec(Ctx& c, const void* a, const void* x, void* y, int L, uint32_t count, double fre, double fim,
+                        bool real_io, hipStream_t s);
+
+fcirc_status polymul_i64(Ctx& c, const int32_t* a, uint64_t na, const int32_t* b, uint64_t nb, int64_t* out, hipStream_t s);
+fcirc_status bigint_mul(Ctx& c, const uint16_t* a, uint64_t na, const uint16_t* b, uint64_t nb, uint16_t* out, hipStream_t s);
+void release_graphs(Ctx& c);
+
+inline fcirc_status hip_status(hipError_t e) {
+  if (e == hipSuccess) return FCIRC_OK;
+  (void)hipGetLastError();
+  return e == hipErrorOutOfMemory ? FCIRC_ENOMEM : FCIRC_EDEVICE;
+}
+
+inline int effective_top(Ctx& c, int ring, int L) {
+  if (c.forced_top >= 0) return c.forced_top;
+  auto it = c.tuned_top.find(TuneKey{ring, L});
+  return it == c.tuned_top.end() ? -1 : it->second;
+}
+
+}  // namespace fcirc

@@ -1,0 +1,23 @@
+// Entry points still to be written: they validate nothing yet and report EINVAL.
+#include <hip/hip_runtime.h>
+
+#include "host.hpp"
+
+namespace fcirc {
+void release_graphs(Ctx&) {}
+}  // namespace fcirc
+
+extern "C" {
+fcirc_status fcirc_matvec_batched(fcirc_ctx*, const void*, const void*, void*, const fcirc_item*, uint32_t, const void*,
+                                  fcirc_ring, void*) {
+  return FCIRC_EINVAL;
+}
+fcirc_status fcirc_matvec_fwd_shared(fcirc_ctx*, const void*, const void*, void*, uint64_t, uint32_t, fcirc_ring, void*) {
+  return FCIRC_EINVAL;
+}
+fcirc_status fcirc_matvec_backward(fcirc_ctx*, const void*, const void*, const void*, void*, void*, uint64_t, uint32_t,
+                                   fcirc_ring, void*) {
+  return FCIRC_EINVAL;
+}
+fcirc_status fcirc_tune(fcirc_ctx*, uint64_t, fcirc_ring, void*) { return FCIRC_EINVAL; }
+}

@@ -1,0 +1,139 @@
+// Ring arithmetic for the f-circulant product kernels (gfx950).
+//
+// Algorithm 1 (section 2 of Rosowski, arXiv 2103.02605) needs +, -, x, 1/2 and the
+// square roots of f in a ring R (Theorem 1). Three butterflies come out of it, one per
+// direction of the recursion, for a pair (u, v) = (low half, high half) of a block whose
+// node value has square root g:
+//   row split    (A1 + A2 g, A1 - A2 g) on first rows:   (u, v) -> (u + g v, u - g v)
+//   vector split (b1 g + b2, b1 g - b2):                 (u, v) -> (g u + v, g u - v)
+//   merge        c1 = (M1 + M2)/(2g), c2 = (M1 - M2)/2:  (u, v) -> ((u + v) / g, u - v)
+// The merge drops the factor 1/2 at every level; the leaves multiply by 1/n instead,
+// which gives the same result (the recursion is linear in the leaf values).
+//
+// Z/p: values live in 32-bit lanes with lazy reduction (Harvey): split outputs in
+// [0, 4p), merge values in [0, 2p), canonical [0, p) only at the final store. All three
+// primes are below 2^30, so 4p < 2^32. Multiplication by a twiddle w uses Shoup's method
+// with the precomputed companion w' = floor(w 2^32 / p): q = hi32(v w'), r = v w - q p
+// lies in [0, 2p) for any 32-bit v. The leaf product of two variables uses a signed
+// Montgomery reduction. On gfx950 the 32-bit v_mul_hi_u32 / v_mad_u64_u32 issue at
+// full rate, which makes this cheaper than an FP64-FMA formulation.
+//
+// Complex FP32: float2 lanes, twiddles are FP32 roundings of FP64-computed roots.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fcirc {
+
+struct ZpTw {
+  uint32_t w, wp;  // w in [0, p) and floor(w * 2^32 / p)
+};
+
+struct ZpParams {
+  uint32_t p;
+  uint32_t pinv;   // p^-1 mod 2^32
+  ZpTw leaf;       // 2^32 / n mod p: undoes the Montgomery factor and applies 1/n
+  ZpTw one;        // {1, floor(2^32 / p)}: reduces any 32-bit value to [0, 2p)
+  uint32_t two31;  // 2^31 mod p
+};
+
+struct Zp {
+  using T = uint32_t;
+  using Tw = ZpTw;
+  using Params = ZpParams;
+  uint32_t p, p2, pinv;
+  ZpTw leafs, one;
+  uint32_t two31;
+
+  __device__ __forceinline__ explicit Zp(const ZpParams& q)
+      : p(q.p), p2(2u * q.p), pinv(q.pinv), leafs(q.leaf), one(q.one), two31(q.two31) {}
+
+  __device__ __forceinline__ uint32_t shoup(uint32_t v, ZpTw t) const {
+    const uint32_t q = __umulhi(v, t.wp);
+    return v * t.w - q * p;  // in [0, 2p)
+  }
+  __device__ __forceinline__ uint32_t red2(uint32_t u) const { return min(u, u - p2); }  // [0,4p) -> [0,2p)
+
+  __device__ __forceinline__ void split_a(T& u, T& v, Tw g) const {
+    const uint32_t uu = red2(u);
+    const uint32_t t = shoup(v, g);
+    u = uu + t;
+    v = uu - t + p2;
+  }
+  __device__ __forceinline__ void split_x(T& u, T& v, Tw g) const {
+    const uint32_t t = shoup(u, g);
+    const uint32_t vv = red2(v);
+    u = t + vv;
+    v = t - vv + p2;
+  }
+  __device__ __forceinline__ void merge(T& u, T& v, Tw gi) const {
+    const uint32_t s = u + v;       // [0, 4p)
+    const uint32_t d = u - v + p2;  // (0, 4p)
+    u = shoup(s, gi);
+    v = red2(d);
+  }
+  // a x / n for a, x in [0, 4p); result in [0, 2p)
+  __device__ __forceinline__ T leaf(T a, T x) const {
+    a = red2(a);
+    x = red2(x);
+    const uint32_t lo = a * x, hi = __umulhi(a, x);  // a x < 4p^2 < p 2^32, so hi < p
+    const uint32_t m = lo * pinv;
+    const uint32_t r = hi - __umulhi(m, p) + p;  // (a x - m p) / 2^32 + p in (0, 2p)
+    return shoup(r, leafs);
+  }
+  // [0, 4p) -> [0, p)
+  __device__ __forceinline__ uint32_t canon(T v) const {
+    v = red2(v);
+    return min(v, v - p);
+  }
+  // any signed 32-bit integer -> its residue in [0, p)
+  __device__ __forceinline__ uint32_t from_i32(int32_t v) const {
+    const uint32_t u = (uint32_t)v ^ 0x80000000u;  // v + 2^31, in [0, 2^32)
+    uint32_t r = shoup(u, one);                      // [0, 2p)
+    r = min(r, r - p);                               // [0, p)
+    r = r + p - two31;                               // [1, 2p)
+    return min(r, r - p);
+  }
+};
+
+struct C32Params {
+  float scale;  // 1/n
+};
+
+struct C32 {
+  using T = float2;
+  using Tw = float2;
+  using Params = C32Params;
+  float scale;
+
+  __device__ __forceinline__ explicit C32(const C32Params& q) : scale(q.scale) {}
+
+  static __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+    return make_float2(fmaf(a.x, b.x, -a.y * b.y), fmaf(a.x, b.y, a.y * b.x));
+  }
+  __device__ __forceinline__ void split_a(T& u, T& v, Tw g) const {
+    const float2 t = cmul(g, v);
+    const float2 uu = u;
+    u = make_float2(uu.x + t.x, uu.y + t.y);
+    v = make_float2(uu.x - t.x, uu.y - t.y);
+  }
+  __device__ __forceinline__ void split_x(T& u, T& v, Tw g) const {
+    const float2 t = cmul(g, u);
+    const float2 vv = v;
+    u = make_float2(t.x + vv.x, t.y + vv.y);
+    v = make_float2(t.x - vv.x, t.y - vv.y);
+  }
+  __device__ __forceinline__ void merge(T& u, T& v, Tw gi) const {
+    const float2 s = make_float2(u.x + v.x, u.y + v.y);
+    const float2 d = make_float2(u.x - v.x, u.y - v.y);
+    u = cmul(s, gi);
+    v = d;
+  }
+  __device__ __forceinline__ T leaf(T a, T x) const {
+    const float2 t = cmul(a, x);
+    return make_float2(t.x * scale, t.y * scale);
+  }
+  __device__ __forceinline__ T canon(T v) const { return v; }
+};
+
+}  // namespace fcirc

@@ -1,0 +1,174 @@
+"""Python API of libfcirc over torch tensors (argument marshalling only).
+
+Every computation runs in the HIP library; torch provides device memory and the stream
+(the current torch stream of the tensors' device is passed to each call).
+
+Conventions (Rosowski, arXiv 2103.02605):
+* The f-circulant matrix A(a, f) is identified by its FIRST ROW a (section 1.2):
+  A[i][j] = a[j-i] for j >= i and f * a[n+j-i] for j < i (Definition 2).
+* ``matvec(a, x, f)`` returns y = A(a, f) x (Theorem 1, Algorithm 1).
+* Z/p: pass ``p`` (998244353, 469762049 or 167772161) and int32/uint32 tensors with
+  values in [0, p); complex64 tensors use the complex ring; float32 tensors the real one.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import torch
+
+from . import _lib as L
+
+P1, P2, P3 = 998244353, 469762049, 167772161
+RING_OF_PRIME = {P1: L.FCIRC_ZP_998244353, P2: L.FCIRC_ZP_469762049, P3: L.FCIRC_ZP_167772161}
+
+
+class Context:
+    """A libfcirc context on one HIP device (plans, workspaces, graphs)."""
+
+    def __init__(self, device: int = 0):
+        self.device = device
+        h = C.c_void_p()
+        L.check(L.lib().fcirc_create(C.byref(h), device), "fcirc_create")
+        self.handle = h
+
+    def close(self):
+        if self.handle:
+            L.lib().fcirc_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_contexts: dict[int, Context] = {}
+
+
+def context(device=None) -> Context:
+    idx = torch.cuda.current_device() if device is None else torch.device(device).index or 0
+    if idx not in _contexts:
+        _contexts[idx] = Context(idx)
+    return _contexts[idx]
+
+
+def _ptr(t: torch.Tensor) -> C.c_void_p:
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(t: torch.Tensor) -> C.c_void_p:
+    return C.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+def _need(t: torch.Tensor, name: str):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a GPU tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def _ring_and_f(t: torch.Tensor, f, p):
+    """(ring id, ctypes value of f) for a data tensor t."""
+    if p is not None:
+        if p not in RING_OF_PRIME:
+            raise ValueError(f"unsupported prime {p}")
+        if t.dtype not in (torch.int32, torch.uint32):
+            raise TypeError("Z/p data must be int32 or uint32 tensors holding values in [0, p)")
+        fv = int(f) % p if f is not None else 1
+        return RING_OF_PRIME[p], C.c_uint32(fv)
+    if t.dtype == torch.complex64:
+        fc = complex(1.0 if f is None else f)
+        return L.FCIRC_C64, (C.c_double * 2)(fc.real, fc.imag)
+    if t.dtype == torch.float32:
+        return L.FCIRC_R32, C.c_double(1.0 if f is None else float(f))
+    raise TypeError(f"unsupported dtype {t.dtype}")
+
+
+def matvec(a: torch.Tensor, x: torch.Tensor, f=None, p: int | None = None, out: torch.Tensor | None = None):
+    """y = A(a, f) x for one product of power-of-two size n (Definition 2, Algorithm 1)."""
+    _need(a, "a")
+    _need(x, "x")
+    if a.shape != x.shape or a.dim() != 1 or a.dtype != x.dtype:
+        raise ValueError("a and x must be 1-D tensors of the same shape and dtype")
+    ring, fv = _ring_and_f(a, f, p)
+    y = torch.empty_like(a) if out is None else out
+    _need(y, "out")
+    ctx = context(a.device)
+    L.check(L.lib().fcirc_matvec(ctx.handle, _ptr(a), _ptr(x), _ptr(y), a.numel(), C.byref(fv), ring, _stream(a)),
+            "fcirc_matvec")
+    return y
+
+
+def matvec_many(a: torch.Tensor, x: torch.Tensor, f=None, p: int | None = None, out: torch.Tensor | None = None):
+    """Row k of the result is A(a[k], f) x[k]; a and x have shape (count, n)."""
+    _need(a, "a")
+    _need(x, "x")
+    if a.shape != x.shape or a.dim() != 2 or a.dtype != x.dtype:
+        raise ValueError("a and x must be 2-D tensors (count, n) of the same shape and dtype")
+    ring, fv = _ring_and_f(a, f, p)
+    y = torch.empty_like(a) if out is None else out
+    ctx = context(a.device)
+    L.check(L.lib().fcirc_matvec_many(ctx.handle, _ptr(a), _ptr(x), _ptr(y), a.shape[1], a.shape[0], C.byref(fv),
+                                      ring, _stream(a)), "fcirc_matvec_many")
+    return y
+
+
+def polymul_i64(a: torch.Tensor, b: torch.Tensor, out: torch.Tensor | None = None):
+    """Exact int64 coefficients of the product of two int32 polynomials (section 3.1)."""
+    _need(a, "a")
+    _need(b, "b")
+    if a.dtype != torch.int32 or b.dtype != torch.int32:
+        raise TypeError("polymul_i64 takes int32 coefficient tensors")
+    c = torch.empty(a.numel() + b.numel() - 1, dtype=torch.int64, device=a.device) if out is None else out
+    ctx = context(a.device)
+    L.check(L.lib().fcirc_polymul_i64(ctx.handle, _ptr(a), a.numel(), _ptr(b), b.numel(), _ptr(c), _stream(a)),
+            "fcirc_polymul_i64")
+    return c
+
+
+def bigint_mul(a: torch.Tensor, b: torch.Tensor, out: torch.Tensor | None = None):
+    """Limbs (little-endian, 16-bit) of the product of two non-negative integers."""
+    _need(a, "a")
+    _need(b, "b")
+    if a.dtype not in (torch.uint16, torch.int16) or b.dtype != a.dtype:
+        raise TypeError("bigint_mul takes uint16 (or int16-viewed) limb tensors")
+    c = torch.empty(a.numel() + b.numel(), dtype=a.dtype, device=a.device) if out is None else out
+    ctx = context(a.device)
+    L.check(L.lib().fcirc_bigint_mul(ctx.handle, _ptr(a), a.numel(), _ptr(b), b.numel(), _ptr(c), _stream(a)),
+            "fcirc_bigint_mul")
+    return c
+
+
+def check(device=None):
+    """Synchronise the current stream and raise on a sticky device-side error (ERANGE)."""
+    ctx = context(device)
+    L.check(L.lib().fcirc_check(ctx.handle, C.c_void_p(torch.cuda.current_stream().cuda_stream)), "fcirc_check")
+
+
+def set_timing(enable: bool, device=None):
+    L.check(L.lib().fcirc_set_timing(context(device).handle, int(bool(enable))), "fcirc_set_timing")
+
+
+def stage_times(device=None) -> dict:
+    """{kernel name: (launches, total ms)} since the last set_timing()."""
+    ctx = context(device)
+    n = L.lib().fcirc_stage_times(ctx.handle, None, None, None, 0)
+    names = (C.c_char_p * max(n, 1))()
+    launches = (C.c_uint64 * max(n, 1))()
+    ms = (C.c_double * max(n, 1))()
+    n = L.lib().fcirc_stage_times(ctx.handle, names, launches, ms, n)
+    return {names[i].decode(): (int(launches[i]), float(ms[i])) for i in range(n)}
+
+
+def set_split(top_levels: int, device=None):
+    L.check(L.lib().fcirc_set_split(context(device).handle, int(top_levels)), "fcirc_set_split")
+
+
+def get_split(n: int, ring: int, device=None) -> int:
+    return int(L.lib().fcirc_get_split(context(device).handle, n, ring))
+
+
+def tune(n: int, ring: int, device=None):
+    L.check(L.lib().fcirc_tune(context(device).handle, n, ring, C.c_void_p(torch.cuda.current_stream().cuda_stream)),
+            "fcirc_tune")

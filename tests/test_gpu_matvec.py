@@ -1,0 +1,196 @@
+"""GPU parity of the f-circulant product against the CPU oracle.
+
+Z/p results must be bit-exact. Complex/real FP32 results must be within relative L2
+error 1e-5 of the FP64 oracle evaluated on the same (FP32) inputs.
+"""
+import random
+
+import numpy as np
+import pytest
+
+from oracle import fcirc as O
+from paper_2103_02605_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+P1, P2, P3 = W.P1, W.P2, W.P3
+PRIMES = (P1, P2, P3)
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def F():
+    import torch
+    from paper_2103_02605_amd import fcirc
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    fcirc.set_split(-1)
+    yield fcirc
+    fcirc.set_split(-1)
+
+
+def dev(arr):
+    import torch
+    a = np.ascontiguousarray(arr)
+    if a.dtype == np.uint32:
+        a = a.view(np.int32)
+    return torch.from_numpy(a).cuda()
+
+
+def host_u32(t):
+    return t.cpu().numpy().view(np.uint32).astype(np.int64)
+
+
+def rand_f(n, p, seed):
+    return pow(random.Random(seed).randrange(1, p), n, p)
+
+
+def oracle_modp(a, x, f, p):
+    n = len(a)
+    if n <= 2048:
+        return O.dense_matvec_modp(a, x, f, p)
+    return O.levels_matvec_modp(a, x, f, p)
+
+
+# C1: n = 1024 over Z/998244353, f = 1 (cyclic) and f = p - 1 (negacyclic), bit-exact -------
+
+@pytest.mark.parametrize("f,seed", [(1, W.SEED_C1_CYCLIC), (P1 - 1, W.SEED_C1_NEGACYCLIC)])
+def test_c1_n1024_bit_exact(F, f, seed):
+    a, x = W.modp_pair(1024, P1, seed)
+    y = F.matvec(dev(a), dev(x), f=f, p=P1)
+    np.testing.assert_array_equal(host_u32(y), O.dense_matvec_modp(a, x, f, P1))
+
+
+@pytest.mark.parametrize("p", PRIMES)
+@pytest.mark.parametrize("L", list(range(0, 15)))
+def test_all_sizes_bit_exact(F, p, L):
+    n = 1 << L
+    a, x = W.modp_pair(n, p, seed=100 + L)
+    for f in (1, p - 1, rand_f(n, p, L)):
+        if f == p - 1 and L >= 23:
+            continue
+        y = F.matvec(dev(a), dev(x), f=f, p=p)
+        np.testing.assert_array_equal(host_u32(y), oracle_modp(a, x, f, p), err_msg=f"p={p} n={n} f={f}")
+
+
+@pytest.mark.parametrize("L,top", [(8, 2), (8, 7), (13, 1), (13, 9), (15, 3), (16, 12), (17, 14), (18, 5)])
+def test_forced_splits_bit_exact(F, L, top):
+    """Every split point of the recursion between HBM passes and the LDS block gives the
+    same bits (covers one and two top passes, narrow and wide tiles)."""
+    n = 1 << L
+    a, x = W.modp_pair(n, P1, seed=7 + L)
+    want = oracle_modp(a, x, 1, P1)
+    F.set_split(top)
+    try:
+        y = F.matvec(dev(a), dev(x), f=1, p=P1)
+    finally:
+        F.set_split(-1)
+    np.testing.assert_array_equal(host_u32(y), want)
+
+
+def test_many_instances(F):
+    import torch
+    for L, count in [(0, 3), (5, 7), (10, 4), (14, 3)]:
+        n = 1 << L
+        a, x = W.modp_batch(count, n, P2, seed=L)
+        y = F.matvec_many(dev(a), dev(x), f=P2 - 1, p=P2)
+        got = host_u32(y)
+        for k in range(count):
+            np.testing.assert_array_equal(got[k], oracle_modp(a[k], x[k], P2 - 1, P2))
+
+
+@pytest.mark.parametrize("p,L", [(P1, 21), (P1, 23), (P3, 25), (P2, 26)])
+def test_large_sampled(F, p, L):
+    """Full sizes up to each prime's limit: sampled outputs from the O(n) definition."""
+    n = 1 << L
+    a, x = W.modp_pair(n, p, seed=W.SEED_HEADLINE)
+    y = host_u32(F.matvec(dev(a), dev(x), f=1, p=p))
+    rng = np.random.default_rng(L)
+    for i in list(rng.integers(0, n, 12)) + [0, n - 1]:
+        assert y[i] == O.matvec_entry_modp(a, x, 1, p, int(i)), f"y[{i}]"
+    assert y.max() < p
+
+
+def test_headline_levels_oracle_full(F):
+    """The n = 2^21 headline product against the level-by-level oracle, every element."""
+    n = 1 << 21
+    a, x = W.modp_pair(n, P1, seed=W.SEED_HEADLINE)
+    y = host_u32(F.matvec(dev(a), dev(x), f=1, p=P1))
+    np.testing.assert_array_equal(y, O.levels_matvec_modp(a, x, 1, P1))
+
+
+def test_deterministic(F):
+    n = 1 << 18
+    a, x = W.modp_pair(n, P1, seed=9)
+    y1 = host_u32(F.matvec(dev(a), dev(x), f=1, p=P1))
+    y2 = host_u32(F.matvec(dev(a), dev(x), f=1, p=P1))
+    np.testing.assert_array_equal(y1, y2)
+
+
+# Complex FP32 ---------------------------------------------------------------------------
+
+def rel_l2(got, want):
+    return np.linalg.norm(got - want) / np.linalg.norm(want)
+
+
+@pytest.mark.parametrize("L", list(range(0, 17)))
+def test_complex_sizes(F, L):
+    n = 1 << L
+    a, x = W.complex_pair(n, seed=L)
+    want = O.matvec_c128(a.astype(np.complex128), x.astype(np.complex128), 1.0)
+    got = F.matvec(dev(a), dev(x)).cpu().numpy()
+    assert rel_l2(got, want) <= TOL
+
+
+@pytest.mark.parametrize("f", [-1.0, 1j, np.exp(0.3j), np.exp(-2.0j)])
+def test_complex_unit_f(F, f):
+    for L in (1, 6, 12, 15):
+        n = 1 << L
+        a, x = W.complex_pair(n, seed=L + 50)
+        want = O.levels_matvec_c128(a.astype(np.complex128), x.astype(np.complex128), f)
+        got = F.matvec(dev(a), dev(x), f=f).cpu().numpy()
+        assert rel_l2(got, want) <= TOL, (L, f)
+
+
+@pytest.mark.parametrize("L", [0, 1, 5, 11, 12, 14, 16])
+def test_real_ring(F, L):
+    n = 1 << L
+    rng = np.random.default_rng(L)
+    a = rng.standard_normal(n).astype(np.float32)
+    x = rng.standard_normal(n).astype(np.float32)
+    want = O.matvec_c128(a.astype(np.complex128), x.astype(np.complex128), 1.0).real
+    got = F.matvec(dev(a), dev(x)).cpu().numpy()
+    assert rel_l2(got, want) <= TOL
+
+
+@pytest.mark.parametrize("L,top", [(12, 3), (14, 10), (16, 13)])
+def test_complex_forced_splits(F, L, top):
+    n = 1 << L
+    a, x = W.complex_pair(n, seed=3)
+    want = O.levels_matvec_c128(a.astype(np.complex128), x.astype(np.complex128), 1.0)
+    F.set_split(top)
+    try:
+        got = F.matvec(dev(a), dev(x)).cpu().numpy()
+    finally:
+        F.set_split(-1)
+    assert rel_l2(got, want) <= TOL
+
+
+# Errors raised before anything is enqueued ------------------------------------------------
+
+def test_errors(F):
+    import torch
+    from paper_2103_02605_amd._lib import FcircError
+    a = dev(np.zeros(12, np.uint32))
+    with pytest.raises(FcircError, match="ESIZE"):
+        F.matvec(a, a.clone(), f=1, p=P1)
+    a = dev(np.zeros(1 << 24, np.uint32))
+    with pytest.raises(FcircError, match="ESIZE"):
+        F.matvec(a, a.clone(), f=1, p=P1)
+    a = dev(np.zeros(8, np.uint32))
+    with pytest.raises(FcircError, match="ENOROOT"):
+        F.matvec(a, a.clone(), f=0, p=P1)
+    # 3 is a generator, so it has no square root, hence no 8-th root
+    with pytest.raises(FcircError, match="ENOROOT"):
+        F.matvec(a, a.clone(), f=3, p=P1)
+    with pytest.raises(FcircError, match="EINVAL"):
+        F.matvec(a, a, f=1, p=P1, out=a)  # output aliases the input
