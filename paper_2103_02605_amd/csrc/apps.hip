@@ -26,7 +26,7 @@ template <class V>
 struct LdRowRev {  // r_k = a_((N - k) mod N), zero beyond na
   const V* a;
   uint64_t na, N;
-  __device__ __forceinline__ uint32_t operator()(const Zp& R, uint32_t, uint64_t k) const {
+  __device__ __forceinline__ uint32_t operator()(const Zp& R, uint32_t, uint32_t k) const {
     const uint64_t j = k == 0 ? 0 : N - k;
     if (j >= na) return 0u;
     if constexpr (sizeof(V) == 4) return R.from_i32((int32_t)a[j]);
@@ -37,7 +37,7 @@ template <class V>
 struct LdVecPad {  // b_k, zero beyond nb
   const V* b;
   uint64_t nb;
-  __device__ __forceinline__ uint32_t operator()(const Zp& R, uint32_t, uint64_t k) const {
+  __device__ __forceinline__ uint32_t operator()(const Zp& R, uint32_t, uint32_t k) const {
     if (k >= nb) return 0u;
     if constexpr (sizeof(V) == 4) return R.from_i32((int32_t)b[k]);
     else return (uint32_t)b[k];

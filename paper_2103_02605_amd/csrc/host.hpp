@@ -18,8 +18,6 @@
 
 namespace fcirc {
 
-constexpr int LOGE = 4;  // radix of a register stage: 16 elements per thread-item
-
 // ----------------------------------------------------------------------------------------
 // Timing: HIP events around every kernel the library enqueues (opt-in).
 // ----------------------------------------------------------------------------------------
@@ -101,7 +99,6 @@ struct Schedule {
   int top_d0[4] = {0, 0, 0, 0};
   int top_r[4] = {0, 0, 0, 0};
   int top_c[4] = {0, 0, 0, 0};  // log2 tile columns
-  int block_nt = 256;
 };
 
 struct TuneKey {
@@ -170,33 +167,35 @@ inline fcirc_status ws_reserve(Ctx& c, size_t bytes) {
 // ----------------------------------------------------------------------------------------
 // Elementwise global access functors used by the tile kernels.
 // ----------------------------------------------------------------------------------------
+// Element i (32-bit, within one instance) of instance `inst` (wave-uniform), so the address
+// is a uniform 64-bit base plus a 32-bit per-lane offset.
 template <class T>
 struct LdPlain {
   const T* p;
   uint64_t stride;
   template <class R>
-  __device__ __forceinline__ T operator()(const R&, uint32_t inst, uint64_t i) const {
-    return p[(uint64_t)inst * stride + i];
+  __device__ __forceinline__ T operator()(const R&, uint32_t inst, uint32_t i) const {
+    return (p + (uint64_t)inst * stride)[i];
   }
 };
 template <class T>
 struct StPlain {
   T* p;
   uint64_t stride;
-  __device__ __forceinline__ void operator()(uint32_t inst, uint64_t i, T v) const { p[(uint64_t)inst * stride + i] = v; }
+  __device__ __forceinline__ void operator()(uint32_t inst, uint32_t i, T v) const { (p + (uint64_t)inst * stride)[i] = v; }
 };
 struct LdR32 {  // real data promoted to complex
   const float* p;
   uint64_t stride;
   template <class R>
-  __device__ __forceinline__ float2 operator()(const R&, uint32_t inst, uint64_t i) const {
-    return make_float2(p[(uint64_t)inst * stride + i], 0.f);
+  __device__ __forceinline__ float2 operator()(const R&, uint32_t inst, uint32_t i) const {
+    return make_float2((p + (uint64_t)inst * stride)[i], 0.f);
   }
 };
 struct StR32 {  // real part of a complex result
   float* p;
   uint64_t stride;
-  __device__ __forceinline__ void operator()(uint32_t inst, uint64_t i, float2 v) const { p[(uint64_t)inst * stride + i] = v.x; }
+  __device__ __forceinline__ void operator()(uint32_t inst, uint32_t i, float2 v) const { (p + (uint64_t)inst * stride)[i] = v.x; }
 };
 
 // ----------------------------------------------------------------------------------------
@@ -214,10 +213,11 @@ inline Schedule make_schedule(int L, int elem_log, int top_levels) {
   Schedule s;
   s.L = L;
   const int block_max = elem_log == 2 ? 12 : 11;  // 32 KiB of LDS for row + vector
-  const int tile_log = elem_log == 2 ? 14 : 13;   // 64 KiB tile in a top pass
+  const int tile_log = elem_log == 2 ? 13 : 12;   // 32 KiB tile in a top pass
   const int top_max = 10;
   int T = top_levels >= 0 ? top_levels : (L > block_max ? L - block_max : 0);
   if (T > L) T = L;
+  if (L < 5) T = 0;                                // too small for a column tile of 16 elements
   if (L - T > 13 - (elem_log - 2)) T = L - (13 - (elem_log - 2));  // block must fit LDS
   s.block_levels = L - T;
   s.ntop = T == 0 ? 0 : (T + top_max - 1) / top_max;
@@ -228,14 +228,11 @@ inline Schedule make_schedule(int L, int elem_log, int top_levels) {
     s.top_r[i] = r;
     const int cols_log = L - d0 - r;
     int c = tile_log - r;
-    if (c > 5) c = 5;
     if (c > cols_log) c = cols_log;
     if (c < 0) c = 0;
     s.top_c[i] = c;
     d0 += r;
   }
-  const int bl = s.block_levels;
-  s.block_nt = bl >= 12 ? 256 : (bl >= 11 ? 128 : 64);
   return s;
 }
 
@@ -247,28 +244,84 @@ inline void allow_lds(K kernel, size_t bytes) {
 
 // ----------------------------------------------------------------------------------------
 // The product driver.
-//   count instances (grid dimension), ring parameters rp[3] / tables tw[3], twi[3]
-//   (instance z uses index z % 3 when ring_per_inst).
-//   srca/srcx read the inputs, dst receives the final (canonical) values.
-//   ws must hold 2 * count * n elements of Ring::T when the schedule has top passes,
-//   plus count * n more when `wy` is null (result kept in workspace before the last
-//   merge pass writes through dst).
+//   count instances, ring parameters rp[3] / tables tw[3], twi[3] (instance z uses index
+//   z % 3 when ring_per_inst). srca/srcx read the inputs, dst receives the final
+//   (canonical) values. ws must hold 2 * count * n elements of Ring::T when the schedule
+//   has top passes, plus count * n more when `wy` is null (the result then stays in
+//   workspace until the last merge pass writes it through dst).
 // ----------------------------------------------------------------------------------------
-template <class Ring, class SrcA, class SrcX, class Dst, int NT>
-inline hipError_t launch_block(Ctx& c, const PassArgs<Ring>& A, const typename Ring::Params* rp, SrcA sa, SrcX sx, Dst d,
-                               uint32_t grid, hipStream_t s) {
-  const size_t lds = 2 * ((size_t)1 << A.logr) * sizeof(typename Ring::T);
-  auto k = k_block<Ring, LOGE, NT, SrcA, SrcX, Dst>;
+template <class Ring, int LOGR, class SrcA, class SrcX, class Dst>
+inline hipError_t launch_block_l(Ctx& c, const PassArgs<Ring>& A, const typename Ring::Params* rp, SrcA sa, SrcX sx, Dst d,
+                                 hipStream_t s) {
+  using S = BlockShape<LOGR>;
+  const uint64_t vwgs = (uint64_t)A.tiles * A.ninst;
+  const uint32_t grid = (uint32_t)((vwgs + S::GROUPS - 1) / S::GROUPS);
+  const size_t lds = (size_t)S::GROUPS * 2 * ((size_t)1 << LOGR) * sizeof(typename Ring::T);
+  auto k = k_block<Ring, LOGR, SrcA, SrcX, Dst>;
   allow_lds(k, lds);
-  return launch(c, "fcirc_block", s, [&] { hipLaunchKernelGGL(k, dim3(grid), dim3(NT), lds, s, A, rp[0], rp[1], rp[2], sa, sx, d); });
+  return launch(c, "fcirc_block", s, [&] { hipLaunchKernelGGL(k, dim3(grid), dim3(S::NT), lds, s, A, rp[0], rp[1], rp[2], sa, sx, d); });
 }
 
 template <class Ring, class SrcA, class SrcX, class Dst>
-inline hipError_t launch_block_nt(Ctx& c, int nt, const PassArgs<Ring>& A, const typename Ring::Params* rp, SrcA sa,
-                                  SrcX sx, Dst d, uint32_t grid, hipStream_t s) {
-  if (nt == 256) return launch_block<Ring, SrcA, SrcX, Dst, 256>(c, A, rp, sa, sx, d, grid, s);
-  if (nt == 128) return launch_block<Ring, SrcA, SrcX, Dst, 128>(c, A, rp, sa, sx, d, grid, s);
-  return launch_block<Ring, SrcA, SrcX, Dst, 64>(c, A, rp, sa, sx, d, grid, s);
+inline hipError_t launch_block(Ctx& c, const PassArgs<Ring>& A, const typename Ring::Params* rp, SrcA sa, SrcX sx, Dst d,
+                               hipStream_t s) {
+  switch (A.logr) {
+#define FCIRC_BLOCK_CASE(l) \
+  case l: return launch_block_l<Ring, l>(c, A, rp, sa, sx, d, s);
+    FCIRC_BLOCK_CASE(0) FCIRC_BLOCK_CASE(1) FCIRC_BLOCK_CASE(2) FCIRC_BLOCK_CASE(3) FCIRC_BLOCK_CASE(4)
+    FCIRC_BLOCK_CASE(5) FCIRC_BLOCK_CASE(6) FCIRC_BLOCK_CASE(7) FCIRC_BLOCK_CASE(8) FCIRC_BLOCK_CASE(9)
+    FCIRC_BLOCK_CASE(10) FCIRC_BLOCK_CASE(11) FCIRC_BLOCK_CASE(12)
+#undef FCIRC_BLOCK_CASE
+    case 13:
+      if constexpr (sizeof(typename Ring::T) == 4) return launch_block_l<Ring, 13>(c, A, rp, sa, sx, d, s);
+      return hipErrorInvalidValue;
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <class Ring, int R, class SrcA, class SrcX, class Dst>
+inline hipError_t launch_split_r(Ctx& c, const PassArgs<Ring>& A, const typename Ring::Params* rp, SrcA sa, SrcX sx, Dst da,
+                                 Dst dx, uint32_t grid, uint32_t nt, size_t lds, hipStream_t s) {
+  auto k = k_split<Ring, R, SrcA, SrcX, Dst>;
+  allow_lds(k, lds);
+  return launch(c, "fcirc_top_split", s, [&] { hipLaunchKernelGGL(k, dim3(grid), dim3(nt), lds, s, A, rp[0], rp[1], rp[2], sa, sx, da, dx); });
+}
+template <class Ring, int R, class Src, class Dst>
+inline hipError_t launch_merge_r(Ctx& c, const PassArgs<Ring>& A, const typename Ring::Params* rp, Src src, Dst dst,
+                                 uint32_t grid, uint32_t nt, size_t lds, hipStream_t s) {
+  auto k = k_merge<Ring, R, Src, Dst>;
+  allow_lds(k, lds);
+  return launch(c, "fcirc_top_merge", s, [&] { hipLaunchKernelGGL(k, dim3(grid), dim3(nt), lds, s, A, rp[0], rp[1], rp[2], src, dst); });
+}
+
+#define FCIRC_R_SWITCH(R_, CALL)          \
+  switch (R_) {                           \
+    case 1: return CALL(1);               \
+    case 2: return CALL(2);               \
+    case 3: return CALL(3);               \
+    case 4: return CALL(4);               \
+    case 5: return CALL(5);               \
+    case 6: return CALL(6);               \
+    case 7: return CALL(7);               \
+    case 8: return CALL(8);               \
+    case 9: return CALL(9);               \
+    case 10: return CALL(10);             \
+    default: return hipErrorInvalidValue; \
+  }
+
+template <class Ring, class SrcA, class SrcX, class Dst>
+inline hipError_t launch_split(Ctx& c, const PassArgs<Ring>& A, const typename Ring::Params* rp, SrcA sa, SrcX sx, Dst da,
+                               Dst dx, uint32_t grid, uint32_t nt, size_t lds, hipStream_t s) {
+#define FCIRC_CALL(r) launch_split_r<Ring, r>(c, A, rp, sa, sx, da, dx, grid, nt, lds, s)
+  FCIRC_R_SWITCH(A.logr, FCIRC_CALL)
+#undef FCIRC_CALL
+}
+template <class Ring, class Src, class Dst>
+inline hipError_t launch_merge(Ctx& c, const PassArgs<Ring>& A, const typename Ring::Params* rp, Src src, Dst dst,
+                               uint32_t grid, uint32_t nt, size_t lds, hipStream_t s) {
+#define FCIRC_CALL(r) launch_merge_r<Ring, r>(c, A, rp, src, dst, grid, nt, lds, s)
+  FCIRC_R_SWITCH(A.logr, FCIRC_CALL)
+#undef FCIRC_CALL
 }
 
 template <class Ring, class SrcA, class SrcX, class Dst>
@@ -285,6 +338,7 @@ inline hipError_t run_product(Ctx& c, const Schedule& S, uint32_t count, const t
     A.twi[i] = twi[i];
   }
   A.logn = L;
+  A.ninst = count;
   A.ring_per_inst = ring_per_inst ? 1 : 0;
   hipError_t e;
   if (S.ntop == 0) {
@@ -294,7 +348,7 @@ inline hipError_t run_product(Ctx& c, const Schedule& S, uint32_t count, const t
     A.tiles = 1;
     A.narr = 1;
     A.final_store = 1;
-    return launch_block_nt<Ring>(c, S.block_nt, A, rp, srca, srcx, dst, count, s);
+    return launch_block<Ring>(c, A, rp, srca, srcx, dst, s);
   }
   T* wa = ws;
   T* wx = ws + (uint64_t)count * n;
@@ -308,17 +362,13 @@ inline hipError_t run_product(Ctx& c, const Schedule& S, uint32_t count, const t
     A.tiles = (uint32_t)(n >> (A.logr + A.logc));
     A.narr = 2;
     A.final_store = 0;
-    const size_t lds = ((size_t)1 << (A.logr + A.logc)) * sizeof(T);
-    const uint32_t grid = A.tiles * 2 * count;
-    if (i == 0) {
-      auto k = k_split<Ring, LOGE, 256, SrcA, SrcX, StPlain<T>>;
-      allow_lds(k, lds);
-      e = launch(c, "fcirc_top_split", s, [&] { hipLaunchKernelGGL(k, dim3(grid), dim3(256), lds, s, A, rp[0], rp[1], rp[2], srca, srcx, swa, swx); });
-    } else {
-      auto k = k_split<Ring, LOGE, 256, LdPlain<T>, LdPlain<T>, StPlain<T>>;
-      allow_lds(k, lds);
-      e = launch(c, "fcirc_top_split", s, [&] { hipLaunchKernelGGL(k, dim3(grid), dim3(256), lds, s, A, rp[0], rp[1], rp[2], lwa, lwx, swa, swx); });
-    }
+    const size_t tile = (size_t)1 << (A.logr + A.logc);
+    const size_t lds = tile * sizeof(T);
+    const uint32_t grid = A.tiles * 2 * count, nt = (uint32_t)(tile >> EPT_LOG);
+    if (i == 0)
+      e = launch_split<Ring>(c, A, rp, srca, srcx, swa, swx, grid, nt, lds, s);
+    else
+      e = launch_split<Ring>(c, A, rp, lwa, lwx, swa, swx, grid, nt, lds, s);
     if (e != hipSuccess) return e;
   }
   A.d0 = L - S.block_levels;
@@ -327,7 +377,7 @@ inline hipError_t run_product(Ctx& c, const Schedule& S, uint32_t count, const t
   A.tiles = 1u << A.d0;
   A.narr = 1;
   A.final_store = 0;
-  e = launch_block_nt<Ring>(c, S.block_nt, A, rp, lwa, lwx, swy, A.tiles * count, s);
+  e = launch_block<Ring>(c, A, rp, lwa, lwx, swy, s);
   if (e != hipSuccess) return e;
   for (int i = S.ntop - 1; i >= 0; --i) {
     A.d0 = S.top_d0[i];
@@ -336,17 +386,13 @@ inline hipError_t run_product(Ctx& c, const Schedule& S, uint32_t count, const t
     A.tiles = (uint32_t)(n >> (A.logr + A.logc));
     A.narr = 1;
     A.final_store = i == 0 ? 1 : 0;
-    const size_t lds = ((size_t)1 << (A.logr + A.logc)) * sizeof(T);
-    const uint32_t grid = A.tiles * count;
-    if (i == 0) {
-      auto k = k_merge<Ring, LOGE, 256, LdPlain<T>, Dst>;
-      allow_lds(k, lds);
-      e = launch(c, "fcirc_top_merge", s, [&] { hipLaunchKernelGGL(k, dim3(grid), dim3(256), lds, s, A, rp[0], rp[1], rp[2], lwy, dst); });
-    } else {
-      auto k = k_merge<Ring, LOGE, 256, LdPlain<T>, StPlain<T>>;
-      allow_lds(k, lds);
-      e = launch(c, "fcirc_top_merge", s, [&] { hipLaunchKernelGGL(k, dim3(grid), dim3(256), lds, s, A, rp[0], rp[1], rp[2], lwy, swy); });
-    }
+    const size_t tile = (size_t)1 << (A.logr + A.logc);
+    const size_t lds = tile * sizeof(T);
+    const uint32_t grid = A.tiles * count, nt = (uint32_t)(tile >> EPT_LOG);
+    if (i == 0)
+      e = launch_merge<Ring>(c, A, rp, lwy, dst, grid, nt, lds, s);
+    else
+      e = launch_merge<Ring>(c, A, rp, lwy, swy, grid, nt, lds, s);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;

@@ -14,17 +14,22 @@
 // as 2^R rows of rs = n / 2^(d0+R) consecutive elements: every butterfly of those levels
 // joins two elements of the same column. A workgroup takes C = 2^logc adjacent columns
 // (the "tile"), so each global row segment it reads is C contiguous elements. The R
-// levels run as radix-2^k stages: a thread owns 2^k elements of one column spaced to
-// cover k consecutive levels, keeps them in registers through those k levels, and
-// exchanges through LDS between stages. The bottom pass of a product (d0 + R = log2 n)
-// has rs = 1 and C = 1, so a tile is one contiguous block; it also does the leaf
-// products and runs the merge levels back up before it writes anything out.
+// levels run as radix-2^k stages (k <= 4): every thread owns 16 elements per stage, as
+// 16 / 2^k items of 2^k elements of one column spaced to cover k consecutive levels.
+// It issues all its twiddle and element loads first, runs the k levels in registers,
+// and writes back; stages exchange through LDS. The first stage takes the remainder
+// (k = R mod 4, or 4) so every later stage is a full radix-16 stage. The bottom pass of
+// a product (d0 + R = log2 n, rs = 1, C = 1) is one contiguous block; it also does the
+// leaf products and runs the merge levels back up before anything leaves the workgroup,
+// and its deepest stage goes split -> leaf -> merge without leaving registers.
 #pragma once
 #include <type_traits>
 
 #include "ring.hpp"
 
 namespace fcirc {
+
+constexpr int EPT_LOG = 4;  // log2 elements per thread per stage
 
 template <class Ring>
 struct PassArgs {
@@ -36,310 +41,440 @@ struct PassArgs {
   uint32_t logc;                    // tile columns
   uint32_t tiles;                   // tiles per instance
   uint32_t narr;                    // arrays per instance handled by this launch (split: 1 or 2)
+  uint32_t ninst;                   // instances
   uint32_t ring_per_inst;           // 1: instance z uses ring parameters [z % 3]
   uint32_t final_store;             // 1: canonicalise values on the way out
 };
 
 struct TilePos {
   uint32_t tile, arr, inst;
-  uint32_t blk;      // depth-d0 block index
-  uint64_t base;     // element index of (row 0, column 0) within the instance
-  uint64_t rs;       // row stride in elements
+  uint32_t blk;   // depth-d0 block index
+  uint32_t base;  // element index of (row 0, column 0) within the instance (n <= 2^26)
+  uint32_t rs;    // row stride in elements
 };
 
 template <class Ring>
-__device__ __forceinline__ TilePos tile_pos(const PassArgs<Ring>& A) {
+__device__ __forceinline__ TilePos tile_pos(const PassArgs<Ring>& A, uint32_t wg) {
   TilePos t;
-  uint32_t wg = blockIdx.x;
   t.tile = wg % A.tiles;
-  uint32_t rest = wg / A.tiles;
+  const uint32_t rest = wg / A.tiles;
   t.arr = rest % A.narr;
   t.inst = rest / A.narr;
   const uint32_t cols_log = A.logn - A.d0 - A.logr;  // log2 rs
   const uint32_t tpb_log = cols_log - A.logc;        // log2 tiles per block
   t.blk = t.tile >> tpb_log;
   const uint32_t col0 = (t.tile & ((1u << tpb_log) - 1)) << A.logc;
-  t.base = ((uint64_t)t.blk << (A.logn - A.d0)) + col0;
-  t.rs = (uint64_t)1 << cols_log;
+  t.base = (t.blk << (A.logn - A.d0)) + col0;
+  t.rs = 1u << cols_log;
   return t;
 }
 
-// Iterate this thread's items of a stage covering tile levels [l0, l0 + K).
-// body(col, sb, row0, sh): element i of the item sits at row row0 + (i << sh), column col;
-// sb is the item's sub-block index at tile level l0.
-template <int K, int NT, class F>
-__device__ __forceinline__ void for_items(uint32_t logr, uint32_t logc, uint32_t l0, F&& body) {
-  const uint32_t sh = logr - l0 - K;
-  const uint32_t items = 1u << (logr + logc - K);
-  for (uint32_t item = threadIdx.x; item < items; item += NT) {
-    const uint32_t col = item & ((1u << logc) - 1);
-    const uint32_t rp = item >> logc;
-    const uint32_t o = rp & ((1u << sh) - 1);
-    const uint32_t sb = rp >> sh;
-    body(col, sb, (sb << (logr - l0)) + o, sh);
+// Position of a stage item: element i sits at row row0 + (i << sh), column col; sb is the
+// item's sub-block index at tile level l0.
+struct Item {
+  uint32_t col, sb, row0, sh;
+};
+
+__device__ __forceinline__ Item item_at(uint32_t item, uint32_t logr, uint32_t logc, uint32_t l0, uint32_t k) {
+  Item it;
+  it.sh = logr - l0 - k;
+  it.col = item & ((1u << logc) - 1);
+  const uint32_t rp = item >> logc;
+  it.sb = rp >> it.sh;
+  it.row0 = (it.sb << (logr - l0)) + (rp & ((1u << it.sh) - 1));
+  return it;
+}
+
+// Heap index of the twiddle used at tile level l0 + j by sub-group g of an item.
+__device__ __forceinline__ uint32_t tw_index(uint32_t d0, uint32_t blk, uint32_t l0, uint32_t j, uint32_t sb) {
+  const uint32_t l = l0 + j;
+  return (1u << (d0 + l)) + (blk << l) + (sb << j);
+}
+
+// The 2^K - 1 twiddles of one item, stored level by level: level j, group g at (2^j - 1 + g).
+template <class Ring, int K>
+__device__ __forceinline__ void load_tw(typename Ring::Tw* t, typename Ring::Tw const* tw, uint32_t d0, uint32_t blk,
+                                        uint32_t l0, uint32_t sb) {
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    const uint32_t ib = tw_index(d0, blk, l0, j, sb);
+#pragma unroll
+    for (int g = 0; g < (1 << j); ++g) t[(1 << j) - 1 + g] = tw[ib + g];
   }
 }
 
-// Heap index of the twiddle used at tile level l (= l0 + j) by sub-group g of an item.
-__device__ __forceinline__ uint32_t tw_index(uint32_t d0, uint32_t blk, uint32_t l0, uint32_t j, uint32_t sb, uint32_t g) {
-  const uint32_t l = l0 + j;
-  return (1u << (d0 + l)) + (blk << l) + (sb << j) + g;
-}
-
-// k split levels on the registers of one item, for the row (a) and/or the vector (x).
+// K split levels on the registers of one item, for the row (a) and/or the vector (x).
 template <class Ring, int K, bool DA, bool DX>
 __device__ __forceinline__ void split_levels(const Ring& R, typename Ring::T* va, typename Ring::T* vx,
-                                             typename Ring::Tw const* tw, uint32_t d0, uint32_t blk,
-                                             uint32_t l0, uint32_t sb) {
+                                             const typename Ring::Tw* t) {
 #pragma unroll
   for (int j = 0; j < K; ++j) {
     const int h = 1 << (K - 1 - j);
-    const uint32_t ib = tw_index(d0, blk, l0, j, sb, 0);
 #pragma unroll
     for (int g = 0; g < (1 << j); ++g) {
-      const typename Ring::Tw t = tw[ib + g];
 #pragma unroll
       for (int q = 0; q < h; ++q) {
         const int i = g * 2 * h + q;
-        if constexpr (DA) R.split_a(va[i], va[i + h], t);
-        if constexpr (DX) R.split_x(vx[i], vx[i + h], t);
+        if constexpr (DA) R.split_a(va[i], va[i + h], t[(1 << j) - 1 + g]);
+        if constexpr (DX) R.split_x(vx[i], vx[i + h], t[(1 << j) - 1 + g]);
       }
     }
   }
 }
 
-// k merge levels, deepest first.
+// K merge levels, deepest first.
 template <class Ring, int K>
-__device__ __forceinline__ void merge_levels(const Ring& R, typename Ring::T* vy, typename Ring::Tw const* twi,
-                                             uint32_t d0, uint32_t blk, uint32_t l0, uint32_t sb) {
+__device__ __forceinline__ void merge_levels(const Ring& R, typename Ring::T* vy, const typename Ring::Tw* t) {
 #pragma unroll
   for (int j = K - 1; j >= 0; --j) {
     const int h = 1 << (K - 1 - j);
-    const uint32_t ib = tw_index(d0, blk, l0, j, sb, 0);
 #pragma unroll
     for (int g = 0; g < (1 << j); ++g) {
-      const typename Ring::Tw t = twi[ib + g];
 #pragma unroll
       for (int q = 0; q < h; ++q) {
         const int i = g * 2 * h + q;
-        R.merge(vy[i], vy[i + h], t);
+        R.merge(vy[i], vy[i + h], t[(1 << j) - 1 + g]);
       }
     }
   }
 }
 
-// ---------------------------------------------------------------------------------------
-// Split pass: levels [d0, d0 + logr) of the row (arr 0) or the vector (arr 1), src -> dst.
-// ---------------------------------------------------------------------------------------
-template <class Ring, int LOGE, int NT, class SrcA, class SrcX, class Dst>
-__global__ void __launch_bounds__(NT) k_split(PassArgs<Ring> A, typename Ring::Params rp0, typename Ring::Params rp1,
-                                              typename Ring::Params rp2, SrcA srca, SrcX srcx, Dst dsta, Dst dstx) {
-  using T = typename Ring::T;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* lds = reinterpret_cast<T*>(smem_raw);
-  const TilePos P = tile_pos(A);
-  const uint32_t rsel = A.ring_per_inst ? P.inst % 3 : 0;
-  const typename Ring::Params rp = rsel == 0 ? rp0 : (rsel == 1 ? rp1 : rp2);
-  const Ring R(rp);
-  const typename Ring::Tw* tw = A.tw[rsel];
-  const uint32_t nst = (A.logr + LOGE - 1) / LOGE;
+template <class Ring>
+__device__ __forceinline__ Ring make_ring(const PassArgs<Ring>& A, uint32_t inst, const typename Ring::Params& rp0,
+                                          const typename Ring::Params& rp1, const typename Ring::Params& rp2,
+                                          uint32_t* rsel_out) {
+  const uint32_t rsel = A.ring_per_inst ? inst % 3 : 0;
+  *rsel_out = rsel;
+  return Ring(rsel == 0 ? rp0 : (rsel == 1 ? rp1 : rp2));
+}
 
-  auto stage = [&](auto kc, uint32_t s) {
-    constexpr int K = decltype(kc)::value;
-    const uint32_t l0 = s * LOGE;
-    const bool first = s == 0, last = s + 1 == nst;
-    for_items<K, NT>(A.logr, A.logc, l0, [&](uint32_t col, uint32_t sb, uint32_t row0, uint32_t sh) {
-      T v[1 << K];
+// ---------------------------------------------------------------------------------------
+// One split stage of a top pass (one array). FIRST: read from global; LAST: write global.
+// ---------------------------------------------------------------------------------------
+template <class Ring, int K, bool FIRST, bool LAST, bool IS_X, class Src, class Dst>
+__device__ __forceinline__ void split_stage(const PassArgs<Ring>& A, const TilePos& P, const Ring& R,
+                                            typename Ring::Tw const* tw, typename Ring::T* lds, uint32_t l0,
+                                            const Src& src, const Dst& dst) {
+  using T = typename Ring::T;
+  using Tw = typename Ring::Tw;
+  constexpr int IPT = 1 << (EPT_LOG - K);
+  constexpr int E = 1 << K;
+  T v[IPT][E];
+  Tw t[IPT][E - 1];
+  Item it[IPT];
 #pragma unroll
-      for (int i = 0; i < (1 << K); ++i) {
-        const uint32_t row = row0 + ((uint32_t)i << sh);
-        if (first) {
-          const uint64_t g = P.base + row * P.rs + col;
-          v[i] = P.arr == 0 ? srca(R, P.inst, g) : srcx(R, P.inst, g);
-        } else {
-          v[i] = lds[(row << A.logc) + col];
-        }
-      }
-      if (P.arr == 0)
-        split_levels<Ring, K, true, false>(R, v, v, tw, A.d0, P.blk, l0, sb);
+  for (int u = 0; u < IPT; ++u) {
+    it[u] = item_at(threadIdx.x + u * blockDim.x, A.logr, A.logc, l0, K);
+    load_tw<Ring, K>(t[u], tw, A.d0, P.blk, l0, it[u].sb);
+  }
+#pragma unroll
+  for (int u = 0; u < IPT; ++u)
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      const uint32_t row = it[u].row0 + ((uint32_t)i << it[u].sh);
+      if constexpr (FIRST)
+        v[u][i] = src(R, P.inst, P.base + row * P.rs + it[u].col);
       else
-        split_levels<Ring, K, false, true>(R, v, v, tw, A.d0, P.blk, l0, sb);
+        v[u][i] = lds[(row << A.logc) + it[u].col];
+    }
 #pragma unroll
-      for (int i = 0; i < (1 << K); ++i) {
-        const uint32_t row = row0 + ((uint32_t)i << sh);
-        if (last) {
-          const uint64_t g = P.base + row * P.rs + col;
-          if (P.arr == 0) dsta(P.inst, g, v[i]); else dstx(P.inst, g, v[i]);
-        } else {
-          lds[(row << A.logc) + col] = v[i];
-        }
-      }
-    });
-  };
-  for (uint32_t s = 0; s < nst; ++s) {
-    const uint32_t k = min((uint32_t)LOGE, A.logr - s * LOGE);
-    if constexpr (LOGE >= 5) { if (k == 5) stage(std::integral_constant<int, 5>{}, s); }
-    if constexpr (LOGE >= 4) { if (k == 4) stage(std::integral_constant<int, 4>{}, s); }
-    if (k == 3) stage(std::integral_constant<int, 3>{}, s);
-    if (k == 2) stage(std::integral_constant<int, 2>{}, s);
-    if (k == 1) stage(std::integral_constant<int, 1>{}, s);
-    __syncthreads();
+  for (int u = 0; u < IPT; ++u) split_levels<Ring, K, !IS_X, IS_X>(R, v[u], v[u], t[u]);
+#pragma unroll
+  for (int u = 0; u < IPT; ++u)
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      const uint32_t row = it[u].row0 + ((uint32_t)i << it[u].sh);
+      if constexpr (LAST)
+        dst(P.inst, P.base + row * P.rs + it[u].col, v[u][i]);
+      else
+        lds[(row << A.logc) + it[u].col] = v[u][i];
+    }
+}
+
+// Stage plan of a pass of R levels: the first stage takes the remainder.
+template <int R>
+struct StagePlan {
+  static constexpr int NST = (R + EPT_LOG - 1) / EPT_LOG;
+  static constexpr int K0 = R - EPT_LOG * (NST - 1);
+  static constexpr int k(int s) { return s == 0 ? K0 : EPT_LOG; }
+  static constexpr int l0(int s) { return s == 0 ? 0 : K0 + EPT_LOG * (s - 1); }
+};
+
+template <int N, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (N > 0) {
+    static_for<N - 1>(f);
+    f(std::integral_constant<int, N - 1>{});
   }
 }
 
 // ---------------------------------------------------------------------------------------
-// Merge pass: levels [d0 + logr - 1 .. d0] of the product, src -> dst (may alias: each
+// Split pass: levels [d0, d0 + R) of the row (arr 0) or the vector (arr 1), src -> dst.
+// blockDim.x = tile elements / 16 (at most 512).
+// ---------------------------------------------------------------------------------------
+template <class Ring, int R, class SrcA, class SrcX, class Dst>
+__global__ void __launch_bounds__(512) k_split(PassArgs<Ring> A, typename Ring::Params rp0, typename Ring::Params rp1,
+                                               typename Ring::Params rp2, SrcA srca, SrcX srcx, Dst dsta, Dst dstx) {
+  using T = typename Ring::T;
+  using SP = StagePlan<R>;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* lds = reinterpret_cast<T*>(smem_raw);
+  const TilePos P = tile_pos(A, blockIdx.x);
+  uint32_t rsel;
+  const Ring Rg = make_ring(A, P.inst, rp0, rp1, rp2, &rsel);
+  const typename Ring::Tw* tw = A.tw[rsel];
+  static_for<SP::NST>([&](auto sc) {
+    constexpr int s = decltype(sc)::value;
+    constexpr bool first = s == 0, last = s + 1 == SP::NST;
+    if (P.arr == 0)
+      split_stage<Ring, SP::k(s), first, last, false>(A, P, Rg, tw, lds, SP::l0(s), srca, dsta);
+    else
+      split_stage<Ring, SP::k(s), first, last, true>(A, P, Rg, tw, lds, SP::l0(s), srcx, dstx);
+    if constexpr (!last) __syncthreads();
+  });
+}
+
+// ---------------------------------------------------------------------------------------
+// One merge stage of a top pass. FIRST: read global (the deepest stage runs first).
+// ---------------------------------------------------------------------------------------
+template <class Ring, int K, bool FIRST, bool LAST, class Src, class Dst>
+__device__ __forceinline__ void merge_stage(const PassArgs<Ring>& A, const TilePos& P, const Ring& R,
+                                            typename Ring::Tw const* twi, typename Ring::T* lds, uint32_t l0,
+                                            const Src& src, const Dst& dst) {
+  using T = typename Ring::T;
+  using Tw = typename Ring::Tw;
+  constexpr int IPT = 1 << (EPT_LOG - K);
+  constexpr int E = 1 << K;
+  T v[IPT][E];
+  Tw t[IPT][E - 1];
+  Item it[IPT];
+#pragma unroll
+  for (int u = 0; u < IPT; ++u) {
+    it[u] = item_at(threadIdx.x + u * blockDim.x, A.logr, A.logc, l0, K);
+    load_tw<Ring, K>(t[u], twi, A.d0, P.blk, l0, it[u].sb);
+  }
+#pragma unroll
+  for (int u = 0; u < IPT; ++u)
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      const uint32_t row = it[u].row0 + ((uint32_t)i << it[u].sh);
+      if constexpr (FIRST)
+        v[u][i] = src(R, P.inst, P.base + row * P.rs + it[u].col);
+      else
+        v[u][i] = lds[(row << A.logc) + it[u].col];
+    }
+#pragma unroll
+  for (int u = 0; u < IPT; ++u) merge_levels<Ring, K>(R, v[u], t[u]);
+#pragma unroll
+  for (int u = 0; u < IPT; ++u)
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      const uint32_t row = it[u].row0 + ((uint32_t)i << it[u].sh);
+      if constexpr (LAST)
+        dst(P.inst, P.base + row * P.rs + it[u].col, A.final_store ? R.canon(v[u][i]) : v[u][i]);
+      else
+        lds[(row << A.logc) + it[u].col] = v[u][i];
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// Merge pass: levels [d0 + R - 1 .. d0] of the product, src -> dst (may alias: a
 // workgroup reads its whole tile before it writes any of it).
 // ---------------------------------------------------------------------------------------
-template <class Ring, int LOGE, int NT, class Src, class Dst>
-__global__ void __launch_bounds__(NT) k_merge(PassArgs<Ring> A, typename Ring::Params rp0, typename Ring::Params rp1,
-                                              typename Ring::Params rp2, Src src, Dst dst) {
+template <class Ring, int R, class Src, class Dst>
+__global__ void __launch_bounds__(512) k_merge(PassArgs<Ring> A, typename Ring::Params rp0, typename Ring::Params rp1,
+                                               typename Ring::Params rp2, Src src, Dst dst) {
   using T = typename Ring::T;
+  using SP = StagePlan<R>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* lds = reinterpret_cast<T*>(smem_raw);
-  const TilePos P = tile_pos(A);
-  const uint32_t rsel = A.ring_per_inst ? P.inst % 3 : 0;
-  const typename Ring::Params rp = rsel == 0 ? rp0 : (rsel == 1 ? rp1 : rp2);
-  const Ring R(rp);
+  const TilePos P = tile_pos(A, blockIdx.x);
+  uint32_t rsel;
+  const Ring Rg = make_ring(A, P.inst, rp0, rp1, rp2, &rsel);
   const typename Ring::Tw* twi = A.twi[rsel];
-  const uint32_t nst = (A.logr + LOGE - 1) / LOGE;
-
-  auto stage = [&](auto kc, uint32_t s) {
-    constexpr int K = decltype(kc)::value;
-    const uint32_t l0 = s * LOGE;
-    const bool first = s + 1 == nst, last = s == 0;  // merge runs deepest stage first
-    for_items<K, NT>(A.logr, A.logc, l0, [&](uint32_t col, uint32_t sb, uint32_t row0, uint32_t sh) {
-      T v[1 << K];
-#pragma unroll
-      for (int i = 0; i < (1 << K); ++i) {
-        const uint32_t row = row0 + ((uint32_t)i << sh);
-        if (first)
-          v[i] = src(R, P.inst, P.base + row * P.rs + col);
-        else
-          v[i] = lds[(row << A.logc) + col];
-      }
-      merge_levels<Ring, K>(R, v, twi, A.d0, P.blk, l0, sb);
-#pragma unroll
-      for (int i = 0; i < (1 << K); ++i) {
-        const uint32_t row = row0 + ((uint32_t)i << sh);
-        if (last)
-          dst(P.inst, P.base + row * P.rs + col, A.final_store ? R.canon(v[i]) : v[i]);
-        else
-          lds[(row << A.logc) + col] = v[i];
-      }
-    });
-  };
-  for (int s = (int)nst - 1; s >= 0; --s) {
-    const uint32_t k = min((uint32_t)LOGE, A.logr - s * LOGE);
-    if constexpr (LOGE >= 5) { if (k == 5) stage(std::integral_constant<int, 5>{}, s); }
-    if constexpr (LOGE >= 4) { if (k == 4) stage(std::integral_constant<int, 4>{}, s); }
-    if (k == 3) stage(std::integral_constant<int, 3>{}, s);
-    if (k == 2) stage(std::integral_constant<int, 2>{}, s);
-    if (k == 1) stage(std::integral_constant<int, 1>{}, s);
-    __syncthreads();
-  }
+  static_for<SP::NST>([&](auto sc) {
+    constexpr int s = SP::NST - 1 - decltype(sc)::value;  // deepest stage first
+    constexpr bool first = s + 1 == SP::NST, last = s == 0;
+    merge_stage<Ring, SP::k(s), first, last>(A, P, Rg, twi, lds, SP::l0(s), src, dst);
+    if constexpr (!last) __syncthreads();
+  });
 }
 
 // ---------------------------------------------------------------------------------------
-// Block pass (bottom of the recursion): one contiguous block of 2^logr elements per
-// workgroup (d0 + logr = logn, logc = 0). Split levels on row and vector, leaf products,
-// merge levels back up, all in LDS and registers; the deepest stage goes split -> leaf ->
-// merge without leaving registers.
+// Block pass (bottom of the recursion): a contiguous block of 2^LOGR elements per thread
+// group (d0 + LOGR = logn, logc = 0). Blocks of fewer than 1024 elements share a
+// workgroup: 64 threads hold 64 / (2^LOGR / 16) groups, each its own block.
 // ---------------------------------------------------------------------------------------
-template <class Ring, int LOGE, int NT, class SrcA, class SrcX, class Dst>
-__global__ void __launch_bounds__(NT) k_block(PassArgs<Ring> A, typename Ring::Params rp0, typename Ring::Params rp1,
-                                              typename Ring::Params rp2, SrcA srca, SrcX srcx, Dst dst) {
+template <int LOGR>
+struct BlockShape {
+  static constexpr int ACTIVE_LOG = LOGR > EPT_LOG ? LOGR - EPT_LOG : 0;  // threads per block
+  static constexpr int NT = (1 << ACTIVE_LOG) < 64 ? 64 : (1 << ACTIVE_LOG);
+  static constexpr int GROUPS = NT >> ACTIVE_LOG;                        // blocks per workgroup
+  static constexpr int NST = LOGR == 0 ? 0 : (LOGR + EPT_LOG - 1) / EPT_LOG;
+  static constexpr int K0 = LOGR - EPT_LOG * (NST > 0 ? NST - 1 : 0);   // levels of the first stage
+  static constexpr int EPT = LOGR < EPT_LOG ? (1 << LOGR) : (1 << EPT_LOG);
+};
+
+template <class Ring, int LOGR, int K, bool FIRST, bool DEEPEST, class SrcA, class SrcX, class Dst>
+__device__ __forceinline__ void block_split_stage(const PassArgs<Ring>& A, const TilePos& P, const Ring& R,
+                                                  typename Ring::Tw const* tw, typename Ring::Tw const* twi,
+                                                  typename Ring::T* sa, typename Ring::T* sx, uint32_t l0, uint32_t ltid,
+                                                  const SrcA& srca, const SrcX& srcx, const Dst& dst) {
   using T = typename Ring::T;
+  using Tw = typename Ring::Tw;
+  using S = BlockShape<LOGR>;
+  constexpr int E = 1 << K;
+  constexpr int IPT = S::EPT / E;
+  constexpr uint32_t ACTIVE = 1u << S::ACTIVE_LOG;
+  T va[IPT][E], vx[IPT][E];
+  Tw t[IPT][E - 1];
+  Tw ti[DEEPEST ? IPT : 1][E - 1];
+  Item it[IPT];
+#pragma unroll
+  for (int u = 0; u < IPT; ++u) {
+    it[u] = item_at(ltid + u * ACTIVE, LOGR, 0, l0, K);
+    load_tw<Ring, K>(t[u], tw, A.d0, P.blk, l0, it[u].sb);
+    if constexpr (DEEPEST) load_tw<Ring, K>(ti[u], twi, A.d0, P.blk, l0, it[u].sb);
+  }
+#pragma unroll
+  for (int u = 0; u < IPT; ++u)
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      const uint32_t row = it[u].row0 + ((uint32_t)i << it[u].sh);
+      if constexpr (FIRST) {
+        va[u][i] = srca(R, P.inst, P.base + row);
+        vx[u][i] = srcx(R, P.inst, P.base + row);
+      } else {
+        va[u][i] = sa[row];
+        vx[u][i] = sx[row];
+      }
+    }
+#pragma unroll
+  for (int u = 0; u < IPT; ++u) split_levels<Ring, K, true, true>(R, va[u], vx[u], t[u]);
+  if constexpr (DEEPEST) {
+#pragma unroll
+    for (int u = 0; u < IPT; ++u)
+#pragma unroll
+      for (int i = 0; i < E; ++i) va[u][i] = R.leaf(va[u][i], vx[u][i]);
+#pragma unroll
+    for (int u = 0; u < IPT; ++u) merge_levels<Ring, K>(R, va[u], ti[u]);
+  }
+#pragma unroll
+  for (int u = 0; u < IPT; ++u)
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      const uint32_t row = it[u].row0 + ((uint32_t)i << it[u].sh);
+      if constexpr (DEEPEST && FIRST) {
+        dst(P.inst, P.base + row, A.final_store ? R.canon(va[u][i]) : va[u][i]);
+      } else {
+        sa[row] = va[u][i];
+        if constexpr (!DEEPEST) sx[row] = vx[u][i];
+      }
+    }
+}
+
+template <class Ring, int LOGR, bool LAST, class Dst>
+__device__ __forceinline__ void block_merge_stage(const PassArgs<Ring>& A, const TilePos& P, const Ring& R,
+                                                  typename Ring::Tw const* twi, typename Ring::T* sa, uint32_t l0,
+                                                  uint32_t ltid, const Dst& dst) {
+  using T = typename Ring::T;
+  using Tw = typename Ring::Tw;
+  constexpr int K = EPT_LOG;
+  constexpr int E = 1 << K;
+  const Item it = item_at(ltid, LOGR, 0, l0, K);
+  Tw t[E - 1];
+  load_tw<Ring, K>(t, twi, A.d0, P.blk, l0, it.sb);
+  T v[E];
+#pragma unroll
+  for (int i = 0; i < E; ++i) v[i] = sa[it.row0 + ((uint32_t)i << it.sh)];
+  merge_levels<Ring, K>(R, v, t);
+#pragma unroll
+  for (int i = 0; i < E; ++i) {
+    const uint32_t row = it.row0 + ((uint32_t)i << it.sh);
+    if constexpr (LAST)
+      dst(P.inst, P.base + row, A.final_store ? R.canon(v[i]) : v[i]);
+    else
+      sa[row] = v[i];
+  }
+}
+
+template <class Ring, int LOGR, class SrcA, class SrcX, class Dst>
+__global__ void __launch_bounds__(BlockShape<LOGR>::NT) k_block(PassArgs<Ring> A, typename Ring::Params rp0,
+                                                                 typename Ring::Params rp1, typename Ring::Params rp2,
+                                                                 SrcA srca, SrcX srcx, Dst dst) {
+  using T = typename Ring::T;
+  using S = BlockShape<LOGR>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* sa = reinterpret_cast<T*>(smem_raw);
-  T* sx = sa + ((size_t)1 << A.logr);
-  const TilePos P = tile_pos(A);
-  const uint32_t rsel = A.ring_per_inst ? P.inst % 3 : 0;
-  const typename Ring::Params rp = rsel == 0 ? rp0 : (rsel == 1 ? rp1 : rp2);
-  const Ring R(rp);
+  const uint32_t group = threadIdx.x >> S::ACTIVE_LOG;
+  const uint32_t ltid = threadIdx.x & ((1u << S::ACTIVE_LOG) - 1);
+  const uint32_t vwg = blockIdx.x * S::GROUPS + group;
+  const bool active = vwg < A.tiles * A.ninst;
+  T* sa = reinterpret_cast<T*>(smem_raw) + ((size_t)group << (LOGR + 1));
+  T* sx = sa + ((size_t)1 << LOGR);
+  const TilePos P = tile_pos(A, active ? vwg : 0);
+  uint32_t rsel;
+  const Ring R = make_ring(A, P.inst, rp0, rp1, rp2, &rsel);
   const typename Ring::Tw* tw = A.tw[rsel];
   const typename Ring::Tw* twi = A.twi[rsel];
-  const uint32_t nst = (A.logr + LOGE - 1) / LOGE;
 
-  if (A.logr == 0) {  // 1 x 1 product
-    if (threadIdx.x == 0) {
+  if constexpr (LOGR == 0) {
+    if (active) {
       const T y = R.leaf(srca(R, P.inst, P.base), srcx(R, P.inst, P.base));
       dst(P.inst, P.base, A.final_store ? R.canon(y) : y);
     }
     return;
-  }
-
-  auto split_stage = [&](auto kc, uint32_t s) {
-    constexpr int K = decltype(kc)::value;
-    const uint32_t l0 = s * LOGE;
-    const bool first = s == 0, deepest = s + 1 == nst;
-    for_items<K, NT>(A.logr, 0, l0, [&](uint32_t, uint32_t sb, uint32_t row0, uint32_t sh) {
-      T va[1 << K], vx[1 << K];
+  } else {
+    constexpr int NST = S::NST, K0 = S::K0;
+    // split stages (first takes K0 levels), the deepest also runs leaf + its merge levels
+    if (active) block_split_stage<Ring, LOGR, K0, true, NST == 1>(A, P, R, tw, twi, sa, sx, 0, ltid, srca, srcx, dst);
+    if constexpr (NST > 1) {
+      __syncthreads();
 #pragma unroll
-      for (int i = 0; i < (1 << K); ++i) {
-        const uint32_t row = row0 + ((uint32_t)i << sh);
-        if (first) {
-          va[i] = srca(R, P.inst, P.base + row);
-          vx[i] = srcx(R, P.inst, P.base + row);
-        } else {
-          va[i] = sa[row];
-          vx[i] = sx[row];
+      for (int s = 1; s < NST; ++s) {
+        const uint32_t l0 = K0 + EPT_LOG * (s - 1);
+        if (active) {
+          if (s + 1 == NST)
+            block_split_stage<Ring, LOGR, EPT_LOG, false, true>(A, P, R, tw, twi, sa, sx, l0, ltid, srca, srcx, dst);
+          else
+            block_split_stage<Ring, LOGR, EPT_LOG, false, false>(A, P, R, tw, twi, sa, sx, l0, ltid, srca, srcx, dst);
         }
+        __syncthreads();
       }
-      split_levels<Ring, K, true, true>(R, va, vx, tw, A.d0, P.blk, l0, sb);
-      if (deepest) {
+      // merge stages above the deepest one (all full radix-16 except the first stage's K0)
 #pragma unroll
-        for (int i = 0; i < (1 << K); ++i) va[i] = R.leaf(va[i], vx[i]);
-        merge_levels<Ring, K>(R, va, twi, A.d0, P.blk, l0, sb);
+      for (int s = NST - 2; s >= 1; --s) {
+        const uint32_t l0 = K0 + EPT_LOG * (s - 1);
+        if (active) block_merge_stage<Ring, LOGR, false>(A, P, R, twi, sa, l0, ltid, dst);
+        __syncthreads();
       }
+      if (active) {
+        // stage 0 merge: K0 levels, items of 2^K0 elements, 16 / 2^K0 items per thread
+        constexpr int E = 1 << K0;
+        constexpr int IPT = S::EPT / E;
+        constexpr uint32_t ACTIVE = 1u << S::ACTIVE_LOG;
+        typename Ring::Tw t[IPT][E - 1];
+        T v[IPT][E];
+        Item it[IPT];
 #pragma unroll
-      for (int i = 0; i < (1 << K); ++i) {
-        const uint32_t row = row0 + ((uint32_t)i << sh);
-        if (deepest && first) {
-          dst(P.inst, P.base + row, A.final_store ? R.canon(va[i]) : va[i]);
-        } else {
-          sa[row] = va[i];
-          if (!deepest) sx[row] = vx[i];
+        for (int u = 0; u < IPT; ++u) {
+          it[u] = item_at(ltid + u * ACTIVE, LOGR, 0, 0, K0);
+          load_tw<Ring, K0>(t[u], twi, A.d0, P.blk, 0, it[u].sb);
         }
-      }
-    });
-  };
-  auto merge_stage = [&](auto kc, uint32_t s) {
-    constexpr int K = decltype(kc)::value;
-    const uint32_t l0 = s * LOGE;
-    const bool last = s == 0;
-    for_items<K, NT>(A.logr, 0, l0, [&](uint32_t, uint32_t sb, uint32_t row0, uint32_t sh) {
-      T v[1 << K];
 #pragma unroll
-      for (int i = 0; i < (1 << K); ++i) v[i] = sa[row0 + ((uint32_t)i << sh)];
-      merge_levels<Ring, K>(R, v, twi, A.d0, P.blk, l0, sb);
+        for (int u = 0; u < IPT; ++u)
 #pragma unroll
-      for (int i = 0; i < (1 << K); ++i) {
-        const uint32_t row = row0 + ((uint32_t)i << sh);
-        if (last)
-          dst(P.inst, P.base + row, A.final_store ? R.canon(v[i]) : v[i]);
-        else
-          sa[row] = v[i];
+          for (int i = 0; i < E; ++i) v[u][i] = sa[it[u].row0 + ((uint32_t)i << it[u].sh)];
+#pragma unroll
+        for (int u = 0; u < IPT; ++u) merge_levels<Ring, K0>(R, v[u], t[u]);
+#pragma unroll
+        for (int u = 0; u < IPT; ++u)
+#pragma unroll
+          for (int i = 0; i < E; ++i) {
+            const uint32_t row = it[u].row0 + ((uint32_t)i << it[u].sh);
+            dst(P.inst, P.base + row, A.final_store ? R.canon(v[u][i]) : v[u][i]);
+          }
       }
-    });
-  };
-  for (uint32_t s = 0; s < nst; ++s) {
-    const uint32_t k = min((uint32_t)LOGE, A.logr - s * LOGE);
-    if constexpr (LOGE >= 5) { if (k == 5) split_stage(std::integral_constant<int, 5>{}, s); }
-    if constexpr (LOGE >= 4) { if (k == 4) split_stage(std::integral_constant<int, 4>{}, s); }
-    if (k == 3) split_stage(std::integral_constant<int, 3>{}, s);
-    if (k == 2) split_stage(std::integral_constant<int, 2>{}, s);
-    if (k == 1) split_stage(std::integral_constant<int, 1>{}, s);
-    __syncthreads();
-  }
-  for (int s = (int)nst - 2; s >= 0; --s) {
-    const uint32_t k = min((uint32_t)LOGE, A.logr - s * LOGE);
-    if constexpr (LOGE >= 5) { if (k == 5) merge_stage(std::integral_constant<int, 5>{}, s); }
-    if constexpr (LOGE >= 4) { if (k == 4) merge_stage(std::integral_constant<int, 4>{}, s); }
-    if (k == 3) merge_stage(std::integral_constant<int, 3>{}, s);
-    if (k == 2) merge_stage(std::integral_constant<int, 2>{}, s);
-    if (k == 1) merge_stage(std::integral_constant<int, 1>{}, s);
-    __syncthreads();
+    }
   }
 }
 
