@@ -157,6 +157,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip timing the CPU oracle")
     ap.add_argument("--no-secondary", action="store_true", help="skip the secondary workloads")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="first run 3 plain 64 MiB device copies (torch), the reference for HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the library runs each product on a single device "
@@ -168,6 +170,13 @@ def main():
     from paper_2103_02605_amd import workloads as W
 
     torch.cuda.set_device(0)
+    if args.calib_copy:
+        src = torch.ones(1 << 24, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     n, ms, stages, T, _ = headline(torch, F, W, args.steps, args.warmup)
     value = n / ms / 1e6  # Gcoeff/s
     L = 21

@@ -155,6 +155,14 @@ int fcirc_stage_times(fcirc_ctx *ctx, const char **names, uint64_t *launches, do
 fcirc_status fcirc_tune(fcirc_ctx *ctx, uint64_t n, fcirc_ring ring, void *stream);
 fcirc_status fcirc_set_split(fcirc_ctx *ctx, int top_levels);
 int fcirc_get_split(fcirc_ctx *ctx, uint64_t n, fcirc_ring ring);
+/*
+ * Set the schedule for (ring, n) explicitly, as fcirc_tune would: top_levels (-1 default),
+ * tile_log = log2 elements of a top-pass tile (-1 default, at most 13), xcd = 1 for the
+ * XCD-aware tile order. fcirc_get_schedule reports the schedule in use and returns the
+ * number of top passes.
+ */
+fcirc_status fcirc_set_schedule(fcirc_ctx *ctx, fcirc_ring ring, uint64_t n, int top_levels, int tile_log, int xcd);
+int fcirc_get_schedule(fcirc_ctx *ctx, fcirc_ring ring, uint64_t n, int *top_levels, int *tile_log, int *xcd);
 
 #ifdef __cplusplus
 }

@@ -49,6 +49,9 @@ SIGNATURES = {
     "fcirc_tune": (C.c_int, [C.c_void_p, C.c_uint64, C.c_int, C.c_void_p]),
     "fcirc_set_split": (C.c_int, [C.c_void_p, C.c_int]),
     "fcirc_get_split": (C.c_int, [C.c_void_p, C.c_uint64, C.c_int]),
+    "fcirc_set_schedule": (C.c_int, [C.c_void_p, C.c_int, C.c_uint64, C.c_int, C.c_int, C.c_int]),
+    "fcirc_get_schedule": (C.c_int, [C.c_void_p, C.c_int, C.c_uint64, C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                     C.POINTER(C.c_int)]),
 }
 
 _lib = None

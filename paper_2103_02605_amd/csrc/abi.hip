@@ -10,9 +10,6 @@
 
 using namespace fcirc;
 
-struct fcirc_ctx {
-  Ctx c;
-};
 
 namespace {
 
@@ -214,9 +211,8 @@ fcirc_status fcirc_set_split(fcirc_ctx* ctx, int top_levels) {
 
 int fcirc_get_split(fcirc_ctx* ctx, uint64_t n, fcirc_ring ring) {
   if (!ctx || !is_pow2(n) || !known_ring(ring)) return -1;
-  const int L = ilog2(n);
-  const Schedule S = make_schedule(L, ring == FCIRC_C64 || ring == FCIRC_R32 ? 3 : 2, effective_top(ctx->c, ring, L));
-  return L - S.block_levels;
+  const Schedule S = schedule_for(ctx->c, ring, ilog2(n));
+  return S.L - S.block_levels;
 }
 
 }  // extern "C"

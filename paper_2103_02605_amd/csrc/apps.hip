@@ -236,6 +236,7 @@ fcirc_status three_prime_products(Ctx& c, const V* a, uint64_t na, const V* b, u
   ZpParams rp[3];
   const ZpTw* tw[3];
   const ZpTw* twi[3];
+  const Uniform16<Zp>* U[3];
   for (int i = 0; i < 3; ++i) {
     const ZpTables* T = nullptr;
     fcirc_status st = zp_tables(c, ps[i], 1u, L, &T);
@@ -243,10 +244,11 @@ fcirc_status three_prime_products(Ctx& c, const V* a, uint64_t na, const V* b, u
     rp[i] = zp_params(ps[i], L);
     tw[i] = T->tw;
     twi[i] = T->twi;
+    U[i] = &T->U;
   }
   const uint64_t N = (uint64_t)1 << L;
-  const Schedule S = make_schedule(L, 2, effective_top(c, 0, L));
-  return hip_status(run_product<Zp>(c, S, 3, rp, tw, twi, true, LdRowRev<V>{a, na, N}, LdVecPad<V>{b, nb},
+  const Schedule S = schedule_for(c, FCIRC_ZP_998244353, L);
+  return hip_status(run_product<Zp>(c, S, 3, rp, tw, twi, U, true, LdRowRev<V>{a, na, N}, LdVecPad<V>{b, nb},
                                     StPlain<uint32_t>{res, N}, res, ws, s));
 }
 
@@ -256,7 +258,7 @@ fcirc_status polymul_i64(Ctx& c, const int32_t* a, uint64_t na, const int32_t* b
   const uint64_t nc = na + nb - 1;
   const int L = ilog2(nc);
   const uint64_t N = (uint64_t)1 << L;
-  const Schedule S = make_schedule(L, 2, effective_top(c, 0, L));
+  const Schedule S = schedule_for(c, FCIRC_ZP_998244353, L);
   const uint64_t wse = 3 * N + product_ws_elems(S, 3, false);
   fcirc_status st = ws_reserve(c, wse * sizeof(uint32_t));
   if (st != FCIRC_OK) return st;
@@ -272,7 +274,7 @@ fcirc_status bigint_mul(Ctx& c, const uint16_t* a, uint64_t na, const uint16_t* 
   const uint64_t nc = na + nb - 1, nl = na + nb;
   const int L = ilog2(nc);
   const uint64_t N = (uint64_t)1 << L;
-  const Schedule S = make_schedule(L, 2, effective_top(c, 0, L));
+  const Schedule S = schedule_for(c, FCIRC_ZP_998244353, L);
   const uint64_t nblk = (nl + CARRY_BLOCK - 1) / CARRY_BLOCK;
   // layout (uint32 units): res[3N] | coeffs u64[nc] | u[nl] | summaries[2 nblk] | product workspace
   const uint64_t off_c = 3 * N, off_u = off_c + 2 * nc, off_s = off_u + nl, off_w = (off_s + 2 * nblk + 63) & ~63ull;

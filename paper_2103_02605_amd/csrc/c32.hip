@@ -37,6 +37,19 @@ __global__ void k_c32_tables(float2* tw, float2* twi, uint32_t nent, double lnab
   twi[idx] = make_float2((float)(cs / mag), (float)(-sn / mag));
 }
 
+Uniform16<C32> c32_uniform16() {
+  // rho_j = e^(i pi / 2^j): tu = e^(i pi brev_j(g) / 2^j), tui its conjugate
+  Uniform16<C32> U;
+  for (int j = 0; j < 4; ++j)
+    for (uint32_t g = 0; g < (1u << j); ++g) {
+      const uint32_t e = j == 0 ? 0u : (__builtin_bitreverse32(g) >> (32 - j));
+      const double ang = M_PI * (double)e / (double)(1u << j);
+      U.tu[(1 << j) - 1 + g] = make_float2((float)std::cos(ang), (float)std::sin(ang));
+      U.tui[(1 << j) - 1 + g] = make_float2((float)std::cos(ang), (float)-std::sin(ang));
+    }
+  return U;
+}
+
 fcirc_status c32_tables(Ctx& c, double fre, double fim, int L, hipStream_t s, const C32Tables** out) {
   if (fre == 0.0 && fim == 0.0) return FCIRC_ENOROOT;
   for (auto& t : c.c32)
@@ -50,6 +63,7 @@ fcirc_status c32_tables(Ctx& c, double fre, double fim, int L, hipStream_t s, co
   t.fre = fre;
   t.fim = fim;
   t.levels = levels;
+  t.U = c32_uniform16();
   if (hipMalloc(&t.tw, ne * sizeof(float2)) != hipSuccess || hipMalloc(&t.twi, ne * sizeof(float2)) != hipSuccess) {
     (void)hipGetLastError();
     if (t.tw) (void)hipFree(t.tw);
@@ -79,7 +93,7 @@ fcirc_status c32_matvec(Ctx& c, const void* a, const void* x, void* y, int L, ui
   const C32Tables* T = nullptr;
   fcirc_status st = c32_tables(c, fre, fim, L, s, &T);
   if (st != FCIRC_OK) return st;
-  const Schedule S = make_schedule(L, 3, effective_top(c, real_io ? 4 : 3, L));
+  const Schedule S = schedule_for(c, real_io ? FCIRC_R32 : FCIRC_C64, L);
   const uint64_t wse = product_ws_elems(S, count, real_io);
   if (wse) {
     st = ws_reserve(c, wse * sizeof(float2));
@@ -91,12 +105,13 @@ fcirc_status c32_matvec(Ctx& c, const void* a, const void* x, void* y, int L, ui
   const float2* twi[3] = {T->twi, T->twi, T->twi};
   const uint64_t n = (uint64_t)1 << L;
   float2* ws = (float2*)c.ws;
+  const Uniform16<C32>* U[3] = {&T->U, &T->U, &T->U};
   hipError_t e;
   if (real_io) {
-    e = run_product<C32>(c, S, count, rps, tw, twi, false, LdR32{(const float*)a, n}, LdR32{(const float*)x, n},
+    e = run_product<C32>(c, S, count, rps, tw, twi, U, false, LdR32{(const float*)a, n}, LdR32{(const float*)x, n},
                          StR32{(float*)y, n}, nullptr, ws, s);
   } else {
-    e = run_product<C32>(c, S, count, rps, tw, twi, false, LdPlain<float2>{(const float2*)a, n},
+    e = run_product<C32>(c, S, count, rps, tw, twi, U, false, LdPlain<float2>{(const float2*)a, n},
                          LdPlain<float2>{(const float2*)x, n}, StPlain<float2>{(float2*)y, n}, (float2*)y, ws, s);
   }
   return hip_status(e);

@@ -6,6 +6,7 @@
 
 #include <cstdint>
 #include <cstdio>
+#include <deque>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -75,11 +76,18 @@ struct Timer {
 // ----------------------------------------------------------------------------------------
 // Twiddle tables (heap order, index 2^d + b) for one ring and one f.
 // ----------------------------------------------------------------------------------------
+// Uniform radix-16 factors rho_j^brev_j(g), j < 4, and their inverses (host side).
+template <class Ring>
+struct Uniform16 {
+  typename Ring::Tw tu[15], tui[15];
+};
+
 struct ZpTables {
   uint32_t p = 0, f = 0;
   int levels = 0;  // covers depths d < levels
   ZpTw* tw = nullptr;
   ZpTw* twi = nullptr;
+  Uniform16<Zp> U;
 };
 
 struct C32Tables {
@@ -87,6 +95,7 @@ struct C32Tables {
   int levels = 0;
   float2* tw = nullptr;
   float2* twi = nullptr;
+  Uniform16<C32> U;
 };
 
 // ----------------------------------------------------------------------------------------
@@ -94,6 +103,7 @@ struct C32Tables {
 // ----------------------------------------------------------------------------------------
 struct Schedule {
   int L = 0;
+  int xcd = 1;           // XCD-aware tile order in the top passes
   int block_levels = 0;  // levels done in the LDS-resident block pass
   int ntop = 0;          // HBM-streamed top passes
   int top_d0[4] = {0, 0, 0, 0};
@@ -105,20 +115,25 @@ struct TuneKey {
   int ring, L;
   bool operator<(const TuneKey& o) const { return ring != o.ring ? ring < o.ring : L < o.L; }
 };
+struct TuneVal {
+  int top = -1;       // top levels (HBM-streamed), -1: default
+  int tile_log = -1;  // log2 elements per top-pass tile, -1: default
+  int xcd = 1;
+};
 
 struct GraphEntry;  // batched launches captured in HIP graphs (batched.hip)
 
 struct Ctx {
   int device = 0;
   hipDeviceProp_t prop{};
-  std::vector<ZpTables> zp;
-  std::vector<C32Tables> c32;
+  std::deque<ZpTables> zp;   // deque: references stay valid as plans are added
+  std::deque<C32Tables> c32;
   void* ws = nullptr;
   size_t ws_bytes = 0;
   size_t ws_limit = SIZE_MAX;
   uint32_t* d_status = nullptr;
   int forced_top = -1;
-  std::map<TuneKey, int> tuned_top;
+  std::map<TuneKey, TuneVal> tuned;
   Timer timer;
   std::vector<GraphEntry*> graphs;  // owned; freed by release_graphs
   bool debug_sync = false;
@@ -208,12 +223,16 @@ inline int ilog2(uint64_t v) {
 }
 
 // elem_log: log2 bytes per element (2 for uint32, 3 for complex64).
-// top_levels < 0: default split.
-inline Schedule make_schedule(int L, int elem_log, int top_levels) {
+// top_levels < 0: default split; tile_log_in < 0: default tile (32 KiB of LDS).
+inline Schedule make_schedule(int L, int elem_log, int top_levels, int tile_log_in = -1, int xcd = 1) {
   Schedule s;
   s.L = L;
+  s.xcd = xcd;
   const int block_max = elem_log == 2 ? 12 : 11;  // 32 KiB of LDS for row + vector
-  const int tile_log = elem_log == 2 ? 13 : 12;   // 32 KiB tile in a top pass
+  const int tile_max = 13;                        // 512 threads x 16 elements per workgroup
+  int tile_log = tile_log_in >= 0 ? tile_log_in : (elem_log == 2 ? 13 : 12);
+  if (tile_log > tile_max) tile_log = tile_max;
+  if (tile_log < 4) tile_log = 4;
   const int top_max = 10;
   int T = top_levels >= 0 ? top_levels : (L > block_max ? L - block_max : 0);
   if (T > L) T = L;
@@ -327,12 +346,17 @@ inline hipError_t launch_merge(Ctx& c, const PassArgs<Ring>& A, const typename R
 template <class Ring, class SrcA, class SrcX, class Dst>
 inline hipError_t run_product(Ctx& c, const Schedule& S, uint32_t count, const typename Ring::Params* rp,
                               typename Ring::Tw const* const* tw, typename Ring::Tw const* const* twi,
-                              bool ring_per_inst, SrcA srca, SrcX srcx, Dst dst, typename Ring::T* wy,
-                              typename Ring::T* ws, hipStream_t s) {
+                              const Uniform16<Ring>* const* U, bool ring_per_inst, SrcA srca, SrcX srcx, Dst dst,
+                              typename Ring::T* wy, typename Ring::T* ws, hipStream_t s) {
   using T = typename Ring::T;
   const int L = S.L;
   const uint64_t n = (uint64_t)1 << L;
   PassArgs<Ring> A{};
+  for (int r = 0; r < 3; ++r)
+    for (int i = 0; i < 15; ++i) {
+      A.tu[r][i] = U[r]->tu[i];
+      A.tui[r][i] = U[r]->tui[i];
+    }
   for (int i = 0; i < 3; ++i) {
     A.tw[i] = tw[i];
     A.twi[i] = twi[i];
@@ -340,6 +364,7 @@ inline hipError_t run_product(Ctx& c, const Schedule& S, uint32_t count, const t
   A.logn = L;
   A.ninst = count;
   A.ring_per_inst = ring_per_inst ? 1 : 0;
+  A.xcd = S.xcd;
   hipError_t e;
   if (S.ntop == 0) {
     A.d0 = 0;
@@ -415,6 +440,7 @@ fcirc_status zp_tables(Ctx& c, uint32_t p, uint32_t f, int L, const ZpTables** o
 ZpParams zp_params(uint32_t p, int L);
 fcirc_status c32_tables(Ctx& c, double fre, double fim, int L, hipStream_t s, const C32Tables** out);
 
+
 fcirc_status zp_matvec(Ctx& c, const uint32_t* a, const uint32_t* x, uint32_t* y, int L, uint32_t count, uint32_t p,
                        uint32_t f, hipStream_t s);
 fcirc_status c32_matvec(Ctx& c, const void* a, const void* x, void* y, int L, uint32_t count, double fre, double fim,
@@ -430,10 +456,18 @@ inline fcirc_status hip_status(hipError_t e) {
   return e == hipErrorOutOfMemory ? FCIRC_ENOMEM : FCIRC_EDEVICE;
 }
 
-inline int effective_top(Ctx& c, int ring, int L) {
-  if (c.forced_top >= 0) return c.forced_top;
-  auto it = c.tuned_top.find(TuneKey{ring, L});
-  return it == c.tuned_top.end() ? -1 : it->second;
+// Schedule for (ring, L): a forced split wins, then a tuned entry, then the defaults.
+inline Schedule schedule_for(Ctx& c, int ring, int L) {
+  const int elem_log = ring == FCIRC_C64 || ring == FCIRC_R32 ? 3 : 2;
+  TuneVal v;
+  auto it = c.tuned.find(TuneKey{ring, L});
+  if (it != c.tuned.end()) v = it->second;
+  if (c.forced_top >= 0) v.top = c.forced_top;
+  return make_schedule(L, elem_log, v.top, v.tile_log, v.xcd);
 }
 
 }  // namespace fcirc
+
+struct fcirc_ctx {
+  fcirc::Ctx c;
+};

@@ -19,5 +19,4 @@ fcirc_status fcirc_matvec_backward(fcirc_ctx*, const void*, const void*, const v
                                    fcirc_ring, void*) {
   return FCIRC_EINVAL;
 }
-fcirc_status fcirc_tune(fcirc_ctx*, uint64_t, fcirc_ring, void*) { return FCIRC_EINVAL; }
 }

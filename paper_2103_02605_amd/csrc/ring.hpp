@@ -72,6 +72,28 @@ struct Zp {
     u = shoup(s, gi);
     v = red2(d);
   }
+  // Butterflies whose twiddle is c * u with u from a small uniform table: two Shoup
+  // multiplications (each result in [0, 2p), any 32-bit input), no derived companion.
+  static constexpr bool kCheapDerive = false;
+  __device__ __forceinline__ void split_a2(T& u, T& v, Tw tu, Tw c) const {
+    const uint32_t uu = red2(u);
+    const uint32_t t = shoup(shoup(v, tu), c);
+    u = uu + t;
+    v = uu - t + p2;
+  }
+  __device__ __forceinline__ void split_x2(T& u, T& v, Tw tu, Tw c) const {
+    const uint32_t t = shoup(shoup(u, tu), c);
+    const uint32_t vv = red2(v);
+    u = t + vv;
+    v = t - vv + p2;
+  }
+  __device__ __forceinline__ void merge2(T& u, T& v, Tw tu, Tw c) const {
+    const uint32_t s = u + v;
+    const uint32_t d = u - v + p2;
+    u = shoup(shoup(s, tu), c);
+    v = red2(d);
+  }
+  __device__ __forceinline__ Tw derive(Tw c, Tw) const { return c; }  // unused (kCheapDerive false)
   // a x / n for a, x in [0, 4p); result in [0, 2p)
   __device__ __forceinline__ T leaf(T a, T x) const {
     a = red2(a);
@@ -129,6 +151,12 @@ struct C32 {
     u = cmul(s, gi);
     v = d;
   }
+  // A twiddle c * u is formed once (one complex product) and used as any other twiddle.
+  static constexpr bool kCheapDerive = true;
+  __device__ __forceinline__ Tw derive(Tw c, Tw u) const { return cmul(c, u); }
+  __device__ __forceinline__ void split_a2(T& u, T& v, Tw tu, Tw c) const { split_a(u, v, cmul(c, tu)); }
+  __device__ __forceinline__ void split_x2(T& u, T& v, Tw tu, Tw c) const { split_x(u, v, cmul(c, tu)); }
+  __device__ __forceinline__ void merge2(T& u, T& v, Tw tu, Tw c) const { merge(u, v, cmul(c, tu)); }
   __device__ __forceinline__ T leaf(T a, T x) const {
     const float2 t = cmul(a, x);
     return make_float2(t.x * scale, t.y * scale);

@@ -44,7 +44,22 @@ struct PassArgs {
   uint32_t ninst;                   // instances
   uint32_t ring_per_inst;           // 1: instance z uses ring parameters [z % 3]
   uint32_t final_store;             // 1: canonicalise values on the way out
+  uint32_t xcd;                     // 1: XCD-aware tile order
+  // Uniform factors of the deepest block stage: for the 2^j consecutive nodes of level j
+  // inside one radix-16 item, twiddle g = (twiddle of the first node) * tu[2^j - 1 + g],
+  // tu[2^j - 1 + g] = rho_j^brev_j(g) (a root of unity that does not depend on f, the
+  // block or the item). tui holds the inverses for the merge.
+  typename Ring::Tw tu[3][15];
+  typename Ring::Tw tui[3][15];
 };
+
+// Workgroups are dispatched round-robin over the 8 XCDs (workgroup i runs on XCD i mod 8),
+// and each XCD has its own L2. Remapping gives every XCD a contiguous range of tiles, so
+// neighbouring column tiles, which share cache lines, are fetched through one L2.
+__device__ __forceinline__ uint32_t xcd_remap(uint32_t bid, uint32_t grid) {
+  if ((grid & 7u) != 0) return bid;
+  return (bid & 7u) * (grid >> 3) + (bid >> 3);
+}
 
 struct TilePos {
   uint32_t tile, arr, inst;
@@ -100,6 +115,70 @@ __device__ __forceinline__ void load_tw(typename Ring::Tw* t, typename Ring::Tw 
     const uint32_t ib = tw_index(d0, blk, l0, j, sb);
 #pragma unroll
     for (int g = 0; g < (1 << j); ++g) t[(1 << j) - 1 + g] = tw[ib + g];
+  }
+}
+
+// The first twiddle of each of the K levels of an item (heap index of group 0).
+template <class Ring, int K>
+__device__ __forceinline__ void load_tw_first(typename Ring::Tw* t, typename Ring::Tw const* tw, uint32_t d0, uint32_t blk,
+                                              uint32_t l0, uint32_t sb) {
+#pragma unroll
+  for (int j = 0; j < K; ++j) t[j] = tw[tw_index(d0, blk, l0, j, sb)];
+}
+
+// K split levels from the first twiddle per level and the uniform factors tu.
+template <class Ring, int K>
+__device__ __forceinline__ void split_levels_first(const Ring& R, typename Ring::T* va, typename Ring::T* vx,
+                                                   const typename Ring::Tw* c, const typename Ring::Tw* tu) {
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    const int h = 1 << (K - 1 - j);
+#pragma unroll
+    for (int g = 0; g < (1 << j); ++g) {
+      if (g == 0 || Ring::kCheapDerive) {
+        const typename Ring::Tw t = g == 0 ? c[j] : R.derive(c[j], tu[(1 << j) - 1 + g]);
+#pragma unroll
+        for (int q = 0; q < h; ++q) {
+          const int i = g * 2 * h + q;
+          R.split_a(va[i], va[i + h], t);
+          R.split_x(vx[i], vx[i + h], t);
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < h; ++q) {
+          const int i = g * 2 * h + q;
+          R.split_a2(va[i], va[i + h], tu[(1 << j) - 1 + g], c[j]);
+          R.split_x2(vx[i], vx[i + h], tu[(1 << j) - 1 + g], c[j]);
+        }
+      }
+    }
+  }
+}
+
+// K merge levels (deepest first) from the first twiddle per level and the factors tui.
+template <class Ring, int K>
+__device__ __forceinline__ void merge_levels_first(const Ring& R, typename Ring::T* vy, const typename Ring::Tw* c,
+                                                   const typename Ring::Tw* tui) {
+#pragma unroll
+  for (int j = K - 1; j >= 0; --j) {
+    const int h = 1 << (K - 1 - j);
+#pragma unroll
+    for (int g = 0; g < (1 << j); ++g) {
+      if (g == 0 || Ring::kCheapDerive) {
+        const typename Ring::Tw t = g == 0 ? c[j] : R.derive(c[j], tui[(1 << j) - 1 + g]);
+#pragma unroll
+        for (int q = 0; q < h; ++q) {
+          const int i = g * 2 * h + q;
+          R.merge(vy[i], vy[i + h], t);
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < h; ++q) {
+          const int i = g * 2 * h + q;
+          R.merge2(vy[i], vy[i + h], tui[(1 << j) - 1 + g], c[j]);
+        }
+      }
+    }
   }
 }
 
@@ -219,7 +298,7 @@ __global__ void __launch_bounds__(512) k_split(PassArgs<Ring> A, typename Ring::
   using SP = StagePlan<R>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* lds = reinterpret_cast<T*>(smem_raw);
-  const TilePos P = tile_pos(A, blockIdx.x);
+  const TilePos P = tile_pos(A, A.xcd ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x);
   uint32_t rsel;
   const Ring Rg = make_ring(A, P.inst, rp0, rp1, rp2, &rsel);
   const typename Ring::Tw* tw = A.tw[rsel];
@@ -288,7 +367,7 @@ __global__ void __launch_bounds__(512) k_merge(PassArgs<Ring> A, typename Ring::
   using SP = StagePlan<R>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* lds = reinterpret_cast<T*>(smem_raw);
-  const TilePos P = tile_pos(A, blockIdx.x);
+  const TilePos P = tile_pos(A, A.xcd ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x);
   uint32_t rsel;
   const Ring Rg = make_ring(A, P.inst, rp0, rp1, rp2, &rsel);
   const typename Ring::Tw* twi = A.twi[rsel];
@@ -316,7 +395,7 @@ struct BlockShape {
 };
 
 template <class Ring, int LOGR, int K, bool FIRST, bool DEEPEST, class SrcA, class SrcX, class Dst>
-__device__ __forceinline__ void block_split_stage(const PassArgs<Ring>& A, const TilePos& P, const Ring& R,
+__device__ __forceinline__ void block_split_stage(const PassArgs<Ring>& A, const TilePos& P, const Ring& R, uint32_t rsel,
                                                   typename Ring::Tw const* tw, typename Ring::Tw const* twi,
                                                   typename Ring::T* sa, typename Ring::T* sx, uint32_t l0, uint32_t ltid,
                                                   const SrcA& srca, const SrcX& srcx, const Dst& dst) {
@@ -326,15 +405,22 @@ __device__ __forceinline__ void block_split_stage(const PassArgs<Ring>& A, const
   constexpr int E = 1 << K;
   constexpr int IPT = S::EPT / E;
   constexpr uint32_t ACTIVE = 1u << S::ACTIVE_LOG;
+  // Radix-16 deepest stages load one twiddle per level and derive the rest (see tu).
+  constexpr bool FIRSTS = DEEPEST && K == EPT_LOG;
   T va[IPT][E], vx[IPT][E];
-  Tw t[IPT][E - 1];
-  Tw ti[DEEPEST ? IPT : 1][E - 1];
+  Tw t[IPT][FIRSTS ? K : E - 1];
+  Tw ti[DEEPEST ? IPT : 1][FIRSTS ? K : E - 1];
   Item it[IPT];
 #pragma unroll
   for (int u = 0; u < IPT; ++u) {
     it[u] = item_at(ltid + u * ACTIVE, LOGR, 0, l0, K);
-    load_tw<Ring, K>(t[u], tw, A.d0, P.blk, l0, it[u].sb);
-    if constexpr (DEEPEST) load_tw<Ring, K>(ti[u], twi, A.d0, P.blk, l0, it[u].sb);
+    if constexpr (FIRSTS) {
+      load_tw_first<Ring, K>(t[u], tw, A.d0, P.blk, l0, it[u].sb);
+      load_tw_first<Ring, K>(ti[u], twi, A.d0, P.blk, l0, it[u].sb);
+    } else {
+      load_tw<Ring, K>(t[u], tw, A.d0, P.blk, l0, it[u].sb);
+      if constexpr (DEEPEST) load_tw<Ring, K>(ti[u], twi, A.d0, P.blk, l0, it[u].sb);
+    }
   }
 #pragma unroll
   for (int u = 0; u < IPT; ++u)
@@ -350,14 +436,24 @@ __device__ __forceinline__ void block_split_stage(const PassArgs<Ring>& A, const
       }
     }
 #pragma unroll
-  for (int u = 0; u < IPT; ++u) split_levels<Ring, K, true, true>(R, va[u], vx[u], t[u]);
+  for (int u = 0; u < IPT; ++u) {
+    if constexpr (FIRSTS)
+      split_levels_first<Ring, K>(R, va[u], vx[u], t[u], A.tu[rsel]);
+    else
+      split_levels<Ring, K, true, true>(R, va[u], vx[u], t[u]);
+  }
   if constexpr (DEEPEST) {
 #pragma unroll
     for (int u = 0; u < IPT; ++u)
 #pragma unroll
       for (int i = 0; i < E; ++i) va[u][i] = R.leaf(va[u][i], vx[u][i]);
 #pragma unroll
-    for (int u = 0; u < IPT; ++u) merge_levels<Ring, K>(R, va[u], ti[u]);
+    for (int u = 0; u < IPT; ++u) {
+      if constexpr (FIRSTS)
+        merge_levels_first<Ring, K>(R, va[u], ti[u], A.tui[rsel]);
+      else
+        merge_levels<Ring, K>(R, va[u], ti[u]);
+    }
   }
 #pragma unroll
   for (int u = 0; u < IPT; ++u)
@@ -426,7 +522,7 @@ __global__ void __launch_bounds__(BlockShape<LOGR>::NT) k_block(PassArgs<Ring> A
   } else {
     constexpr int NST = S::NST, K0 = S::K0;
     // split stages (first takes K0 levels), the deepest also runs leaf + its merge levels
-    if (active) block_split_stage<Ring, LOGR, K0, true, NST == 1>(A, P, R, tw, twi, sa, sx, 0, ltid, srca, srcx, dst);
+    if (active) block_split_stage<Ring, LOGR, K0, true, NST == 1>(A, P, R, rsel, tw, twi, sa, sx, 0, ltid, srca, srcx, dst);
     if constexpr (NST > 1) {
       __syncthreads();
 #pragma unroll
@@ -434,9 +530,9 @@ __global__ void __launch_bounds__(BlockShape<LOGR>::NT) k_block(PassArgs<Ring> A
         const uint32_t l0 = K0 + EPT_LOG * (s - 1);
         if (active) {
           if (s + 1 == NST)
-            block_split_stage<Ring, LOGR, EPT_LOG, false, true>(A, P, R, tw, twi, sa, sx, l0, ltid, srca, srcx, dst);
+            block_split_stage<Ring, LOGR, EPT_LOG, false, true>(A, P, R, rsel, tw, twi, sa, sx, l0, ltid, srca, srcx, dst);
           else
-            block_split_stage<Ring, LOGR, EPT_LOG, false, false>(A, P, R, tw, twi, sa, sx, l0, ltid, srca, srcx, dst);
+            block_split_stage<Ring, LOGR, EPT_LOG, false, false>(A, P, R, rsel, tw, twi, sa, sx, l0, ltid, srca, srcx, dst);
         }
         __syncthreads();
       }

@@ -1,0 +1,131 @@
+// Autotuner for the pass schedule of one (ring, n): how many top levels are streamed
+// through HBM before the LDS-resident block pass, how large a top-pass tile is, and
+// whether the top passes use the XCD-aware tile order. Every candidate is timed with HIP
+// events on the caller's stream over scratch buffers; the fastest is kept in the context.
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+#include "host.hpp"
+
+using namespace fcirc;
+
+
+namespace {
+
+fcirc_status run_once(Ctx& c, fcirc_ring ring, int L, void* a, void* x, void* y, hipStream_t s) {
+  if (ring <= FCIRC_ZP_167772161)
+    return zp_matvec(c, (const uint32_t*)a, (const uint32_t*)x, (uint32_t*)y, L, 1, zp_prime(ring), 1u, s);
+  return c32_matvec(c, a, x, y, L, 1, 1.0, 0.0, ring == FCIRC_R32, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+fcirc_status fcirc_set_schedule(fcirc_ctx* ctx, fcirc_ring ring, uint64_t n, int top_levels, int tile_log, int xcd) {
+  if (!ctx || n == 0 || (n & (n - 1)) || ring < FCIRC_ZP_998244353 || ring > FCIRC_R32) return FCIRC_EINVAL;
+  if (top_levels < -1 || top_levels > 26 || tile_log < -1 || tile_log > 13 || xcd < 0 || xcd > 1) return FCIRC_EINVAL;
+  TuneVal v;
+  v.top = top_levels;
+  v.tile_log = tile_log;
+  v.xcd = xcd;
+  ctx->c.tuned[TuneKey{(int)ring, ilog2(n)}] = v;
+  return FCIRC_OK;
+}
+
+fcirc_status fcirc_tune(fcirc_ctx* ctx, uint64_t n, fcirc_ring ring, void* stream) {
+  if (!ctx || n == 0 || (n & (n - 1)) || ring < FCIRC_ZP_998244353 || ring > FCIRC_R32) return FCIRC_EINVAL;
+  Ctx& c = ctx->c;
+  if (hipSetDevice(c.device) != hipSuccess) return FCIRC_EDEVICE;
+  const int L = ilog2(n);
+  if (ring <= FCIRC_ZP_167772161 && L > zp_two_adic(zp_prime(ring))) return FCIRC_ESIZE;
+  if (L > 26) return FCIRC_ESIZE;
+  hipStream_t s = (hipStream_t)stream;
+  const size_t eb = ring == FCIRC_C64 ? 8 : 4;
+  void *a = nullptr, *x = nullptr, *y = nullptr;
+  if (hipMalloc(&a, n * eb) != hipSuccess || hipMalloc(&x, n * eb) != hipSuccess || hipMalloc(&y, n * eb) != hipSuccess) {
+    (void)hipGetLastError();
+    if (a) (void)hipFree(a);
+    if (x) (void)hipFree(x);
+    return FCIRC_ENOMEM;
+  }
+  fcirc_status st = FCIRC_OK;
+  if (hipMemsetAsync(a, 0, n * eb, s) != hipSuccess || hipMemsetAsync(x, 0, n * eb, s) != hipSuccess) st = FCIRC_EDEVICE;
+  const bool zp = ring <= FCIRC_ZP_167772161;
+  const int bmax = zp ? 13 : 12, bmin = 9;
+  std::vector<TuneVal> cands;
+  for (int bl = bmin; bl <= bmax; ++bl) {
+    const int top = L - bl;
+    if (top < 0) continue;
+    if (top == 0) {
+      TuneVal v;
+      v.top = 0;
+      cands.push_back(v);
+      continue;
+    }
+    for (int tl = 10; tl <= 13; ++tl)
+      for (int xc = 0; xc <= 1; ++xc) {
+        TuneVal v;
+        v.top = top;
+        v.tile_log = tl;
+        v.xcd = xc;
+        cands.push_back(v);
+      }
+  }
+  if (cands.empty()) {
+    TuneVal v;
+    v.top = 0;
+    cands.push_back(v);
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (st == FCIRC_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)) st = FCIRC_EDEVICE;
+  const bool timing = c.timer.enabled;
+  c.timer.enabled = false;
+  const int forced = c.forced_top;
+  c.forced_top = -1;
+  const TuneKey key{(int)ring, L};
+  float best = 1e30f;
+  TuneVal bestv = cands[0];
+  const int reps = n >= (1u << 20) ? 10 : 30;
+  for (const TuneVal& v : cands) {
+    if (st != FCIRC_OK) break;
+    c.tuned[key] = v;
+    for (int w = 0; w < 3 && st == FCIRC_OK; ++w) st = run_once(c, ring, L, a, x, y, s);
+    if (st != FCIRC_OK) break;
+    (void)hipEventRecord(e0, s);
+    for (int r = 0; r < reps && st == FCIRC_OK; ++r) st = run_once(c, ring, L, a, x, y, s);
+    (void)hipEventRecord(e1, s);
+    float ms = 0.f;
+    if (st == FCIRC_OK && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+      st = FCIRC_EDEVICE;
+    if (st == FCIRC_OK && ms < best) {
+      best = ms;
+      bestv = v;
+    }
+  }
+  c.tuned[key] = bestv;
+  c.timer.enabled = timing;
+  c.forced_top = forced;
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipStreamSynchronize(s);
+  (void)hipFree(a);
+  (void)hipFree(x);
+  (void)hipFree(y);
+  if (std::getenv("FCIRC_LOG"))
+    std::fprintf(stderr, "fcirc_tune ring=%d L=%d: top=%d tile_log=%d xcd=%d (%.2f us/call)\n", (int)ring, L, bestv.top,
+                 bestv.tile_log, bestv.xcd, 1000.0 * best / reps);
+  return st;
+}
+
+int fcirc_get_schedule(fcirc_ctx* ctx, fcirc_ring ring, uint64_t n, int* top_levels, int* tile_log, int* xcd) {
+  if (!ctx || n == 0 || (n & (n - 1))) return -1;
+  const Schedule S = schedule_for(ctx->c, ring, ilog2(n));
+  if (top_levels) *top_levels = S.L - S.block_levels;
+  if (tile_log) *tile_log = S.ntop ? S.top_r[0] + S.top_c[0] : -1;
+  if (xcd) *xcd = S.xcd;
+  return S.ntop;
+}
+
+}  // extern "C"

@@ -116,6 +116,22 @@ ZpParams zp_params(uint32_t p, int L) {
   return q;
 }
 
+Uniform16<Zp> zp_uniform16(uint32_t p) {
+  // rho_j = gen^((p-1)/2^(j+1)), the same roots the tables are built from
+  const uint32_t gen = generator(p);
+  Uniform16<Zp> U;
+  for (int j = 0; j < 4; ++j) {
+    const uint32_t rho = powmod(gen, (uint64_t)(p - 1) >> (j + 1), p);
+    for (uint32_t g = 0; g < (1u << j); ++g) {
+      const uint32_t e = brev(g, j);
+      const uint32_t w = powmod(rho, e, p), wi = invmod(w, p);
+      U.tu[(1 << j) - 1 + g] = shoup_tw(w, p);
+      U.tui[(1 << j) - 1 + g] = shoup_tw(wi, p);
+    }
+  }
+  return U;
+}
+
 fcirc_status zp_tables(Ctx& c, uint32_t p, uint32_t f, int L, const ZpTables** out) {
   const int e2 = zp_two_adic(p);
   if (L > e2) return FCIRC_ESIZE;
@@ -168,6 +184,7 @@ fcirc_status zp_tables(Ctx& c, uint32_t p, uint32_t f, int L, const ZpTables** o
   t.p = p;
   t.f = f;
   t.levels = levels;
+  t.U = zp_uniform16(p);
   if (hipMalloc(&t.tw, ne * sizeof(ZpTw)) != hipSuccess || hipMalloc(&t.twi, ne * sizeof(ZpTw)) != hipSuccess) {
     (void)hipGetLastError();
     if (t.tw) (void)hipFree(t.tw);
@@ -197,7 +214,7 @@ fcirc_status zp_matvec(Ctx& c, const uint32_t* a, const uint32_t* x, uint32_t* y
   fcirc_status st = zp_tables(c, p, f, L, &T);
   if (st != FCIRC_OK) return st;
   const int ring = p == 998244353u ? 0 : (p == 469762049u ? 1 : 2);
-  const Schedule S = make_schedule(L, 2, effective_top(c, ring, L));
+  const Schedule S = schedule_for(c, ring, L);
   const uint64_t wse = product_ws_elems(S, count, false);
   if (wse) {
     st = ws_reserve(c, wse * sizeof(uint32_t));
@@ -208,8 +225,9 @@ fcirc_status zp_matvec(Ctx& c, const uint32_t* a, const uint32_t* x, uint32_t* y
   const ZpTw* tw[3] = {T->tw, T->tw, T->tw};
   const ZpTw* twi[3] = {T->twi, T->twi, T->twi};
   const uint64_t n = (uint64_t)1 << L;
-  return hip_status(run_product<Zp>(c, S, count, rps, tw, twi, false, LdPlain<uint32_t>{a, n}, LdPlain<uint32_t>{x, n},
-                                    StPlain<uint32_t>{y, n}, y, (uint32_t*)c.ws, s));
+  const Uniform16<Zp>* U[3] = {&T->U, &T->U, &T->U};
+  return hip_status(run_product<Zp>(c, S, count, rps, tw, twi, U, false, LdPlain<uint32_t>{a, n},
+                                    LdPlain<uint32_t>{x, n}, StPlain<uint32_t>{y, n}, y, (uint32_t*)c.ws, s));
 }
 
 }  // namespace fcirc

@@ -172,3 +172,14 @@ def get_split(n: int, ring: int, device=None) -> int:
 def tune(n: int, ring: int, device=None):
     L.check(L.lib().fcirc_tune(context(device).handle, n, ring, C.c_void_p(torch.cuda.current_stream().cuda_stream)),
             "fcirc_tune")
+
+
+def set_schedule(n: int, ring: int, top_levels: int = -1, tile_log: int = -1, xcd: int = 1, device=None):
+    """Fix the pass schedule for (ring, n): see fcirc_set_schedule in include/fcirc.h."""
+    L.check(L.lib().fcirc_set_schedule(context(device).handle, ring, n, top_levels, tile_log, xcd), "fcirc_set_schedule")
+
+
+def get_schedule(n: int, ring: int, device=None) -> dict:
+    top, tile, xcd = C.c_int(), C.c_int(), C.c_int()
+    ntop = L.lib().fcirc_get_schedule(context(device).handle, ring, n, C.byref(top), C.byref(tile), C.byref(xcd))
+    return {"top_passes": ntop, "top_levels": top.value, "tile_log": tile.value, "xcd": xcd.value}

@@ -194,3 +194,29 @@ def test_errors(F):
         F.matvec(a, a.clone(), f=3, p=P1)
     with pytest.raises(FcircError, match="EINVAL"):
         F.matvec(a, a, f=1, p=P1, out=a)  # output aliases the input
+
+
+@pytest.mark.parametrize("L", [14, 18, 21])
+def test_schedule_variants_bit_exact(F, L):
+    """Every top-pass tile size and tile order the tuner may pick gives the same bits."""
+    from paper_2103_02605_amd import _lib
+    n = 1 << L
+    a, x = W.modp_pair(n, P3, seed=L)
+    want = oracle_modp(a, x, 1, P3) if L <= 18 else None
+    ring = _lib.FCIRC_ZP_167772161
+    base = None
+    try:
+        for top in (L - 13, L - 11, L - 9):
+            for tile_log in (10, 11, 12, 13):
+                for xcd in (0, 1):
+                    F.set_schedule(n, ring, top, tile_log, xcd)
+                    got = host_u32(F.matvec(dev(a), dev(x), f=1, p=P3))
+                    if want is not None:
+                        np.testing.assert_array_equal(got, want, err_msg=f"{top} {tile_log} {xcd}")
+                    if base is None:
+                        base = got
+                    np.testing.assert_array_equal(got, base)
+        F.tune(n, ring)
+        np.testing.assert_array_equal(host_u32(F.matvec(dev(a), dev(x), f=1, p=P3)), base)
+    finally:
+        F.set_schedule(n, ring, -1, -1, 1)
