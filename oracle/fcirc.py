@@ -328,6 +328,19 @@ def levels_matvec_c128(a, x, f=1.0):
     return Y
 
 
+def cyclic_matvec_fft_c128(a, x):
+    """The f = 1 product through the discrete Fourier transform, in complex128.
+
+    Section 1.2 recalls that a circulant is diagonalised by the DFT (A = F^-1 diag(F a) F
+    for the usual column convention). For the row convention used here,
+    y_i = sum_k a_k x_((i+k) mod n), which is ifft(conj(fft(conj(a))) * fft(x)). The pins
+    tie this identity to the recursion of Algorithm 1 at several sizes.
+    """
+    a = np.asarray(a, dtype=np.complex128)
+    x = np.asarray(x, dtype=np.complex128)
+    return np.fft.ifft(np.conj(np.fft.fft(np.conj(a))) * np.fft.fft(x))
+
+
 def matvec_modp(a, x, f, p: int):
     """y = A(a, f) x over Z/p: dense definition for small n, else the level form."""
     n = len(a)

@@ -120,10 +120,12 @@ void fcirc_destroy(fcirc_ctx* ctx) {
   for (auto& t : ctx->c.zp) {
     (void)hipFree(t.tw);
     (void)hipFree(t.twi);
+    (void)hipFree(t.dU);
   }
   for (auto& t : ctx->c.c32) {
     (void)hipFree(t.tw);
     (void)hipFree(t.twi);
+    (void)hipFree(t.dU);
   }
   release_graphs(ctx->c);
   if (ctx->c.ws) (void)hipFree(ctx->c.ws);

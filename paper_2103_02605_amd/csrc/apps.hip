@@ -236,7 +236,7 @@ fcirc_status three_prime_products(Ctx& c, const V* a, uint64_t na, const V* b, u
   ZpParams rp[3];
   const ZpTw* tw[3];
   const ZpTw* twi[3];
-  const Uniform16<Zp>* U[3];
+  const ZpTw* U[3];
   for (int i = 0; i < 3; ++i) {
     const ZpTables* T = nullptr;
     fcirc_status st = zp_tables(c, ps[i], 1u, L, &T);
@@ -244,7 +244,7 @@ fcirc_status three_prime_products(Ctx& c, const V* a, uint64_t na, const V* b, u
     rp[i] = zp_params(ps[i], L);
     tw[i] = T->tw;
     twi[i] = T->twi;
-    U[i] = &T->U;
+    U[i] = T->dU;
   }
   const uint64_t N = (uint64_t)1 << L;
   const Schedule S = schedule_for(c, FCIRC_ZP_998244353, L);

@@ -1,0 +1,468 @@
+// Many independent f-circulant products of different power-of-two sizes in one persistent
+// launch (the recursion of Algorithm 1, Rosowski arXiv 2103.02605, section 2, applied to each
+// instance), captured in a HIP graph and replayed for a repeated batch.
+//
+// Work items, issued from one queue in this order:
+//   SPLIT  one top-split tile (row or vector) of a large instance (2^13 .. 2^16)
+//   FULL   a group of small instances of one size (2^0 .. 2^12), each a whole product
+//          (split, leaf products, merge) by one group of threads of the workgroup
+//   BLOCK  one LDS-resident block of a large instance (waits for all of its SPLIT tiles)
+//   MERGE  one top-merge tile of a large instance (waits for all of its BLOCKs)
+// Large instances are ordered largest first. Every item waits only for items that sit
+// earlier in the queue, which some running workgroup has already taken, so waits end;
+// each wait is also bounded and reports an error instead of spinning forever.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "host.hpp"
+
+namespace fcirc {
+
+namespace {
+
+constexpr int BT = 256;        // threads per persistent workgroup
+constexpr int BLOCK_LOG = 12;  // block pass size of large instances (256 threads x 16)
+constexpr int TILE_LOG = 12;   // top-pass tile of large instances
+constexpr int FULL_MAX = 12;   // largest instance done as one FULL item
+constexpr uint32_t SPIN_LIMIT = 1u << 24;
+
+enum : uint32_t { IT_SPLIT = 0, IT_FULL = 1, IT_BLOCK = 2, IT_MERGE = 3 };
+
+struct BItem {
+  uint32_t type, L;
+  uint32_t inst;  // FULL: first instance; else: instance
+  uint32_t arg;   // FULL: instance count; SPLIT/MERGE: virtual workgroup; BLOCK: block
+};
+
+struct BInst {
+  uint64_t a, x, y;  // element offsets into a_base, x_base, y_base
+  uint64_t ws;       // element offset of this instance's workspace (large instances)
+  uint32_t L, big;   // log2 size; index among large instances (or ~0)
+};
+
+template <class Ring>
+struct BatchArgs {
+  const typename Ring::T* a;
+  const typename Ring::T* x;
+  typename Ring::T* y;
+  typename Ring::T* ws;
+  const BItem* items;
+  const BInst* insts;
+  uint32_t nitems;
+  uint32_t* head;        // queue head
+  uint32_t* cnt;         // per large instance: [2j] SPLIT tiles done, [2j+1] BLOCKs done
+  uint32_t* status;      // sticky error bits
+  typename Ring::Tw const* tw;
+  typename Ring::Tw const* twi;
+  typename Ring::Params rp[17];  // per log2 size (the leaf scale depends on n)
+  typename Ring::Tw const* U;    // uniform radix-16 factors: tu[15] then tui[15]
+};
+
+// Element access for one instance (uniform per workgroup).
+template <class T>
+struct LdInst {
+  const T* base;
+  const BInst* insts;
+  int which;  // 0: a, 1: x
+  template <class R>
+  __device__ __forceinline__ T operator()(const R&, uint32_t inst, uint32_t i) const {
+    const BInst& b = insts[inst];
+    return base[(which == 0 ? b.a : b.x) + i];
+  }
+};
+template <class T>
+struct StInstY {
+  T* base;
+  const BInst* insts;
+  __device__ __forceinline__ void operator()(uint32_t inst, uint32_t i, T v) const { base[insts[inst].y + i] = v; }
+};
+template <class T>
+struct LdInstY {
+  const T* base;
+  const BInst* insts;
+  template <class R>
+  __device__ __forceinline__ T operator()(const R&, uint32_t inst, uint32_t i) const {
+    return base[insts[inst].y + i];
+  }
+};
+// Workspace of a large instance: row at [ws, ws + n), vector at [ws + n, ws + 2n).
+template <class T>
+struct WsInst {
+  T* ws;
+  const BInst* insts;
+  int which;
+  template <class R>
+  __device__ __forceinline__ T operator()(const R&, uint32_t inst, uint32_t i) const {
+    const BInst& b = insts[inst];
+    return ws[b.ws + ((uint64_t)which << b.L) + i];
+  }
+  __device__ __forceinline__ void operator()(uint32_t inst, uint32_t i, T v) const {
+    const BInst& b = insts[inst];
+    ws[b.ws + ((uint64_t)which << b.L) + i] = v;
+  }
+};
+
+__device__ __forceinline__ void wait_count(uint32_t* c, uint32_t target, uint32_t* status) {
+  if (threadIdx.x == 0) {
+    uint32_t spins = 0;
+    while (__hip_atomic_load(c, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      __builtin_amdgcn_s_sleep(2);
+      if (++spins > SPIN_LIMIT) {
+        atomicOr(status, 2u);
+        break;
+      }
+    }
+  }
+  __syncthreads();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
+__device__ __forceinline__ void signal_done(uint32_t* c) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __syncthreads();
+  if (threadIdx.x == 0) __hip_atomic_fetch_add(c, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <class Ring>
+__device__ __forceinline__ PassArgs<Ring> batch_pass_args(const BatchArgs<Ring>& B) {
+  PassArgs<Ring> A{};
+  for (int r = 0; r < 3; ++r) {
+    A.tw[r] = B.tw;
+    A.twi[r] = B.twi;
+    A.tu[r] = B.U;
+    A.tui[r] = B.U + 15;
+  }
+  A.narr = 1;
+  A.ring_per_inst = 0;
+  A.xcd = 0;
+  return A;
+}
+
+template <class Ring, int L>
+__device__ __forceinline__ void do_full(const BatchArgs<Ring>& B, const BItem& it, unsigned char* smem) {
+  PassArgs<Ring> A = batch_pass_args(B);
+  A.logn = L;
+  A.d0 = 0;
+  A.logr = L;
+  A.logc = 0;
+  A.tiles = 1;
+  A.ninst = it.inst + it.arg;
+  A.final_store = 1;
+  const typename Ring::Params& rp = B.rp[L];
+  block_pass<Ring, L, BT>(A, it.inst, smem, rp, rp, rp, LdInst<typename Ring::T>{B.a, B.insts, 0},
+                          LdInst<typename Ring::T>{B.x, B.insts, 1}, StInstY<typename Ring::T>{B.y, B.insts});
+}
+
+template <class Ring, int R>
+__device__ __forceinline__ void do_split(const BatchArgs<Ring>& B, const BItem& it, unsigned char* smem) {
+  const uint32_t L = it.L;
+  PassArgs<Ring> A = batch_pass_args(B);
+  A.logn = L;
+  A.d0 = 0;
+  A.logr = R;
+  A.logc = TILE_LOG - R;
+  A.tiles = 1u << (L - TILE_LOG);
+  A.narr = 2;
+  A.ninst = 1;
+  A.final_store = 0;
+  TilePos P = tile_pos(A, it.arg);
+  P.inst = it.inst;
+  const Ring Rg(B.rp[L]);
+  using T = typename Ring::T;
+  split_pass<Ring, R>(A, P, Rg, 0, BT, reinterpret_cast<T*>(smem), LdInst<T>{B.a, B.insts, 0}, LdInst<T>{B.x, B.insts, 1},
+                      WsInst<T>{B.ws, B.insts, 0}, WsInst<T>{B.ws, B.insts, 1});
+}
+
+template <class Ring, int R>
+__device__ __forceinline__ void do_merge(const BatchArgs<Ring>& B, const BItem& it, unsigned char* smem) {
+  const uint32_t L = it.L;
+  PassArgs<Ring> A = batch_pass_args(B);
+  A.logn = L;
+  A.d0 = 0;
+  A.logr = R;
+  A.logc = TILE_LOG - R;
+  A.tiles = 1u << (L - TILE_LOG);
+  A.ninst = 1;
+  A.final_store = 1;
+  TilePos P = tile_pos(A, it.arg);
+  P.inst = it.inst;
+  const Ring Rg(B.rp[L]);
+  using T = typename Ring::T;
+  merge_pass<Ring, R>(A, P, Rg, 0, BT, reinterpret_cast<T*>(smem), LdInstY<T>{B.y, B.insts}, StInstY<T>{B.y, B.insts});
+}
+
+template <class Ring>
+__device__ __forceinline__ void do_block(const BatchArgs<Ring>& B, const BItem& it, unsigned char* smem) {
+  const uint32_t L = it.L;
+  PassArgs<Ring> A = batch_pass_args(B);
+  A.logn = L;
+  A.d0 = L - BLOCK_LOG;
+  A.logr = BLOCK_LOG;
+  A.logc = 0;
+  A.tiles = 1u << A.d0;
+  A.ninst = it.inst + 1;
+  A.final_store = 0;
+  using T = typename Ring::T;
+  const typename Ring::Params& rp = B.rp[L];
+  // virtual workgroup (block it.arg of instance it.inst) = inst * tiles + block
+  block_pass<Ring, BLOCK_LOG, BT>(A, it.inst * A.tiles + it.arg, smem, rp, rp, rp, WsInst<T>{B.ws, B.insts, 0},
+                                  WsInst<T>{B.ws, B.insts, 1}, StInstY<T>{B.y, B.insts});
+}
+
+template <class Ring>
+__global__ void __launch_bounds__(BT) k_batched(BatchArgs<Ring> B) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ uint32_t s_item;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = atomicAdd(B.head, 1u);
+    __syncthreads();
+    const uint32_t id = s_item;
+    __syncthreads();
+    if (id >= B.nitems) break;
+    const BItem it = B.items[id];
+    if (it.type == IT_FULL) {
+      switch (it.L) {
+#define FCIRC_FULL(l) \
+  case l: do_full<Ring, l>(B, it, smem); break;
+        FCIRC_FULL(0) FCIRC_FULL(1) FCIRC_FULL(2) FCIRC_FULL(3) FCIRC_FULL(4) FCIRC_FULL(5) FCIRC_FULL(6)
+        FCIRC_FULL(7) FCIRC_FULL(8) FCIRC_FULL(9) FCIRC_FULL(10) FCIRC_FULL(11) FCIRC_FULL(12)
+#undef FCIRC_FULL
+        default: break;
+      }
+    } else if (it.type == IT_SPLIT) {
+      switch (it.L - BLOCK_LOG) {
+        case 1: do_split<Ring, 1>(B, it, smem); break;
+        case 2: do_split<Ring, 2>(B, it, smem); break;
+        case 3: do_split<Ring, 3>(B, it, smem); break;
+        case 4: do_split<Ring, 4>(B, it, smem); break;
+        default: break;
+      }
+      signal_done(&B.cnt[2 * B.insts[it.inst].big]);
+    } else if (it.type == IT_BLOCK) {
+      const uint32_t tiles = 1u << (it.L - TILE_LOG);
+      wait_count(&B.cnt[2 * B.insts[it.inst].big], 2 * tiles, B.status);
+      do_block<Ring>(B, it, smem);
+      signal_done(&B.cnt[2 * B.insts[it.inst].big + 1]);
+    } else {
+      wait_count(&B.cnt[2 * B.insts[it.inst].big + 1], 1u << (it.L - BLOCK_LOG), B.status);
+      switch (it.L - BLOCK_LOG) {
+        case 1: do_merge<Ring, 1>(B, it, smem); break;
+        case 2: do_merge<Ring, 2>(B, it, smem); break;
+        case 3: do_merge<Ring, 3>(B, it, smem); break;
+        case 4: do_merge<Ring, 4>(B, it, smem); break;
+        default: break;
+      }
+    }
+    __syncthreads();  // LDS is reused by the next item
+  }
+}
+
+__global__ void k_zero(uint32_t* p, uint32_t n) {
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
+}
+
+}  // namespace
+
+// A captured batch: device copies of the work list, counters, workspace and the graph.
+struct GraphEntry {
+  std::vector<uint64_t> key;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  void* dev = nullptr;  // items | insts | counters
+  void* ws = nullptr;
+  ~GraphEntry() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (dev) (void)hipFree(dev);
+    if (ws) (void)hipFree(ws);
+  }
+};
+
+void release_graphs(Ctx& c) {
+  for (GraphEntry* g : c.graphs) delete g;
+  c.graphs.clear();
+}
+
+namespace {
+
+template <class Ring>
+fcirc_status build_and_launch(Ctx& c, const std::vector<uint64_t>& key, const void* a_base, const void* x_base,
+                              void* y_base, const fcirc_item* items, uint32_t count, typename Ring::Tw const* tw,
+                              typename Ring::Tw const* twi, typename Ring::Tw const* U,
+                              const typename Ring::Params* rp_by_L, hipStream_t s) {
+  using T = typename Ring::T;
+  for (GraphEntry* g : c.graphs)
+    if (g->key == key) return hip_status(hipGraphLaunch(g->exec, s));
+
+  // instances sorted by size, largest first
+  std::vector<uint32_t> order(count);
+  for (uint32_t i = 0; i < count; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](uint32_t p, uint32_t q) { return items[p].log2n > items[q].log2n; });
+  std::vector<BInst> insts(count);
+  uint64_t ws_elems = 0;
+  uint32_t nbig = 0;
+  for (uint32_t k = 0; k < count; ++k) {
+    const fcirc_item& it = items[order[k]];
+    BInst b{it.a_off, it.x_off, it.y_off, 0, it.log2n, ~0u};
+    if (it.log2n > (uint32_t)FULL_MAX) {
+      b.ws = ws_elems;
+      ws_elems += 2ull << it.log2n;
+      b.big = nbig++;
+    }
+    insts[k] = b;
+  }
+  std::vector<BItem> q;
+  // SPLIT tiles of the large instances (row and vector of each), largest first
+  for (uint32_t k = 0; k < count; ++k)
+    if (insts[k].big != ~0u) {
+      const uint32_t tiles = 1u << (insts[k].L - TILE_LOG);
+      for (uint32_t v = 0; v < 2 * tiles; ++v) q.push_back(BItem{IT_SPLIT, insts[k].L, k, v});
+    }
+  // FULL items: consecutive instances of equal size, as many as one workgroup holds
+  std::vector<BItem> full;
+  for (uint32_t k = 0; k < count;) {
+    if (insts[k].big != ~0u) {
+      ++k;
+      continue;
+    }
+    const uint32_t L = insts[k].L;
+    const uint32_t per = L > 4 ? (uint32_t)BT >> (L - 4) : (uint32_t)BT;
+    uint32_t m = 0;
+    while (k + m < count && insts[k + m].L == L && m < per) ++m;
+    full.push_back(BItem{IT_FULL, L, k, m});
+    k += m;
+  }
+  const size_t half = full.size() / 2;
+  q.insert(q.end(), full.begin(), full.begin() + half);
+  for (uint32_t k = 0; k < count; ++k)
+    if (insts[k].big != ~0u)
+      for (uint32_t b = 0; b < (1u << (insts[k].L - BLOCK_LOG)); ++b) q.push_back(BItem{IT_BLOCK, insts[k].L, k, b});
+  q.insert(q.end(), full.begin() + half, full.end());
+  for (uint32_t k = 0; k < count; ++k)
+    if (insts[k].big != ~0u)
+      for (uint32_t v = 0; v < (1u << (insts[k].L - TILE_LOG)); ++v) q.push_back(BItem{IT_MERGE, insts[k].L, k, v});
+
+  GraphEntry* g = new GraphEntry;
+  g->key = key;
+  const size_t items_b = q.size() * sizeof(BItem), insts_b = insts.size() * sizeof(BInst);
+  const uint32_t ncnt = 1 + 2 * nbig;  // head + counters
+  const size_t off_insts = (items_b + 255) & ~(size_t)255, off_cnt = (off_insts + insts_b + 255) & ~(size_t)255;
+  if (hipMalloc(&g->dev, off_cnt + ncnt * sizeof(uint32_t)) != hipSuccess ||
+      (ws_elems && hipMalloc(&g->ws, ws_elems * sizeof(T)) != hipSuccess)) {
+    (void)hipGetLastError();
+    delete g;
+    return FCIRC_ENOMEM;
+  }
+  char* dev = (char*)g->dev;
+  if (hipMemcpy(dev, q.data(), items_b, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(dev + off_insts, insts.data(), insts_b, hipMemcpyHostToDevice) != hipSuccess) {
+    delete g;
+    return FCIRC_EDEVICE;
+  }
+  BatchArgs<Ring> B{};
+  B.a = (const T*)a_base;
+  B.x = (const T*)x_base;
+  B.y = (T*)y_base;
+  B.ws = (T*)g->ws;
+  B.items = (const BItem*)dev;
+  B.insts = (const BInst*)(dev + off_insts);
+  B.nitems = (uint32_t)q.size();
+  B.head = (uint32_t*)(dev + off_cnt);
+  B.cnt = B.head + 1;
+  B.status = c.d_status;
+  B.tw = tw;
+  B.twi = twi;
+  for (int L = 0; L <= 16; ++L) B.rp[L] = rp_by_L[L];
+  B.U = U;
+  const size_t lds = 2 * ((size_t)1 << BLOCK_LOG) * sizeof(T);
+  auto kb = k_batched<Ring>;
+  allow_lds(kb, lds);
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)kb, BT, lds) != hipSuccess || per_cu < 1)
+    per_cu = 1;
+  const uint32_t grid = (uint32_t)std::min<size_t>((size_t)per_cu * c.prop.multiProcessorCount, q.size());
+
+  hipStream_t cap = nullptr;
+  if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) {
+    delete g;
+    return FCIRC_EDEVICE;
+  }
+  hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_zero, dim3(1), dim3(256), 0, cap, B.head, ncnt);
+    hipLaunchKernelGGL(kb, dim3(grid), dim3(BT), lds, cap, B);
+    e = hipStreamEndCapture(cap, &g->graph);
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+  (void)hipStreamDestroy(cap);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    delete g;
+    return FCIRC_EDEVICE;
+  }
+  c.graphs.push_back(g);
+  return hip_status(launch(c, "fcirc_batched", s, [&] { (void)hipGraphLaunch(g->exec, s); }));
+}
+
+}  // namespace
+
+}  // namespace fcirc
+
+using namespace fcirc;
+
+extern "C" fcirc_status fcirc_matvec_batched(fcirc_ctx* ctx, const void* a_base, const void* x_base, void* y_base,
+                                             const fcirc_item* items, uint32_t count, const void* f, fcirc_ring ring,
+                                             void* stream) {
+  if (!ctx || !a_base || !x_base || !y_base || !items || !f) return FCIRC_EINVAL;
+  if (ring == FCIRC_R32 || ring < FCIRC_ZP_998244353 || ring > FCIRC_R32) return FCIRC_EINVAL;
+  if (count == 0) return FCIRC_OK;
+  uint32_t maxL = 0;
+  for (uint32_t i = 0; i < count; ++i) {
+    if (items[i].reserved != 0 || items[i].log2n > 16) return items[i].log2n > 16 ? FCIRC_ESIZE : FCIRC_EINVAL;
+    maxL = std::max(maxL, items[i].log2n);
+  }
+  Ctx& c = ctx->c;
+  if (hipSetDevice(c.device) != hipSuccess) return FCIRC_EDEVICE;
+  hipStream_t s = (hipStream_t)stream;
+  // key: ring, f, base pointers and the whole item list
+  std::vector<uint64_t> key;
+  key.reserve(8 + 4 * (size_t)count);
+  key.push_back((uint64_t)ring);
+  if (ring == FCIRC_C64) {
+    uint64_t w[2];
+    std::memcpy(w, f, 16);
+    key.push_back(w[0]);
+    key.push_back(w[1]);
+  } else {
+    key.push_back(*(const uint32_t*)f);
+  }
+  key.push_back((uint64_t)(uintptr_t)a_base);
+  key.push_back((uint64_t)(uintptr_t)x_base);
+  key.push_back((uint64_t)(uintptr_t)y_base);
+  for (uint32_t i = 0; i < count; ++i) {
+    key.push_back(items[i].a_off);
+    key.push_back(items[i].x_off);
+    key.push_back(items[i].y_off);
+    key.push_back(items[i].log2n);
+  }
+  if (ring == FCIRC_C64) {
+    const double* fc = (const double*)f;
+    const C32Tables* T = nullptr;
+    fcirc_status st = c32_tables(c, fc[0], fc[1], (int)std::max<uint32_t>(maxL, 1), s, &T);
+    if (st != FCIRC_OK) return st;
+    C32Params rp[17];
+    for (int L = 0; L <= 16; ++L) rp[L] = C32Params{(float)std::ldexp(1.0, -L)};
+    return build_and_launch<C32>(c, key, a_base, x_base, y_base, items, count, T->tw, T->twi, T->dU, rp, s);
+  }
+  const uint32_t p = zp_prime(ring), fv = *(const uint32_t*)f;
+  if (fv >= p) return FCIRC_EINVAL;
+  const ZpTables* T = nullptr;
+  fcirc_status st = zp_tables(c, p, fv, (int)std::max<uint32_t>(maxL, 1), &T);
+  if (st != FCIRC_OK) return st;
+  ZpParams rp[17];
+  for (int L = 0; L <= 16; ++L) rp[L] = zp_params(p, L);
+  return build_and_launch<Zp>(c, key, a_base, x_base, y_base, items, count, T->tw, T->twi, T->dU, rp, s);
+}

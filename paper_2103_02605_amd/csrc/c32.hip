@@ -74,11 +74,16 @@ fcirc_status c32_tables(Ctx& c, double fre, double fim, int L, hipStream_t s, co
   const uint32_t threads = 256, blocks = (uint32_t)((ne + threads - 1) / threads);
   hipLaunchKernelGGL(k_c32_tables, dim3(blocks), dim3(threads), 0, s, t.tw, t.twi, (uint32_t)ne, lnabs, arg_over_pi);
   if (hipGetLastError() != hipSuccess) return FCIRC_EDEVICE;
+  if (hipMalloc(&t.dU, 30 * sizeof(float2)) != hipSuccess ||
+      hipMemcpy(t.dU, t.U.tu, 15 * sizeof(float2), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(t.dU + 15, t.U.tui, 15 * sizeof(float2), hipMemcpyHostToDevice) != hipSuccess)
+    return FCIRC_ENOMEM;
   for (auto& old : c.c32)
     if (old.fre == fre && old.fim == fim) {
       if (hipDeviceSynchronize() != hipSuccess) return FCIRC_EDEVICE;
       (void)hipFree(old.tw);
       (void)hipFree(old.twi);
+      (void)hipFree(old.dU);
       old = t;
       *out = &old;
       return FCIRC_OK;
@@ -105,7 +110,7 @@ fcirc_status c32_matvec(Ctx& c, const void* a, const void* x, void* y, int L, ui
   const float2* twi[3] = {T->twi, T->twi, T->twi};
   const uint64_t n = (uint64_t)1 << L;
   float2* ws = (float2*)c.ws;
-  const Uniform16<C32>* U[3] = {&T->U, &T->U, &T->U};
+  const float2* U[3] = {T->dU, T->dU, T->dU};
   hipError_t e;
   if (real_io) {
     e = run_product<C32>(c, S, count, rps, tw, twi, U, false, LdR32{(const float*)a, n}, LdR32{(const float*)x, n},

@@ -88,6 +88,7 @@ struct ZpTables {
   ZpTw* tw = nullptr;
   ZpTw* twi = nullptr;
   Uniform16<Zp> U;
+  ZpTw* dU = nullptr;  // device copy: tu[15] then tui[15]
 };
 
 struct C32Tables {
@@ -96,6 +97,7 @@ struct C32Tables {
   float2* tw = nullptr;
   float2* twi = nullptr;
   Uniform16<C32> U;
+  float2* dU = nullptr;  // device copy: tu[15] then tui[15]
 };
 
 // ----------------------------------------------------------------------------------------
@@ -346,17 +348,16 @@ inline hipError_t launch_merge(Ctx& c, const PassArgs<Ring>& A, const typename R
 template <class Ring, class SrcA, class SrcX, class Dst>
 inline hipError_t run_product(Ctx& c, const Schedule& S, uint32_t count, const typename Ring::Params* rp,
                               typename Ring::Tw const* const* tw, typename Ring::Tw const* const* twi,
-                              const Uniform16<Ring>* const* U, bool ring_per_inst, SrcA srca, SrcX srcx, Dst dst,
+                              typename Ring::Tw const* const* U, bool ring_per_inst, SrcA srca, SrcX srcx, Dst dst,
                               typename Ring::T* wy, typename Ring::T* ws, hipStream_t s) {
   using T = typename Ring::T;
   const int L = S.L;
   const uint64_t n = (uint64_t)1 << L;
   PassArgs<Ring> A{};
-  for (int r = 0; r < 3; ++r)
-    for (int i = 0; i < 15; ++i) {
-      A.tu[r][i] = U[r]->tu[i];
-      A.tui[r][i] = U[r]->tui[i];
-    }
+  for (int r = 0; r < 3; ++r) {
+    A.tu[r] = U[r];
+    A.tui[r] = U[r] + 15;
+  }
   for (int i = 0; i < 3; ++i) {
     A.tw[i] = tw[i];
     A.twi[i] = twi[i];

@@ -4,14 +4,9 @@
 #include "host.hpp"
 
 namespace fcirc {
-void release_graphs(Ctx&) {}
 }  // namespace fcirc
 
 extern "C" {
-fcirc_status fcirc_matvec_batched(fcirc_ctx*, const void*, const void*, void*, const fcirc_item*, uint32_t, const void*,
-                                  fcirc_ring, void*) {
-  return FCIRC_EINVAL;
-}
 fcirc_status fcirc_matvec_fwd_shared(fcirc_ctx*, const void*, const void*, void*, uint64_t, uint32_t, fcirc_ring, void*) {
   return FCIRC_EINVAL;
 }

@@ -49,8 +49,8 @@ struct PassArgs {
   // inside one radix-16 item, twiddle g = (twiddle of the first node) * tu[2^j - 1 + g],
   // tu[2^j - 1 + g] = rho_j^brev_j(g) (a root of unity that does not depend on f, the
   // block or the item). tui holds the inverses for the merge.
-  typename Ring::Tw tu[3][15];
-  typename Ring::Tw tui[3][15];
+  typename Ring::Tw const* tu[3];   // 15 entries each, in device memory
+  typename Ring::Tw const* tui[3];
 };
 
 // Workgroups are dispatched round-robin over the 8 XCDs (workgroup i runs on XCD i mod 8),
@@ -233,7 +233,7 @@ __device__ __forceinline__ Ring make_ring(const PassArgs<Ring>& A, uint32_t inst
 template <class Ring, int K, bool FIRST, bool LAST, bool IS_X, class Src, class Dst>
 __device__ __forceinline__ void split_stage(const PassArgs<Ring>& A, const TilePos& P, const Ring& R,
                                             typename Ring::Tw const* tw, typename Ring::T* lds, uint32_t l0,
-                                            const Src& src, const Dst& dst) {
+                                            uint32_t nt, const Src& src, const Dst& dst) {
   using T = typename Ring::T;
   using Tw = typename Ring::Tw;
   constexpr int IPT = 1 << (EPT_LOG - K);
@@ -243,7 +243,7 @@ __device__ __forceinline__ void split_stage(const PassArgs<Ring>& A, const TileP
   Item it[IPT];
 #pragma unroll
   for (int u = 0; u < IPT; ++u) {
-    it[u] = item_at(threadIdx.x + u * blockDim.x, A.logr, A.logc, l0, K);
+    it[u] = item_at(threadIdx.x + u * nt, A.logr, A.logc, l0, K);
     load_tw<Ring, K>(t[u], tw, A.d0, P.blk, l0, it[u].sb);
   }
 #pragma unroll
@@ -288,29 +288,34 @@ __device__ __forceinline__ void static_for(F&& f) {
 }
 
 // ---------------------------------------------------------------------------------------
-// Split pass: levels [d0, d0 + R) of the row (arr 0) or the vector (arr 1), src -> dst.
-// blockDim.x = tile elements / 16 (at most 512).
+// Split pass: levels [d0, d0 + R) of the row (arr 0) or the vector (arr 1), src -> dst, by
+// nt = tile elements / 16 threads (threads 0 .. nt-1 of the workgroup).
 // ---------------------------------------------------------------------------------------
 template <class Ring, int R, class SrcA, class SrcX, class Dst>
-__global__ void __launch_bounds__(512) k_split(PassArgs<Ring> A, typename Ring::Params rp0, typename Ring::Params rp1,
-                                               typename Ring::Params rp2, SrcA srca, SrcX srcx, Dst dsta, Dst dstx) {
-  using T = typename Ring::T;
+__device__ __forceinline__ void split_pass(const PassArgs<Ring>& A, const TilePos& P, const Ring& Rg, uint32_t rsel,
+                                           uint32_t nt, typename Ring::T* lds, const SrcA& srca, const SrcX& srcx,
+                                           const Dst& dsta, const Dst& dstx) {
   using SP = StagePlan<R>;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* lds = reinterpret_cast<T*>(smem_raw);
-  const TilePos P = tile_pos(A, A.xcd ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x);
-  uint32_t rsel;
-  const Ring Rg = make_ring(A, P.inst, rp0, rp1, rp2, &rsel);
   const typename Ring::Tw* tw = A.tw[rsel];
   static_for<SP::NST>([&](auto sc) {
     constexpr int s = decltype(sc)::value;
     constexpr bool first = s == 0, last = s + 1 == SP::NST;
     if (P.arr == 0)
-      split_stage<Ring, SP::k(s), first, last, false>(A, P, Rg, tw, lds, SP::l0(s), srca, dsta);
+      split_stage<Ring, SP::k(s), first, last, false>(A, P, Rg, tw, lds, SP::l0(s), nt, srca, dsta);
     else
-      split_stage<Ring, SP::k(s), first, last, true>(A, P, Rg, tw, lds, SP::l0(s), srcx, dstx);
+      split_stage<Ring, SP::k(s), first, last, true>(A, P, Rg, tw, lds, SP::l0(s), nt, srcx, dstx);
     if constexpr (!last) __syncthreads();
   });
+}
+
+template <class Ring, int R, class SrcA, class SrcX, class Dst>
+__global__ void __launch_bounds__(512) k_split(PassArgs<Ring> A, typename Ring::Params rp0, typename Ring::Params rp1,
+                                               typename Ring::Params rp2, SrcA srca, SrcX srcx, Dst dsta, Dst dstx) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const TilePos P = tile_pos(A, A.xcd ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x);
+  uint32_t rsel;
+  const Ring Rg = make_ring(A, P.inst, rp0, rp1, rp2, &rsel);
+  split_pass<Ring, R>(A, P, Rg, rsel, blockDim.x, reinterpret_cast<typename Ring::T*>(smem_raw), srca, srcx, dsta, dstx);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -319,7 +324,7 @@ __global__ void __launch_bounds__(512) k_split(PassArgs<Ring> A, typename Ring::
 template <class Ring, int K, bool FIRST, bool LAST, class Src, class Dst>
 __device__ __forceinline__ void merge_stage(const PassArgs<Ring>& A, const TilePos& P, const Ring& R,
                                             typename Ring::Tw const* twi, typename Ring::T* lds, uint32_t l0,
-                                            const Src& src, const Dst& dst) {
+                                            uint32_t nt, const Src& src, const Dst& dst) {
   using T = typename Ring::T;
   using Tw = typename Ring::Tw;
   constexpr int IPT = 1 << (EPT_LOG - K);
@@ -329,7 +334,7 @@ __device__ __forceinline__ void merge_stage(const PassArgs<Ring>& A, const TileP
   Item it[IPT];
 #pragma unroll
   for (int u = 0; u < IPT; ++u) {
-    it[u] = item_at(threadIdx.x + u * blockDim.x, A.logr, A.logc, l0, K);
+    it[u] = item_at(threadIdx.x + u * nt, A.logr, A.logc, l0, K);
     load_tw<Ring, K>(t[u], twi, A.d0, P.blk, l0, it[u].sb);
   }
 #pragma unroll
@@ -361,22 +366,26 @@ __device__ __forceinline__ void merge_stage(const PassArgs<Ring>& A, const TileP
 // workgroup reads its whole tile before it writes any of it).
 // ---------------------------------------------------------------------------------------
 template <class Ring, int R, class Src, class Dst>
-__global__ void __launch_bounds__(512) k_merge(PassArgs<Ring> A, typename Ring::Params rp0, typename Ring::Params rp1,
-                                               typename Ring::Params rp2, Src src, Dst dst) {
-  using T = typename Ring::T;
+__device__ __forceinline__ void merge_pass(const PassArgs<Ring>& A, const TilePos& P, const Ring& Rg, uint32_t rsel,
+                                           uint32_t nt, typename Ring::T* lds, const Src& src, const Dst& dst) {
   using SP = StagePlan<R>;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* lds = reinterpret_cast<T*>(smem_raw);
-  const TilePos P = tile_pos(A, A.xcd ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x);
-  uint32_t rsel;
-  const Ring Rg = make_ring(A, P.inst, rp0, rp1, rp2, &rsel);
   const typename Ring::Tw* twi = A.twi[rsel];
   static_for<SP::NST>([&](auto sc) {
     constexpr int s = SP::NST - 1 - decltype(sc)::value;  // deepest stage first
     constexpr bool first = s + 1 == SP::NST, last = s == 0;
-    merge_stage<Ring, SP::k(s), first, last>(A, P, Rg, twi, lds, SP::l0(s), src, dst);
+    merge_stage<Ring, SP::k(s), first, last>(A, P, Rg, twi, lds, SP::l0(s), nt, src, dst);
     if constexpr (!last) __syncthreads();
   });
+}
+
+template <class Ring, int R, class Src, class Dst>
+__global__ void __launch_bounds__(512) k_merge(PassArgs<Ring> A, typename Ring::Params rp0, typename Ring::Params rp1,
+                                               typename Ring::Params rp2, Src src, Dst dst) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const TilePos P = tile_pos(A, A.xcd ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x);
+  uint32_t rsel;
+  const Ring Rg = make_ring(A, P.inst, rp0, rp1, rp2, &rsel);
+  merge_pass<Ring, R>(A, P, Rg, rsel, blockDim.x, reinterpret_cast<typename Ring::T*>(smem_raw), src, dst);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -384,10 +393,10 @@ __global__ void __launch_bounds__(512) k_merge(PassArgs<Ring> A, typename Ring::
 // group (d0 + LOGR = logn, logc = 0). Blocks of fewer than 1024 elements share a
 // workgroup: 64 threads hold 64 / (2^LOGR / 16) groups, each its own block.
 // ---------------------------------------------------------------------------------------
-template <int LOGR>
+template <int LOGR, int NT_ = 0>
 struct BlockShape {
   static constexpr int ACTIVE_LOG = LOGR > EPT_LOG ? LOGR - EPT_LOG : 0;  // threads per block
-  static constexpr int NT = (1 << ACTIVE_LOG) < 64 ? 64 : (1 << ACTIVE_LOG);
+  static constexpr int NT = NT_ ? NT_ : ((1 << ACTIVE_LOG) < 64 ? 64 : (1 << ACTIVE_LOG));
   static constexpr int GROUPS = NT >> ACTIVE_LOG;                        // blocks per workgroup
   static constexpr int NST = LOGR == 0 ? 0 : (LOGR + EPT_LOG - 1) / EPT_LOG;
   static constexpr int K0 = LOGR - EPT_LOG * (NST > 0 ? NST - 1 : 0);   // levels of the first stage
@@ -494,17 +503,19 @@ __device__ __forceinline__ void block_merge_stage(const PassArgs<Ring>& A, const
   }
 }
 
-template <class Ring, int LOGR, class SrcA, class SrcX, class Dst>
-__global__ void __launch_bounds__(BlockShape<LOGR>::NT) k_block(PassArgs<Ring> A, typename Ring::Params rp0,
-                                                                 typename Ring::Params rp1, typename Ring::Params rp2,
-                                                                 SrcA srca, SrcX srcx, Dst dst) {
+// The block pass for workgroup-local virtual workgroups vwg0 .. vwg0 + GROUPS - 1 (NT threads;
+// each group of 2^(LOGR-4) threads owns one block).
+template <class Ring, int LOGR, int NT, class SrcA, class SrcX, class Dst>
+__device__ __forceinline__ void block_pass(const PassArgs<Ring>& A, uint32_t vwg0, unsigned char* smem_raw,
+                                           const typename Ring::Params& rp0, const typename Ring::Params& rp1,
+                                           const typename Ring::Params& rp2, const SrcA& srca, const SrcX& srcx,
+                                           const Dst& dst) {
   using T = typename Ring::T;
-  using S = BlockShape<LOGR>;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
+  using S = BlockShape<LOGR, NT>;
   const uint32_t group = threadIdx.x >> S::ACTIVE_LOG;
   const uint32_t ltid = threadIdx.x & ((1u << S::ACTIVE_LOG) - 1);
-  const uint32_t vwg = blockIdx.x * S::GROUPS + group;
-  const bool active = vwg < A.tiles * A.ninst;
+  const uint32_t vwg = vwg0 + group;
+  const bool active = group < S::GROUPS && vwg < A.tiles * A.ninst;
   T* sa = reinterpret_cast<T*>(smem_raw) + ((size_t)group << (LOGR + 1));
   T* sx = sa + ((size_t)1 << LOGR);
   const TilePos P = tile_pos(A, active ? vwg : 0);
@@ -518,7 +529,6 @@ __global__ void __launch_bounds__(BlockShape<LOGR>::NT) k_block(PassArgs<Ring> A
       const T y = R.leaf(srca(R, P.inst, P.base), srcx(R, P.inst, P.base));
       dst(P.inst, P.base, A.final_store ? R.canon(y) : y);
     }
-    return;
   } else {
     constexpr int NST = S::NST, K0 = S::K0;
     // split stages (first takes K0 levels), the deepest also runs leaf + its merge levels
@@ -572,6 +582,15 @@ __global__ void __launch_bounds__(BlockShape<LOGR>::NT) k_block(PassArgs<Ring> A
       }
     }
   }
+}
+
+template <class Ring, int LOGR, class SrcA, class SrcX, class Dst>
+__global__ void __launch_bounds__(BlockShape<LOGR>::NT) k_block(PassArgs<Ring> A, typename Ring::Params rp0,
+                                                                 typename Ring::Params rp1, typename Ring::Params rp2,
+                                                                 SrcA srca, SrcX srcx, Dst dst) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  using S = BlockShape<LOGR>;
+  block_pass<Ring, LOGR, S::NT>(A, blockIdx.x * S::GROUPS, smem_raw, rp0, rp1, rp2, srca, srcx, dst);
 }
 
 }  // namespace fcirc

@@ -193,12 +193,17 @@ fcirc_status zp_tables(Ctx& c, uint32_t p, uint32_t f, int L, const ZpTables** o
   if (hipMemcpy(t.tw, tw.data(), ne * sizeof(ZpTw), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(t.twi, twi.data(), ne * sizeof(ZpTw), hipMemcpyHostToDevice) != hipSuccess)
     return FCIRC_EDEVICE;
+  if (hipMalloc(&t.dU, 30 * sizeof(ZpTw)) != hipSuccess ||
+      hipMemcpy(t.dU, t.U.tu, 15 * sizeof(ZpTw), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(t.dU + 15, t.U.tui, 15 * sizeof(ZpTw), hipMemcpyHostToDevice) != hipSuccess)
+    return FCIRC_ENOMEM;
   // Replace a smaller table for the same (p, f) only after the device is idle.
   for (auto& old : c.zp)
     if (old.p == p && old.f == f) {
       if (hipDeviceSynchronize() != hipSuccess) return FCIRC_EDEVICE;
       (void)hipFree(old.tw);
       (void)hipFree(old.twi);
+      (void)hipFree(old.dU);
       old = t;
       *out = &old;
       return FCIRC_OK;
@@ -225,7 +230,7 @@ fcirc_status zp_matvec(Ctx& c, const uint32_t* a, const uint32_t* x, uint32_t* y
   const ZpTw* tw[3] = {T->tw, T->tw, T->tw};
   const ZpTw* twi[3] = {T->twi, T->twi, T->twi};
   const uint64_t n = (uint64_t)1 << L;
-  const Uniform16<Zp>* U[3] = {&T->U, &T->U, &T->U};
+  const ZpTw* U[3] = {T->dU, T->dU, T->dU};
   return hip_status(run_product<Zp>(c, S, count, rps, tw, twi, U, false, LdPlain<uint32_t>{a, n},
                                     LdPlain<uint32_t>{x, n}, StPlain<uint32_t>{y, n}, y, (uint32_t*)c.ws, s));
 }

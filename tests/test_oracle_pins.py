@@ -160,6 +160,16 @@ def test_p4_complex_matches_fft_identity():
             assert np.linalg.norm(np.array(O.alg1_c128(a, x)) - want) <= 1e-12 * np.linalg.norm(want)
 
 
+def test_fft_oracle_matches_recursion():
+    rng = np.random.default_rng(12)
+    for n in (1, 2, 16, 256, 8192):
+        a = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+        x = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+        want = O.levels_matvec_c128(a, x, 1.0)
+        got = O.cyclic_matvec_fft_c128(a, x)
+        assert np.linalg.norm(got - want) <= 1e-12 * np.linalg.norm(want)
+
+
 def test_p4_complex_general_unit_f():
     rng = np.random.default_rng(10)
     for n in (2, 16, 128):
