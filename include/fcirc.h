@@ -120,7 +120,7 @@ fcirc_status fcirc_matvec_batched(fcirc_ctx *ctx, const void *a_base, const void
                                   const void *f, fcirc_ring ring, void *stream);
 
 /*
- * Circulant layer over a batch with one shared row (f = 1; rings C64 or R32):
+ * Circulant layer over a batch with one shared row (f = 1; rings C64 or R32; 16 <= n <= 2^24):
  *   forward : y[b] = C(a) x[b] for b < batch (x, y: batch*n elements, row-major).
  *   backward: gx[b] = C(a)^H gy[b] and ga = sum_b C(gy[b]) conj(x[b]), i.e. the
  *             gradients of a real loss with upstream gradient gy (PyTorch's convention

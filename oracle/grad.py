@@ -64,3 +64,25 @@ def finite_differences(a, x, g, h: float = 1e-6):
         e[idx] = h
         gx[idx] = (loss(a, x + e) - loss(a, x - e)) / (2 * h)
     return ga, gx
+
+
+def grads_fft(a, x, g):
+    """(y, grad_a, grad_x) of the layer through the f = 1 DFT identity (large n).
+
+    Uses y_b = C(a) x_b, grad_x_b = C(a)^H g_b = C(conj(rev a)) g_b and
+    grad_a = sum_b C(g_b) conj(x_b), each product computed by
+    ``fcirc.cyclic_matvec_fft_c128``. The tests pin this against ``dense_autograd``.
+    """
+    from .fcirc import cyclic_matvec_fft_c128
+    a = np.asarray(a)
+    x = np.atleast_2d(np.asarray(x))
+    g = np.atleast_2d(np.asarray(g))
+    cplx = np.iscomplexobj(a) or np.iscomplexobj(x) or np.iscomplexobj(g)
+    n = a.shape[0]
+    rev_conj_a = np.conj(a[(-np.arange(n)) % n])
+    y = np.stack([cyclic_matvec_fft_c128(a, xb) for xb in x])
+    gx = np.stack([cyclic_matvec_fft_c128(rev_conj_a, gb) for gb in g])
+    ga = sum(cyclic_matvec_fft_c128(gb, np.conj(xb)) for gb, xb in zip(g, x))
+    if not cplx:
+        return y.real, ga.real, gx.real
+    return y, ga, gx

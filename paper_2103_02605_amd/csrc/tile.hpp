@@ -41,6 +41,7 @@ struct PassArgs {
   uint32_t logc;                    // tile columns
   uint32_t tiles;                   // tiles per instance
   uint32_t narr;                    // arrays per instance handled by this launch (split: 1 or 2)
+  uint32_t arr0;                    // array of the first (split with narr 1: 0 row, 1 vector)
   uint32_t ninst;                   // instances
   uint32_t ring_per_inst;           // 1: instance z uses ring parameters [z % 3]
   uint32_t final_store;             // 1: canonicalise values on the way out
@@ -73,7 +74,7 @@ __device__ __forceinline__ TilePos tile_pos(const PassArgs<Ring>& A, uint32_t wg
   TilePos t;
   t.tile = wg % A.tiles;
   const uint32_t rest = wg / A.tiles;
-  t.arr = rest % A.narr;
+  t.arr = rest % A.narr + A.arr0;
   t.inst = rest / A.narr;
   const uint32_t cols_log = A.logn - A.d0 - A.logr;  // log2 rs
   const uint32_t tpb_log = cols_log - A.logc;        // log2 tiles per block

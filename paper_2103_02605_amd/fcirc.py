@@ -183,3 +183,67 @@ def get_schedule(n: int, ring: int, device=None) -> dict:
     top, tile, xcd = C.c_int(), C.c_int(), C.c_int()
     ntop = L.lib().fcirc_get_schedule(context(device).handle, ring, n, C.byref(top), C.byref(tile), C.byref(xcd))
     return {"top_passes": ntop, "top_levels": top.value, "tile_log": tile.value, "xcd": xcd.value}
+
+
+# -------------------------------------------------------------------------------------
+# Circulant layer (f = 1) with a hand-written backward: fcirc_matvec_fwd_shared and
+# fcirc_matvec_backward. x has shape (batch, n) and a shape (n,), float32 or complex64.
+# -------------------------------------------------------------------------------------
+
+def _layer_ring(a: torch.Tensor):
+    if a.dtype == torch.float32:
+        return L.FCIRC_R32
+    if a.dtype == torch.complex64:
+        return L.FCIRC_C64
+    raise TypeError("the circulant layer takes float32 or complex64 tensors")
+
+
+def layer_forward(a: torch.Tensor, x: torch.Tensor) -> torch.Tensor:
+    """y[b] = C(a) x[b] for every row b (one shared defining row, f = 1)."""
+    _need(a, "a")
+    _need(x, "x")
+    if x.dim() != 2 or a.dim() != 1 or x.shape[1] != a.shape[0] or x.dtype != a.dtype:
+        raise ValueError("a must be (n,) and x (batch, n) of the same dtype")
+    y = torch.empty_like(x)
+    ctx = context(a.device)
+    L.check(L.lib().fcirc_matvec_fwd_shared(ctx.handle, _ptr(a), _ptr(x), _ptr(y), a.shape[0], x.shape[0],
+                                            _layer_ring(a), _stream(a)), "fcirc_matvec_fwd_shared")
+    return y
+
+
+def layer_backward(a: torch.Tensor, x: torch.Tensor, gy: torch.Tensor, need_a: bool = True, need_x: bool = True):
+    """(grad_a, grad_x) of a real loss whose gradient with respect to y is gy."""
+    _need(a, "a")
+    _need(x, "x")
+    _need(gy, "gy")
+    ga = torch.empty_like(a) if need_a else None
+    gx = torch.empty_like(x) if need_x else None
+    ctx = context(a.device)
+    L.check(L.lib().fcirc_matvec_backward(ctx.handle, _ptr(a), _ptr(x), _ptr(gy),
+                                          _ptr(ga) if ga is not None else None,
+                                          _ptr(gx) if gx is not None else None,
+                                          a.shape[0], x.shape[0], _layer_ring(a), _stream(a)),
+            "fcirc_matvec_backward")
+    return ga, gx
+
+
+class CirculantFn(torch.autograd.Function):
+    """y = C(a) x row by row (f = 1) with the gradients computed by the library."""
+
+    @staticmethod
+    def forward(ctx, a, x):
+        a = a.contiguous()
+        x = x.contiguous()
+        ctx.save_for_backward(a, x)
+        return layer_forward(a, x)
+
+    @staticmethod
+    def backward(ctx, gy):
+        a, x = ctx.saved_tensors
+        ga, gx = layer_backward(a, x, gy.contiguous(), ctx.needs_input_grad[0], ctx.needs_input_grad[1])
+        return ga, gx
+
+
+def circulant(a: torch.Tensor, x: torch.Tensor) -> torch.Tensor:
+    """Differentiable circulant layer: rows of x multiplied by the circulant with first row a."""
+    return CirculantFn.apply(a, x)

@@ -383,3 +383,17 @@ def test_ring_inverse_root_identity(p):
     r = ring.sqrt_mod(s, p)
     assert r * r % p == s
     assert (-i * s * r) % p == ring.inv(r, p)
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+def test_fft_grads_match_dense_autograd(cplx):
+    rng = np.random.default_rng(15)
+    n, batch = 32, 3
+    def draw(*shape):
+        v = rng.standard_normal(shape)
+        return v + 1j * rng.standard_normal(shape) if cplx else v
+    a, x, g = draw(n), draw(batch, n), draw(batch, n)
+    y, ga, gx = OG.dense_autograd(a, x, g)
+    y2, ga2, gx2 = OG.grads_fft(a, x, g)
+    for u, v in ((y, y2), (ga, ga2), (gx, gx2)):
+        np.testing.assert_allclose(v, u, rtol=1e-10, atol=1e-10)
