@@ -131,7 +131,56 @@ def secondary(torch, F, W, quick: bool):
     c = torch.empty(1 << 21, dtype=torch.int16, device="cuda")
     ms = time_steps(torch, lambda i: F.bigint_mul(ta, tb, out=c), 20 if quick else 100, 5)
     out["bigint_mul_2x2^24bit"] = {"ms": ms, "Glimb_per_s": (1 << 21) / ms / 1e6}
+    out["batched_c64_4096"] = batched_vs_plain(torch, F, W, quick)
+    out["layer_fwd_bwd_256x2^14"] = layer_vs_plain(torch, F, W, quick)
     return out
+
+
+def batched_vs_plain(torch, F, W, quick: bool):
+    """4096 complex64 products of sizes 2^6..2^16 (seed 6): one graph-replayed persistent
+    launch against one fcirc_matvec call per instance, on the same device buffers."""
+    from paper_2103_02605_amd.batched import BatchPlan
+    e, a_list, x_list = W.batched_c64(4096, W.SEED_BATCHED)
+    plan = BatchPlan(a_list, x_list, dtype=np.complex64)
+    total = int(plan.offsets[-1])
+    ms_b = time_steps(torch, lambda i: plan.run(), 5 if quick else 20, 2)
+    views = [(plan.a[plan.offsets[k]:plan.offsets[k + 1]], plan.x[plan.offsets[k]:plan.offsets[k + 1]],
+              plan.y[plan.offsets[k]:plan.offsets[k + 1]]) for k in range(len(a_list))]
+
+    def plain(i):
+        for a, x, y in views:
+            F.matvec(a, x, out=y)
+    ms_p = time_steps(torch, plain, 1 if quick else 3, 1)
+    return {"coefficients": total, "batched_ms": ms_b, "plain_ms": ms_p,
+            "batched_Gcoeff_per_s": total / ms_b / 1e6, "plain_Gcoeff_per_s": total / ms_p / 1e6,
+            "batched_over_plain": ms_p / ms_b}
+
+
+def layer_vs_plain(torch, F, W, quick: bool):
+    """Circulant layer, batch 256 x 2^14 float32 (seed 7): library forward + backward against
+    one product per row for y, grad_x and grad_a plus a torch sum."""
+    a, x, g = W.circ_layer_f32()
+    ta, tx, tg = torch.from_numpy(a).cuda(), torch.from_numpy(x).cuda(), torch.from_numpy(g).cuda()
+    n = a.shape[0]
+
+    def fused(i):
+        F.layer_forward(ta, tx)
+        F.layer_backward(ta, tx, tg)
+    ms_f = time_steps(torch, fused, 5 if quick else 20, 2)
+    rev = ta[(-torch.arange(n, device="cuda")) % n].contiguous()
+    y = torch.empty_like(tx)
+    gx = torch.empty_like(tx)
+    parts = torch.empty_like(tx)
+
+    def plain(i):
+        for b in range(tx.shape[0]):
+            F.matvec(ta, tx[b], out=y[b])
+            F.matvec(rev, tg[b], out=gx[b])
+            F.matvec(tg[b], tx[b], out=parts[b])
+        parts.sum(0)
+    ms_p = time_steps(torch, plain, 1 if quick else 3, 1)
+    return {"fwd_bwd_ms": ms_f, "plain_ms": ms_p, "fused_over_plain": ms_p / ms_f,
+            "coefficients_per_pass": int(tx.numel())}
 
 
 def cpu_baseline(W, budget_s: float = 15.0):
