@@ -157,12 +157,18 @@ fcirc_status fcirc_set_split(fcirc_ctx *ctx, int top_levels);
 int fcirc_get_split(fcirc_ctx *ctx, uint64_t n, fcirc_ring ring);
 /*
  * Set the schedule for (ring, n) explicitly, as fcirc_tune would: top_levels (-1 default),
- * tile_log = log2 elements of a top-pass tile (-1 default, at most 13), xcd = 1 for the
- * XCD-aware tile order. fcirc_get_schedule reports the schedule in use and returns the
- * number of top passes.
+ * tile_log = log2 elements of a top-pass tile (-1 default, at most 13), flags = a bitwise
+ * OR of FCIRC_SCHED_* (0..3; the default is FCIRC_SCHED_XCD). fcirc_get_schedule reports
+ * the schedule in use and returns the number of top passes.
+ *   FCIRC_SCHED_XCD       top-pass tiles in XCD-aware order (neighbouring column tiles on
+ *                         one XCD, so they share its L2)
+ *   FCIRC_SCHED_SEPARATE  the split passes take the row and the vector in separate
+ *                         workgroups (default: one workgroup splits the same tile of both)
  */
-fcirc_status fcirc_set_schedule(fcirc_ctx *ctx, fcirc_ring ring, uint64_t n, int top_levels, int tile_log, int xcd);
-int fcirc_get_schedule(fcirc_ctx *ctx, fcirc_ring ring, uint64_t n, int *top_levels, int *tile_log, int *xcd);
+#define FCIRC_SCHED_XCD 1
+#define FCIRC_SCHED_SEPARATE 2
+fcirc_status fcirc_set_schedule(fcirc_ctx *ctx, fcirc_ring ring, uint64_t n, int top_levels, int tile_log, int flags);
+int fcirc_get_schedule(fcirc_ctx *ctx, fcirc_ring ring, uint64_t n, int *top_levels, int *tile_log, int *flags);
 
 #ifdef __cplusplus
 }

@@ -121,6 +121,10 @@ void fcirc_destroy(fcirc_ctx* ctx) {
     (void)hipFree(t.tw);
     (void)hipFree(t.twi);
     (void)hipFree(t.dU);
+    for (int L = 0; L < 27; ++L) {
+      if (t.ft[L]) (void)hipFree(t.ft[L]);
+      if (t.fti[L]) (void)hipFree(t.fti[L]);
+    }
   }
   for (auto& t : ctx->c.c32) {
     (void)hipFree(t.tw);

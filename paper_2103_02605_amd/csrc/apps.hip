@@ -237,6 +237,9 @@ fcirc_status three_prime_products(Ctx& c, const V* a, uint64_t na, const V* b, u
   const ZpTw* tw[3];
   const ZpTw* twi[3];
   const ZpTw* U[3];
+  const ZpTw* FT[3];
+  const ZpTw* FTI[3];
+  bool have_ft = true;
   for (int i = 0; i < 3; ++i) {
     const ZpTables* T = nullptr;
     fcirc_status st = zp_tables(c, ps[i], 1u, L, &T);
@@ -245,10 +248,13 @@ fcirc_status three_prime_products(Ctx& c, const V* a, uint64_t na, const V* b, u
     tw[i] = T->tw;
     twi[i] = T->twi;
     U[i] = T->dU;
+    st = zp_first_tables(c, T, L, &FT[i], &FTI[i]);
+    if (st != FCIRC_OK) return st;
+    have_ft = have_ft && FT[i] != nullptr;
   }
   const uint64_t N = (uint64_t)1 << L;
   const Schedule S = schedule_for(c, FCIRC_ZP_998244353, L);
-  return hip_status(run_product<Zp>(c, S, 3, rp, tw, twi, U, true, LdRowRev<V>{a, na, N}, LdVecPad<V>{b, nb},
+  return hip_status(run_product<Zp>(c, S, 3, rp, tw, twi, U, have_ft ? FT : nullptr, have_ft ? FTI : nullptr, true, LdRowRev<V>{a, na, N}, LdVecPad<V>{b, nb},
                                     StPlain<uint32_t>{res, N}, res, ws, s));
 }
 
@@ -267,7 +273,7 @@ fcirc_status polymul_i64(Ctx& c, const int32_t* a, uint64_t na, const int32_t* b
   if (st != FCIRC_OK) return st;
   const CrtConsts K = crt_consts();
   const uint32_t grid = (uint32_t)((nc + 255) / 256);
-  return hip_status(launch(c, "fcirc_crt", s, [&] { hipLaunchKernelGGL(k_crt_i64, dim3(grid), dim3(256), 0, s, res, N, nc, K, out, c.d_status); }));
+  return hip_status(launch(c, "fcirc_crt", s, [&](hipEvent_t e0_, hipEvent_t e1_) { FCIRC_LAUNCH(e0_, e1_, k_crt_i64, dim3(grid), dim3(256), 0, s, res, N, nc, K, out, c.d_status); }));
 }
 
 fcirc_status bigint_mul(Ctx& c, const uint16_t* a, uint64_t na, const uint16_t* b, uint64_t nb, uint16_t* out, hipStream_t s) {
@@ -289,13 +295,13 @@ fcirc_status bigint_mul(Ctx& c, const uint16_t* a, uint64_t na, const uint16_t* 
   st = three_prime_products<uint16_t>(c, a, na, b, nb, L, res, base + off_w, s);
   if (st != FCIRC_OK) return st;
   const CrtConsts K = crt_consts();
-  hipError_t e = launch(c, "fcirc_crt", s, [&] {
-    hipLaunchKernelGGL(k_crt_u64, dim3((uint32_t)((nc + 255) / 256)), dim3(256), 0, s, res, N, nc, K, coef, c.d_status);
+  hipError_t e = launch(c, "fcirc_crt", s, [&](hipEvent_t e0_, hipEvent_t e1_) {
+    FCIRC_LAUNCH(e0_, e1_, k_crt_u64, dim3((uint32_t)((nc + 255) / 256)), dim3(256), 0, s, res, N, nc, K, coef, c.d_status);
   });
   if (e != hipSuccess) return hip_status(e);
-  e = launch(c, "fcirc_carry", s, [&] { hipLaunchKernelGGL(k_carry_scan1, dim3((uint32_t)nblk), dim3(CARRY_NT), 0, s, coef, nc, nl, u, summ); });
+  e = launch(c, "fcirc_carry", s, [&](hipEvent_t e0_, hipEvent_t e1_) { FCIRC_LAUNCH(e0_, e1_, k_carry_scan1, dim3((uint32_t)nblk), dim3(CARRY_NT), 0, s, coef, nc, nl, u, summ); });
   if (e != hipSuccess) return hip_status(e);
-  return hip_status(launch(c, "fcirc_carry", s, [&] { hipLaunchKernelGGL(k_carry_scan2, dim3((uint32_t)nblk), dim3(CARRY_NT), 0, s, u, nl, summ, out); }));
+  return hip_status(launch(c, "fcirc_carry", s, [&](hipEvent_t e0_, hipEvent_t e1_) { FCIRC_LAUNCH(e0_, e1_, k_carry_scan2, dim3((uint32_t)nblk), dim3(CARRY_NT), 0, s, u, nl, summ, out); }));
 }
 
 }  // namespace fcirc

@@ -295,7 +295,12 @@ fcirc_status build_and_launch(Ctx& c, const std::vector<uint64_t>& key, const vo
                               const typename Ring::Params* rp_by_L, hipStream_t s) {
   using T = typename Ring::T;
   for (GraphEntry* g : c.graphs)
-    if (g->key == key) return hip_status(hipGraphLaunch(g->exec, s));
+    if (g->key == key)
+      return hip_status(launch(c, "fcirc_batched", s, [&](hipEvent_t e0_, hipEvent_t e1_) {
+        if (e0_) (void)hipEventRecord(e0_, s);
+        (void)hipGraphLaunch(g->exec, s);
+        if (e1_) (void)hipEventRecord(e1_, s);
+      }));
 
   // instances sorted by size, largest first
   std::vector<uint32_t> order(count);
@@ -377,7 +382,7 @@ fcirc_status build_and_launch(Ctx& c, const std::vector<uint64_t>& key, const vo
   B.twi = twi;
   for (int L = 0; L <= 16; ++L) B.rp[L] = rp_by_L[L];
   B.U = U;
-  const size_t lds = 2 * ((size_t)1 << BLOCK_LOG) * sizeof(T);
+  const size_t lds = block_lds_bytes<Ring, BLOCK_LOG, BT>();
   auto kb = k_batched<Ring>;
   allow_lds(kb, lds);
   int per_cu = 0;
@@ -404,7 +409,11 @@ fcirc_status build_and_launch(Ctx& c, const std::vector<uint64_t>& key, const vo
     return FCIRC_EDEVICE;
   }
   c.graphs.push_back(g);
-  return hip_status(launch(c, "fcirc_batched", s, [&] { (void)hipGraphLaunch(g->exec, s); }));
+  return hip_status(launch(c, "fcirc_batched", s, [&](hipEvent_t e0_, hipEvent_t e1_) {
+    if (e0_) (void)hipEventRecord(e0_, s);
+    (void)hipGraphLaunch(g->exec, s);
+    if (e1_) (void)hipEventRecord(e1_, s);
+  }));
 }
 
 }  // namespace

@@ -113,10 +113,10 @@ fcirc_status c32_matvec(Ctx& c, const void* a, const void* x, void* y, int L, ui
   const float2* U[3] = {T->dU, T->dU, T->dU};
   hipError_t e;
   if (real_io) {
-    e = run_product<C32>(c, S, count, rps, tw, twi, U, false, LdR32{(const float*)a, n}, LdR32{(const float*)x, n},
+    e = run_product<C32>(c, S, count, rps, tw, twi, U, nullptr, nullptr, false, LdR32{(const float*)a, n}, LdR32{(const float*)x, n},
                          StR32{(float*)y, n}, nullptr, ws, s);
   } else {
-    e = run_product<C32>(c, S, count, rps, tw, twi, U, false, LdPlain<float2>{(const float2*)a, n},
+    e = run_product<C32>(c, S, count, rps, tw, twi, U, nullptr, nullptr, false, LdPlain<float2>{(const float2*)a, n},
                          LdPlain<float2>{(const float2*)x, n}, StPlain<float2>{(float2*)y, n}, (float2*)y, ws, s);
   }
   return hip_status(e);

@@ -2,6 +2,7 @@
 // per-kernel event timing, and the driver that enqueues one f-circulant product (or a
 // batch of equal-size products) as top split passes -> block pass -> top merge passes.
 #pragma once
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -89,6 +90,9 @@ struct ZpTables {
   ZpTw* twi = nullptr;
   Uniform16<Zp> U;
   ZpTw* dU = nullptr;  // device copy: tu[15] then tui[15]
+  // packed first twiddles of the deepest radix-16 stage, per log2 n (see PassArgs::ft)
+  ZpTw* ft[27] = {nullptr};
+  ZpTw* fti[27] = {nullptr};
 };
 
 struct C32Tables {
@@ -105,7 +109,7 @@ struct C32Tables {
 // ----------------------------------------------------------------------------------------
 struct Schedule {
   int L = 0;
-  int xcd = 1;           // XCD-aware tile order in the top passes
+  int flags = 1;         // FCIRC_SCHED_* bits: XCD-aware tile order, separate row/vector split
   int block_levels = 0;  // levels done in the LDS-resident block pass
   int ntop = 0;          // HBM-streamed top passes
   int top_d0[4] = {0, 0, 0, 0};
@@ -120,7 +124,7 @@ struct TuneKey {
 struct TuneVal {
   int top = -1;       // top levels (HBM-streamed), -1: default
   int tile_log = -1;  // log2 elements per top-pass tile, -1: default
-  int xcd = 1;
+  int flags = 1;      // FCIRC_SCHED_* bits
 };
 
 struct GraphEntry;  // batched launches captured in HIP graphs (batched.hip)
@@ -141,21 +145,28 @@ struct Ctx {
   bool debug_sync = false;
 };
 
-// Launch wrapper: optional events on the stream, error check, optional debug sync.
+// Launch wrapper. fn(e0, e1) enqueues one kernel; with timing on, e0/e1 are events that
+// the kernel's own dispatch records (hipExtLaunchKernelGGL), so the measured interval is
+// the kernel alone. Errors are checked; FCIRC_DEBUG_SYNC synchronises after each launch.
+#define FCIRC_LAUNCH(e0, e1, kern, grid, block, lds, strm, ...)                                  \
+  do {                                                                                        \
+    if (e0)                                                                                   \
+      hipExtLaunchKernelGGL(kern, grid, block, lds, strm, e0, e1, 0, __VA_ARGS__);            \
+    else                                                                                      \
+      hipLaunchKernelGGL(kern, grid, block, lds, strm, __VA_ARGS__);                          \
+  } while (0)
+
 template <class F>
 inline hipError_t launch(Ctx& c, const char* name, hipStream_t s, F&& fn) {
   hipEvent_t a = nullptr, b = nullptr;
   if (c.timer.enabled) {
     a = c.timer.get();
     b = c.timer.get();
-    if (a) (void)hipEventRecord(a, s);
+    if (!a || !b) a = b = nullptr;
   }
-  fn();
+  fn(a, b);
   hipError_t e = hipGetLastError();
-  if (c.timer.enabled && a && b) {
-    (void)hipEventRecord(b, s);
-    c.timer.pending.push_back({c.timer.name_id(name), a, b});
-  }
+  if (a && b) c.timer.pending.push_back({c.timer.name_id(name), a, b});
   if (e == hipSuccess && c.debug_sync) e = hipStreamSynchronize(s);
   return e;
 }
@@ -226,10 +237,10 @@ inline int ilog2(uint64_t v) {
 
 // elem_log: log2 bytes per element (2 for uint32, 3 for complex64).
 // top_levels < 0: default split; tile_log_in < 0: default tile (32 KiB of LDS).
-inline Schedule make_schedule(int L, int elem_log, int top_levels, int tile_log_in = -1, int xcd = 1) {
+inline Schedule make_schedule(int L, int elem_log, int top_levels, int tile_log_in = -1, int flags = 1) {
   Schedule s;
   s.L = L;
-  s.xcd = xcd;
+  s.flags = flags;
   const int block_max = elem_log == 2 ? 12 : 11;  // 32 KiB of LDS for row + vector
   const int tile_max = 13;                        // 512 threads x 16 elements per workgroup
   int tile_log = tile_log_in >= 0 ? tile_log_in : (elem_log == 2 ? 13 : 12);
@@ -277,10 +288,10 @@ inline hipError_t launch_block_l(Ctx& c, const PassArgs<Ring>& A, const typename
   using S = BlockShape<LOGR>;
   const uint64_t vwgs = (uint64_t)A.tiles * A.ninst;
   const uint32_t grid = (uint32_t)((vwgs + S::GROUPS - 1) / S::GROUPS);
-  const size_t lds = (size_t)S::GROUPS * 2 * ((size_t)1 << LOGR) * sizeof(typename Ring::T);
+  const size_t lds = block_lds_bytes<Ring, LOGR>();
   auto k = k_block<Ring, LOGR, SrcA, SrcX, Dst>;
   allow_lds(k, lds);
-  return launch(c, "fcirc_block", s, [&] { hipLaunchKernelGGL(k, dim3(grid), dim3(S::NT), lds, s, A, rp[0], rp[1], rp[2], sa, sx, d); });
+  return launch(c, "fcirc_block", s, [&](hipEvent_t e0_, hipEvent_t e1_) { FCIRC_LAUNCH(e0_, e1_, k, dim3(grid), dim3(S::NT), lds, s, A, rp[0], rp[1], rp[2], sa, sx, d); });
 }
 
 template <class Ring, class SrcA, class SrcX, class Dst>
@@ -305,14 +316,21 @@ inline hipError_t launch_split_r(Ctx& c, const PassArgs<Ring>& A, const typename
                                  Dst dx, uint32_t grid, uint32_t nt, size_t lds, hipStream_t s) {
   auto k = k_split<Ring, R, SrcA, SrcX, Dst>;
   allow_lds(k, lds);
-  return launch(c, "fcirc_top_split", s, [&] { hipLaunchKernelGGL(k, dim3(grid), dim3(nt), lds, s, A, rp[0], rp[1], rp[2], sa, sx, da, dx); });
+  return launch(c, "fcirc_top_split", s, [&](hipEvent_t e0_, hipEvent_t e1_) { FCIRC_LAUNCH(e0_, e1_, k, dim3(grid), dim3(nt), lds, s, A, rp[0], rp[1], rp[2], sa, sx, da, dx); });
+}
+template <class Ring, int R, class SrcA, class SrcX, class Dst>
+inline hipError_t launch_split_ax_r(Ctx& c, const PassArgs<Ring>& A, const typename Ring::Params* rp, SrcA sa, SrcX sx,
+                                    Dst da, Dst dx, uint32_t grid, uint32_t nt, size_t lds, hipStream_t s) {
+  auto k = k_split_ax<Ring, R, SrcA, SrcX, Dst>;
+  allow_lds(k, lds);
+  return launch(c, "fcirc_top_split", s, [&](hipEvent_t e0_, hipEvent_t e1_) { FCIRC_LAUNCH(e0_, e1_, k, dim3(grid), dim3(nt), lds, s, A, rp[0], rp[1], rp[2], sa, sx, da, dx); });
 }
 template <class Ring, int R, class Src, class Dst>
 inline hipError_t launch_merge_r(Ctx& c, const PassArgs<Ring>& A, const typename Ring::Params* rp, Src src, Dst dst,
                                  uint32_t grid, uint32_t nt, size_t lds, hipStream_t s) {
   auto k = k_merge<Ring, R, Src, Dst>;
   allow_lds(k, lds);
-  return launch(c, "fcirc_top_merge", s, [&] { hipLaunchKernelGGL(k, dim3(grid), dim3(nt), lds, s, A, rp[0], rp[1], rp[2], src, dst); });
+  return launch(c, "fcirc_top_merge", s, [&](hipEvent_t e0_, hipEvent_t e1_) { FCIRC_LAUNCH(e0_, e1_, k, dim3(grid), dim3(nt), lds, s, A, rp[0], rp[1], rp[2], src, dst); });
 }
 
 #define FCIRC_R_SWITCH(R_, CALL)          \
@@ -337,6 +355,13 @@ inline hipError_t launch_split(Ctx& c, const PassArgs<Ring>& A, const typename R
   FCIRC_R_SWITCH(A.logr, FCIRC_CALL)
 #undef FCIRC_CALL
 }
+template <class Ring, class SrcA, class SrcX, class Dst>
+inline hipError_t launch_split_ax(Ctx& c, const PassArgs<Ring>& A, const typename Ring::Params* rp, SrcA sa, SrcX sx, Dst da,
+                                  Dst dx, uint32_t grid, uint32_t nt, size_t lds, hipStream_t s) {
+#define FCIRC_CALL(r) launch_split_ax_r<Ring, r>(c, A, rp, sa, sx, da, dx, grid, nt, lds, s)
+  FCIRC_R_SWITCH(A.logr, FCIRC_CALL)
+#undef FCIRC_CALL
+}
 template <class Ring, class Src, class Dst>
 inline hipError_t launch_merge(Ctx& c, const PassArgs<Ring>& A, const typename Ring::Params* rp, Src src, Dst dst,
                                uint32_t grid, uint32_t nt, size_t lds, hipStream_t s) {
@@ -348,7 +373,8 @@ inline hipError_t launch_merge(Ctx& c, const PassArgs<Ring>& A, const typename R
 template <class Ring, class SrcA, class SrcX, class Dst>
 inline hipError_t run_product(Ctx& c, const Schedule& S, uint32_t count, const typename Ring::Params* rp,
                               typename Ring::Tw const* const* tw, typename Ring::Tw const* const* twi,
-                              typename Ring::Tw const* const* U, bool ring_per_inst, SrcA srca, SrcX srcx, Dst dst,
+                              typename Ring::Tw const* const* U, typename Ring::Tw const* const* FT,
+                              typename Ring::Tw const* const* FTI, bool ring_per_inst, SrcA srca, SrcX srcx, Dst dst,
                               typename Ring::T* wy, typename Ring::T* ws, hipStream_t s) {
   using T = typename Ring::T;
   const int L = S.L;
@@ -357,6 +383,8 @@ inline hipError_t run_product(Ctx& c, const Schedule& S, uint32_t count, const t
   for (int r = 0; r < 3; ++r) {
     A.tu[r] = U[r];
     A.tui[r] = U[r] + 15;
+    A.ft[r] = FT ? FT[r] : nullptr;
+    A.fti[r] = FTI ? FTI[r] : nullptr;
   }
   for (int i = 0; i < 3; ++i) {
     A.tw[i] = tw[i];
@@ -365,7 +393,7 @@ inline hipError_t run_product(Ctx& c, const Schedule& S, uint32_t count, const t
   A.logn = L;
   A.ninst = count;
   A.ring_per_inst = ring_per_inst ? 1 : 0;
-  A.xcd = S.xcd;
+  A.xcd = (S.flags & FCIRC_SCHED_XCD) ? 1 : 0;
   hipError_t e;
   if (S.ntop == 0) {
     A.d0 = 0;
@@ -386,15 +414,26 @@ inline hipError_t run_product(Ctx& c, const Schedule& S, uint32_t count, const t
     A.logr = S.top_r[i];
     A.logc = S.top_c[i];
     A.tiles = (uint32_t)(n >> (A.logr + A.logc));
-    A.narr = 2;
     A.final_store = 0;
     const size_t tile = (size_t)1 << (A.logr + A.logc);
-    const size_t lds = tile * sizeof(T);
-    const uint32_t grid = A.tiles * 2 * count, nt = (uint32_t)(tile >> EPT_LOG);
-    if (i == 0)
-      e = launch_split<Ring>(c, A, rp, srca, srcx, swa, swx, grid, nt, lds, s);
-    else
-      e = launch_split<Ring>(c, A, rp, lwa, lwx, swa, swx, grid, nt, lds, s);
+    const uint32_t nt = (uint32_t)(tile >> EPT_LOG);
+    if (S.flags & FCIRC_SCHED_SEPARATE) {  // row and vector tiles in separate workgroups
+      A.narr = 2;
+      const size_t lds = tile * sizeof(T);
+      const uint32_t grid = A.tiles * 2 * count;
+      if (i == 0)
+        e = launch_split<Ring>(c, A, rp, srca, srcx, swa, swx, grid, nt, lds, s);
+      else
+        e = launch_split<Ring>(c, A, rp, lwa, lwx, swa, swx, grid, nt, lds, s);
+    } else {  // one workgroup per tile of both
+      A.narr = 1;
+      const size_t lds = 2 * tile * sizeof(T);
+      const uint32_t grid = A.tiles * count;
+      if (i == 0)
+        e = launch_split_ax<Ring>(c, A, rp, srca, srcx, swa, swx, grid, nt, lds, s);
+      else
+        e = launch_split_ax<Ring>(c, A, rp, lwa, lwx, swa, swx, grid, nt, lds, s);
+    }
     if (e != hipSuccess) return e;
   }
   A.d0 = L - S.block_levels;
@@ -438,6 +477,8 @@ uint32_t zp_prime(fcirc_ring r);
 int zp_two_adic(uint32_t p);
 // Tables for (p, f) covering at least L levels; ENOROOT if f has no 2^L-th root.
 fcirc_status zp_tables(Ctx& c, uint32_t p, uint32_t f, int L, const ZpTables** out);
+// Packed deepest-stage first twiddles for size 2^L (L >= 4), built on first use.
+fcirc_status zp_first_tables(Ctx& c, const ZpTables* T, int L, const ZpTw** ft, const ZpTw** fti);
 ZpParams zp_params(uint32_t p, int L);
 fcirc_status c32_tables(Ctx& c, double fre, double fim, int L, hipStream_t s, const C32Tables** out);
 
@@ -464,7 +505,7 @@ inline Schedule schedule_for(Ctx& c, int ring, int L) {
   auto it = c.tuned.find(TuneKey{ring, L});
   if (it != c.tuned.end()) v = it->second;
   if (c.forced_top >= 0) v.top = c.forced_top;
-  return make_schedule(L, elem_log, v.top, v.tile_log, v.xcd);
+  return make_schedule(L, elem_log, v.top, v.tile_log, v.flags);
 }
 
 }  // namespace fcirc

@@ -213,7 +213,7 @@ hipError_t merge_leaves(Ctx& c, const C32Tables* T, int L, uint32_t count, float
 hipError_t leaf_mul(Ctx& c, const float2* A, float2* X, uint32_t n, uint32_t count, bool conj_a, float scale, hipStream_t s) {
   const uint64_t total = (uint64_t)n * count;
   const uint32_t grid = (uint32_t)std::min<uint64_t>((total + 255) / 256, 8192);
-  return launch(c, "fcirc_leaf_mul", s, [&] { hipLaunchKernelGGL(k_leaf_mul, dim3(grid), dim3(256), 0, s, A, X, n, count, conj_a ? 1 : 0, scale); });
+  return launch(c, "fcirc_leaf_mul", s, [&](hipEvent_t e0_, hipEvent_t e1_) { FCIRC_LAUNCH(e0_, e1_, k_leaf_mul, dim3(grid), dim3(256), 0, s, A, X, n, count, conj_a ? 1 : 0, scale); });
 }
 
 struct LayerWs {
@@ -318,7 +318,7 @@ extern "C" fcirc_status fcirc_matvec_backward(fcirc_ctx* ctx, const void* a, con
                : transform(c, T, L, count, 1, LdConj{(const float2*)x, n}, w.v2, s);
     if (e == hipSuccess) {
       const uint32_t grid = (uint32_t)((n + 255) / 256);
-      e = launch(c, "fcirc_leaf_sum", s, [&] { hipLaunchKernelGGL(k_leaf_sum, dim3(grid), dim3(256), 0, s, w.v1, w.v2, w.ahat, (uint32_t)n, count, scale); });
+      e = launch(c, "fcirc_leaf_sum", s, [&](hipEvent_t e0_, hipEvent_t e1_) { FCIRC_LAUNCH(e0_, e1_, k_leaf_sum, dim3(grid), dim3(256), 0, s, w.v1, w.v2, w.ahat, (uint32_t)n, count, scale); });
     }
     if (e == hipSuccess)
       e = real ? merge_leaves(c, T, L, 1, w.ahat, StR32{(float*)ga, n}, s)

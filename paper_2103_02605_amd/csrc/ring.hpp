@@ -52,13 +52,19 @@ struct Zp {
     const uint32_t q = __umulhi(v, t.wp);
     return v * t.w - q * p;  // in [0, 2p)
   }
+  // The negated product: q p - v w = -shoup(v, t) mod 2^32 (same cost). With it the row
+  // split needs one subtraction and one three-operand addition.
+  __device__ __forceinline__ uint32_t shoup_neg(uint32_t v, ZpTw t) const {
+    const uint32_t q = __umulhi(v, t.wp);
+    return q * p - v * t.w;
+  }
   __device__ __forceinline__ uint32_t red2(uint32_t u) const { return min(u, u - p2); }  // [0,4p) -> [0,2p)
 
   __device__ __forceinline__ void split_a(T& u, T& v, Tw g) const {
     const uint32_t uu = red2(u);
-    const uint32_t t = shoup(v, g);
-    u = uu + t;
-    v = uu - t + p2;
+    const uint32_t tn = shoup_neg(v, g);  // -g v, as 2^32 - [0, 2p)
+    u = uu - tn;                          // uu + g v in [0, 4p)
+    v = uu + p2 + tn;                     // uu - g v + 2p in (0, 4p)
   }
   __device__ __forceinline__ void split_x(T& u, T& v, Tw g) const {
     const uint32_t t = shoup(u, g);
@@ -77,9 +83,9 @@ struct Zp {
   static constexpr bool kCheapDerive = false;
   __device__ __forceinline__ void split_a2(T& u, T& v, Tw tu, Tw c) const {
     const uint32_t uu = red2(u);
-    const uint32_t t = shoup(shoup(v, tu), c);
-    u = uu + t;
-    v = uu - t + p2;
+    const uint32_t tn = shoup_neg(shoup(v, tu), c);
+    u = uu - tn;
+    v = uu + p2 + tn;
   }
   __device__ __forceinline__ void split_x2(T& u, T& v, Tw tu, Tw c) const {
     const uint32_t t = shoup(shoup(u, tu), c);

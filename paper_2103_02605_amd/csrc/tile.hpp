@@ -52,6 +52,11 @@ struct PassArgs {
   // block or the item). tui holds the inverses for the merge.
   typename Ring::Tw const* tu[3];   // 15 entries each, in device memory
   typename Ring::Tw const* tui[3];
+  // First twiddles of the deepest radix-16 stage, packed per item (may be null): for the
+  // node b0 at depth logn - 4, entries [4 b0 + j] = g_{logn-4+j, b0 2^j}, j < 4 (split);
+  // fti the inverses. One 32-byte load per item instead of four scattered ones.
+  typename Ring::Tw const* ft[3];
+  typename Ring::Tw const* fti[3];
 };
 
 // Workgroups are dispatched round-robin over the 8 XCDs (workgroup i runs on XCD i mod 8),
@@ -320,6 +325,97 @@ __global__ void __launch_bounds__(512) k_split(PassArgs<Ring> A, typename Ring::
 }
 
 // ---------------------------------------------------------------------------------------
+// Joint split pass: one workgroup takes the same tile of the row and of the vector. Both
+// use the same twiddles (the row split and the vector split of a node share g), so they
+// are loaded once; the vector's element loads are issued before the row's arithmetic and
+// the row's stores overlap the vector's arithmetic. LDS holds two tiles.
+// ---------------------------------------------------------------------------------------
+template <class Ring, int K, bool FIRST, bool LAST, class SrcA, class SrcX, class Dst>
+__device__ __forceinline__ void split_stage_ax(const PassArgs<Ring>& A, const TilePos& P, const Ring& R,
+                                               typename Ring::Tw const* tw, typename Ring::T* lda, typename Ring::T* ldx,
+                                               uint32_t l0, uint32_t nt, const SrcA& srca, const SrcX& srcx,
+                                               const Dst& dsta, const Dst& dstx) {
+  using T = typename Ring::T;
+  using Tw = typename Ring::Tw;
+  constexpr int IPT = 1 << (EPT_LOG - K);
+  constexpr int E = 1 << K;
+  T va[IPT][E], vx[IPT][E];
+  Tw t[IPT][E - 1];
+  Item it[IPT];
+#pragma unroll
+  for (int u = 0; u < IPT; ++u) {
+    it[u] = item_at(threadIdx.x + u * nt, A.logr, A.logc, l0, K);
+    load_tw<Ring, K>(t[u], tw, A.d0, P.blk, l0, it[u].sb);
+  }
+#pragma unroll
+  for (int u = 0; u < IPT; ++u)
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      const uint32_t row = it[u].row0 + ((uint32_t)i << it[u].sh);
+      if constexpr (FIRST)
+        va[u][i] = srca(R, P.inst, P.base + row * P.rs + it[u].col);
+      else
+        va[u][i] = lda[(row << A.logc) + it[u].col];
+    }
+  __builtin_amdgcn_sched_barrier(0);  // row loads first, then the vector's
+#pragma unroll
+  for (int u = 0; u < IPT; ++u)
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      const uint32_t row = it[u].row0 + ((uint32_t)i << it[u].sh);
+      if constexpr (FIRST)
+        vx[u][i] = srcx(R, P.inst, P.base + row * P.rs + it[u].col);
+      else
+        vx[u][i] = ldx[(row << A.logc) + it[u].col];
+    }
+  __builtin_amdgcn_sched_barrier(0);  // all loads in flight before the row's arithmetic
+#pragma unroll
+  for (int u = 0; u < IPT; ++u) split_levels<Ring, K, true, false>(R, va[u], va[u], t[u]);
+#pragma unroll
+  for (int u = 0; u < IPT; ++u)
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      const uint32_t row = it[u].row0 + ((uint32_t)i << it[u].sh);
+      if constexpr (LAST)
+        dsta(P.inst, P.base + row * P.rs + it[u].col, va[u][i]);
+      else
+        lda[(row << A.logc) + it[u].col] = va[u][i];
+    }
+#pragma unroll
+  for (int u = 0; u < IPT; ++u) split_levels<Ring, K, false, true>(R, vx[u], vx[u], t[u]);
+#pragma unroll
+  for (int u = 0; u < IPT; ++u)
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      const uint32_t row = it[u].row0 + ((uint32_t)i << it[u].sh);
+      if constexpr (LAST)
+        dstx(P.inst, P.base + row * P.rs + it[u].col, vx[u][i]);
+      else
+        ldx[(row << A.logc) + it[u].col] = vx[u][i];
+    }
+}
+
+template <class Ring, int R, class SrcA, class SrcX, class Dst>
+__global__ void __launch_bounds__(512) k_split_ax(PassArgs<Ring> A, typename Ring::Params rp0, typename Ring::Params rp1,
+                                                  typename Ring::Params rp2, SrcA srca, SrcX srcx, Dst dsta, Dst dstx) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  using T = typename Ring::T;
+  using SP = StagePlan<R>;
+  const TilePos P = tile_pos(A, A.xcd ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x);
+  uint32_t rsel;
+  const Ring Rg = make_ring(A, P.inst, rp0, rp1, rp2, &rsel);
+  T* lda = reinterpret_cast<T*>(smem_raw);
+  T* ldx = lda + ((size_t)1 << (A.logr + A.logc));
+  const typename Ring::Tw* tw = A.tw[rsel];
+  static_for<SP::NST>([&](auto sc) {
+    constexpr int s = decltype(sc)::value;
+    constexpr bool first = s == 0, last = s + 1 == SP::NST;
+    split_stage_ax<Ring, SP::k(s), first, last>(A, P, Rg, tw, lda, ldx, SP::l0(s), blockDim.x, srca, srcx, dsta, dstx);
+    if constexpr (!last) __syncthreads();
+  });
+}
+
+// ---------------------------------------------------------------------------------------
 // One merge stage of a top pass. FIRST: read global (the deepest stage runs first).
 // ---------------------------------------------------------------------------------------
 template <class Ring, int K, bool FIRST, bool LAST, class Src, class Dst>
@@ -393,6 +489,13 @@ __global__ void __launch_bounds__(512) k_merge(PassArgs<Ring> A, typename Ring::
 // Block pass (bottom of the recursion): a contiguous block of 2^LOGR elements per thread
 // group (d0 + LOGR = logn, logc = 0). Blocks of fewer than 1024 elements share a
 // workgroup: 64 threads hold 64 / (2^LOGR / 16) groups, each its own block.
+//
+// Twiddle latency. A thread group holds the whole block, so there is one workgroup per
+// CU and little else to hide a global load behind. The twiddles of every level above the
+// deepest radix-16 stage (2^(LOGR-4) - 1 nodes per direction, contiguous per level in the
+// heap) are therefore copied into LDS at the start, and the first twiddles of the deepest
+// stage are loaded into registers at the start too; all of these loads overlap the
+// element loads of the first stage.
 // ---------------------------------------------------------------------------------------
 template <int LOGR, int NT_ = 0>
 struct BlockShape {
@@ -402,11 +505,59 @@ struct BlockShape {
   static constexpr int NST = LOGR == 0 ? 0 : (LOGR + EPT_LOG - 1) / EPT_LOG;
   static constexpr int K0 = LOGR - EPT_LOG * (NST > 0 ? NST - 1 : 0);   // levels of the first stage
   static constexpr int EPT = LOGR < EPT_LOG ? (1 << LOGR) : (1 << EPT_LOG);
+  static constexpr int NTW = LOGR > EPT_LOG ? (1 << (LOGR - EPT_LOG)) - 1 : 0;  // LDS twiddles per direction
 };
 
+// LDS of a block pass: [GROUPS][row, vector][2^LOGR] elements, then [GROUPS][split, merge][NTW]
+// twiddles (local heap order: level l, node b at 2^l - 1 + b).
+template <class Ring, int LOGR, int NT = 0>
+constexpr size_t block_lds_bytes() {
+  using S = BlockShape<LOGR, NT>;
+  return (size_t)S::GROUPS * (2 * (sizeof(typename Ring::T) << LOGR) + 2 * (size_t)S::NTW * sizeof(typename Ring::Tw));
+}
+
+// First twiddles of the deepest radix-16 stage (one item per thread), split and merge.
+template <class Ring>
+struct DeepTw {
+  typename Ring::Tw t[EPT_LOG], ti[EPT_LOG];
+};
+
+template <class Ring, int LOGR>
+__device__ __forceinline__ void load_deep_tw(DeepTw<Ring>& D, const PassArgs<Ring>& A, const TilePos& P, uint32_t rsel,
+                                             typename Ring::Tw const* tw, typename Ring::Tw const* twi, uint32_t ltid) {
+  constexpr uint32_t l0 = LOGR - EPT_LOG;
+  const Item it = item_at(ltid, LOGR, 0, l0, EPT_LOG);
+  if (A.ft[rsel] != nullptr && A.d0 + (uint32_t)LOGR == A.logn) {
+    const uint32_t b0 = (P.blk << l0) + it.sb;  // node at depth logn - 4
+#pragma unroll
+    for (int j = 0; j < EPT_LOG; ++j) {
+      D.t[j] = A.ft[rsel][4 * b0 + j];
+      D.ti[j] = A.fti[rsel][4 * b0 + j];
+    }
+  } else {
+    load_tw_first<Ring, EPT_LOG>(D.t, tw, A.d0, P.blk, l0, it.sb);
+    load_tw_first<Ring, EPT_LOG>(D.ti, twi, A.d0, P.blk, l0, it.sb);
+  }
+}
+
+// The 2^K - 1 twiddles of an item from the LDS copy (levels l0 .. l0 + K - 1).
+template <class Ring, int K>
+__device__ __forceinline__ void lds_tw(typename Ring::Tw* t, const typename Ring::Tw* stw, uint32_t l0, uint32_t sb) {
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    const uint32_t ib = (1u << (l0 + j)) - 1 + (sb << j);
+#pragma unroll
+    for (int g = 0; g < (1 << j); ++g) t[(1 << j) - 1 + g] = stw[ib + g];
+  }
+}
+
+// One split stage of the block pass on row and vector. FIRST: elements come from global
+// memory (twiddles too); otherwise from LDS. DEEPEST: the stage also forms the leaf
+// products and runs its merge levels, leaving y in sa (or writing dst if also FIRST).
 template <class Ring, int LOGR, int K, bool FIRST, bool DEEPEST, class SrcA, class SrcX, class Dst>
 __device__ __forceinline__ void block_split_stage(const PassArgs<Ring>& A, const TilePos& P, const Ring& R, uint32_t rsel,
                                                   typename Ring::Tw const* tw, typename Ring::Tw const* twi,
+                                                  const typename Ring::Tw* stw, const DeepTw<Ring>& D,
                                                   typename Ring::T* sa, typename Ring::T* sx, uint32_t l0, uint32_t ltid,
                                                   const SrcA& srca, const SrcX& srcx, const Dst& dst) {
   using T = typename Ring::T;
@@ -415,21 +566,27 @@ __device__ __forceinline__ void block_split_stage(const PassArgs<Ring>& A, const
   constexpr int E = 1 << K;
   constexpr int IPT = S::EPT / E;
   constexpr uint32_t ACTIVE = 1u << S::ACTIVE_LOG;
-  // Radix-16 deepest stages load one twiddle per level and derive the rest (see tu).
+  // the deepest stage of a multi-stage pass takes its first twiddles from D (radix 16)
+  constexpr bool FROM_D = DEEPEST && !FIRST;
   constexpr bool FIRSTS = DEEPEST && K == EPT_LOG;
+  static_assert(!FROM_D || K == EPT_LOG, "deepest stage of a multi-stage block pass is radix 16");
   T va[IPT][E], vx[IPT][E];
-  Tw t[IPT][FIRSTS ? K : E - 1];
-  Tw ti[DEEPEST ? IPT : 1][FIRSTS ? K : E - 1];
+  Tw t[FROM_D ? 1 : IPT][FIRSTS ? K : E - 1];
+  Tw ti[(DEEPEST && !FROM_D) ? IPT : 1][FIRSTS ? K : E - 1];
   Item it[IPT];
 #pragma unroll
   for (int u = 0; u < IPT; ++u) {
     it[u] = item_at(ltid + u * ACTIVE, LOGR, 0, l0, K);
-    if constexpr (FIRSTS) {
-      load_tw_first<Ring, K>(t[u], tw, A.d0, P.blk, l0, it[u].sb);
-      load_tw_first<Ring, K>(ti[u], twi, A.d0, P.blk, l0, it[u].sb);
-    } else {
-      load_tw<Ring, K>(t[u], tw, A.d0, P.blk, l0, it[u].sb);
-      if constexpr (DEEPEST) load_tw<Ring, K>(ti[u], twi, A.d0, P.blk, l0, it[u].sb);
+    if constexpr (FIRST) {
+      if constexpr (FIRSTS) {
+        load_tw_first<Ring, K>(t[u], tw, A.d0, P.blk, l0, it[u].sb);
+        load_tw_first<Ring, K>(ti[u], twi, A.d0, P.blk, l0, it[u].sb);
+      } else {
+        load_tw<Ring, K>(t[u], tw, A.d0, P.blk, l0, it[u].sb);
+        if constexpr (DEEPEST) load_tw<Ring, K>(ti[u], twi, A.d0, P.blk, l0, it[u].sb);
+      }
+    } else if constexpr (!DEEPEST) {
+      lds_tw<Ring, K>(t[u], stw, l0, it[u].sb);
     }
   }
 #pragma unroll
@@ -447,7 +604,9 @@ __device__ __forceinline__ void block_split_stage(const PassArgs<Ring>& A, const
     }
 #pragma unroll
   for (int u = 0; u < IPT; ++u) {
-    if constexpr (FIRSTS)
+    if constexpr (FROM_D)
+      split_levels_first<Ring, K>(R, va[u], vx[u], D.t, A.tu[rsel]);
+    else if constexpr (FIRSTS)
       split_levels_first<Ring, K>(R, va[u], vx[u], t[u], A.tu[rsel]);
     else
       split_levels<Ring, K, true, true>(R, va[u], vx[u], t[u]);
@@ -459,7 +618,9 @@ __device__ __forceinline__ void block_split_stage(const PassArgs<Ring>& A, const
       for (int i = 0; i < E; ++i) va[u][i] = R.leaf(va[u][i], vx[u][i]);
 #pragma unroll
     for (int u = 0; u < IPT; ++u) {
-      if constexpr (FIRSTS)
+      if constexpr (FROM_D)
+        merge_levels_first<Ring, K>(R, va[u], D.ti, A.tui[rsel]);
+      else if constexpr (FIRSTS)
         merge_levels_first<Ring, K>(R, va[u], ti[u], A.tui[rsel]);
       else
         merge_levels<Ring, K>(R, va[u], ti[u]);
@@ -479,39 +640,53 @@ __device__ __forceinline__ void block_split_stage(const PassArgs<Ring>& A, const
     }
 }
 
-template <class Ring, int LOGR, bool LAST, class Dst>
+// One radix-2^K merge stage of the block pass (twiddles from the LDS copy). LAST: write dst.
+template <class Ring, int LOGR, int K, bool LAST, class Dst>
 __device__ __forceinline__ void block_merge_stage(const PassArgs<Ring>& A, const TilePos& P, const Ring& R,
-                                                  typename Ring::Tw const* twi, typename Ring::T* sa, uint32_t l0,
+                                                  const typename Ring::Tw* stwi, typename Ring::T* sa, uint32_t l0,
                                                   uint32_t ltid, const Dst& dst) {
   using T = typename Ring::T;
   using Tw = typename Ring::Tw;
-  constexpr int K = EPT_LOG;
+  using S = BlockShape<LOGR>;
   constexpr int E = 1 << K;
-  const Item it = item_at(ltid, LOGR, 0, l0, K);
-  Tw t[E - 1];
-  load_tw<Ring, K>(t, twi, A.d0, P.blk, l0, it.sb);
-  T v[E];
+  constexpr int IPT = S::EPT / E;
+  constexpr uint32_t ACTIVE = 1u << S::ACTIVE_LOG;
+  Tw t[IPT][E - 1];
+  T v[IPT][E];
+  Item it[IPT];
 #pragma unroll
-  for (int i = 0; i < E; ++i) v[i] = sa[it.row0 + ((uint32_t)i << it.sh)];
-  merge_levels<Ring, K>(R, v, t);
-#pragma unroll
-  for (int i = 0; i < E; ++i) {
-    const uint32_t row = it.row0 + ((uint32_t)i << it.sh);
-    if constexpr (LAST)
-      dst(P.inst, P.base + row, A.final_store ? R.canon(v[i]) : v[i]);
-    else
-      sa[row] = v[i];
+  for (int u = 0; u < IPT; ++u) {
+    it[u] = item_at(ltid + u * ACTIVE, LOGR, 0, l0, K);
+    lds_tw<Ring, K>(t[u], stwi, l0, it[u].sb);
   }
+#pragma unroll
+  for (int u = 0; u < IPT; ++u)
+#pragma unroll
+    for (int i = 0; i < E; ++i) v[u][i] = sa[it[u].row0 + ((uint32_t)i << it[u].sh)];
+#pragma unroll
+  for (int u = 0; u < IPT; ++u) merge_levels<Ring, K>(R, v[u], t[u]);
+#pragma unroll
+  for (int u = 0; u < IPT; ++u)
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      const uint32_t row = it[u].row0 + ((uint32_t)i << it[u].sh);
+      if constexpr (LAST)
+        dst(P.inst, P.base + row, A.final_store ? R.canon(v[u][i]) : v[u][i]);
+      else
+        sa[row] = v[u][i];
+    }
 }
 
 // The block pass for workgroup-local virtual workgroups vwg0 .. vwg0 + GROUPS - 1 (NT threads;
-// each group of 2^(LOGR-4) threads owns one block).
+// each group of 2^(LOGR-4) threads owns one block). smem_raw holds block_lds_bytes<Ring,
+// LOGR, NT>() bytes.
 template <class Ring, int LOGR, int NT, class SrcA, class SrcX, class Dst>
 __device__ __forceinline__ void block_pass(const PassArgs<Ring>& A, uint32_t vwg0, unsigned char* smem_raw,
                                            const typename Ring::Params& rp0, const typename Ring::Params& rp1,
                                            const typename Ring::Params& rp2, const SrcA& srca, const SrcX& srcx,
                                            const Dst& dst) {
   using T = typename Ring::T;
+  using Tw = typename Ring::Tw;
   using S = BlockShape<LOGR, NT>;
   const uint32_t group = threadIdx.x >> S::ACTIVE_LOG;
   const uint32_t ltid = threadIdx.x & ((1u << S::ACTIVE_LOG) - 1);
@@ -519,11 +694,13 @@ __device__ __forceinline__ void block_pass(const PassArgs<Ring>& A, uint32_t vwg
   const bool active = group < S::GROUPS && vwg < A.tiles * A.ninst;
   T* sa = reinterpret_cast<T*>(smem_raw) + ((size_t)group << (LOGR + 1));
   T* sx = sa + ((size_t)1 << LOGR);
+  Tw* stw = reinterpret_cast<Tw*>(smem_raw + (size_t)S::GROUPS * 2 * (sizeof(T) << LOGR)) + (size_t)group * 2 * S::NTW;
+  Tw* stwi = stw + S::NTW;
   const TilePos P = tile_pos(A, active ? vwg : 0);
   uint32_t rsel;
   const Ring R = make_ring(A, P.inst, rp0, rp1, rp2, &rsel);
-  const typename Ring::Tw* tw = A.tw[rsel];
-  const typename Ring::Tw* twi = A.twi[rsel];
+  const Tw* tw = A.tw[rsel];
+  const Tw* twi = A.twi[rsel];
 
   if constexpr (LOGR == 0) {
     if (active) {
@@ -532,8 +709,22 @@ __device__ __forceinline__ void block_pass(const PassArgs<Ring>& A, uint32_t vwg
     }
   } else {
     constexpr int NST = S::NST, K0 = S::K0;
+    DeepTw<Ring> D;
+    if constexpr (NST > 1) {
+      if (active) {
+        // LDS copy of the twiddles above the deepest stage: level l of the block is the
+        // contiguous heap range [2^(d0+l) + blk 2^l, + 2^l)
+        for (uint32_t e = ltid; e < (uint32_t)S::NTW; e += 1u << S::ACTIVE_LOG) {
+          const uint32_t l = 31u - __clz(e + 1);
+          const uint32_t gi = (1u << (A.d0 + l)) + (P.blk << l) + (e + 1 - (1u << l));
+          stw[e] = tw[gi];
+          stwi[e] = twi[gi];
+        }
+        load_deep_tw<Ring, LOGR>(D, A, P, rsel, tw, twi, ltid);
+      }
+    }
     // split stages (first takes K0 levels), the deepest also runs leaf + its merge levels
-    if (active) block_split_stage<Ring, LOGR, K0, true, NST == 1>(A, P, R, rsel, tw, twi, sa, sx, 0, ltid, srca, srcx, dst);
+    if (active) block_split_stage<Ring, LOGR, K0, true, NST == 1>(A, P, R, rsel, tw, twi, stw, D, sa, sx, 0, ltid, srca, srcx, dst);
     if constexpr (NST > 1) {
       __syncthreads();
 #pragma unroll
@@ -541,46 +732,20 @@ __device__ __forceinline__ void block_pass(const PassArgs<Ring>& A, uint32_t vwg
         const uint32_t l0 = K0 + EPT_LOG * (s - 1);
         if (active) {
           if (s + 1 == NST)
-            block_split_stage<Ring, LOGR, EPT_LOG, false, true>(A, P, R, rsel, tw, twi, sa, sx, l0, ltid, srca, srcx, dst);
+            block_split_stage<Ring, LOGR, EPT_LOG, false, true>(A, P, R, rsel, tw, twi, stw, D, sa, sx, l0, ltid, srca, srcx, dst);
           else
-            block_split_stage<Ring, LOGR, EPT_LOG, false, false>(A, P, R, rsel, tw, twi, sa, sx, l0, ltid, srca, srcx, dst);
+            block_split_stage<Ring, LOGR, EPT_LOG, false, false>(A, P, R, rsel, tw, twi, stw, D, sa, sx, l0, ltid, srca, srcx, dst);
         }
         __syncthreads();
       }
-      // merge stages above the deepest one (all full radix-16 except the first stage's K0)
+      // merge stages above the deepest one, then the first stage's K0 levels to dst
 #pragma unroll
       for (int s = NST - 2; s >= 1; --s) {
         const uint32_t l0 = K0 + EPT_LOG * (s - 1);
-        if (active) block_merge_stage<Ring, LOGR, false>(A, P, R, twi, sa, l0, ltid, dst);
+        if (active) block_merge_stage<Ring, LOGR, EPT_LOG, false>(A, P, R, stwi, sa, l0, ltid, dst);
         __syncthreads();
       }
-      if (active) {
-        // stage 0 merge: K0 levels, items of 2^K0 elements, 16 / 2^K0 items per thread
-        constexpr int E = 1 << K0;
-        constexpr int IPT = S::EPT / E;
-        constexpr uint32_t ACTIVE = 1u << S::ACTIVE_LOG;
-        typename Ring::Tw t[IPT][E - 1];
-        T v[IPT][E];
-        Item it[IPT];
-#pragma unroll
-        for (int u = 0; u < IPT; ++u) {
-          it[u] = item_at(ltid + u * ACTIVE, LOGR, 0, 0, K0);
-          load_tw<Ring, K0>(t[u], twi, A.d0, P.blk, 0, it[u].sb);
-        }
-#pragma unroll
-        for (int u = 0; u < IPT; ++u)
-#pragma unroll
-          for (int i = 0; i < E; ++i) v[u][i] = sa[it[u].row0 + ((uint32_t)i << it[u].sh)];
-#pragma unroll
-        for (int u = 0; u < IPT; ++u) merge_levels<Ring, K0>(R, v[u], t[u]);
-#pragma unroll
-        for (int u = 0; u < IPT; ++u)
-#pragma unroll
-          for (int i = 0; i < E; ++i) {
-            const uint32_t row = it[u].row0 + ((uint32_t)i << it[u].sh);
-            dst(P.inst, P.base + row, A.final_store ? R.canon(v[u][i]) : v[u][i]);
-          }
-      }
+      if (active) block_merge_stage<Ring, LOGR, K0, true>(A, P, R, stwi, sa, 0, ltid, dst);
     }
   }
 }

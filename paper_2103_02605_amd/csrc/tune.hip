@@ -1,6 +1,7 @@
 // Autotuner for the pass schedule of one (ring, n): how many top levels are streamed
 // through HBM before the LDS-resident block pass, how large a top-pass tile is, and
-// whether the top passes use the XCD-aware tile order. Every candidate is timed with HIP
+// the top-pass flags (XCD-aware tile order; row and vector split jointly or in separate
+// workgroups). Every candidate is timed with HIP
 // events on the caller's stream over scratch buffers; the fastest is kept in the context.
 #include <hip/hip_runtime.h>
 
@@ -23,13 +24,13 @@ fcirc_status run_once(Ctx& c, fcirc_ring ring, int L, void* a, void* x, void* y,
 
 extern "C" {
 
-fcirc_status fcirc_set_schedule(fcirc_ctx* ctx, fcirc_ring ring, uint64_t n, int top_levels, int tile_log, int xcd) {
+fcirc_status fcirc_set_schedule(fcirc_ctx* ctx, fcirc_ring ring, uint64_t n, int top_levels, int tile_log, int flags) {
   if (!ctx || n == 0 || (n & (n - 1)) || ring < FCIRC_ZP_998244353 || ring > FCIRC_R32) return FCIRC_EINVAL;
-  if (top_levels < -1 || top_levels > 26 || tile_log < -1 || tile_log > 13 || xcd < 0 || xcd > 1) return FCIRC_EINVAL;
+  if (top_levels < -1 || top_levels > 26 || tile_log < -1 || tile_log > 13 || flags < 0 || flags > 3) return FCIRC_EINVAL;
   TuneVal v;
   v.top = top_levels;
   v.tile_log = tile_log;
-  v.xcd = xcd;
+  v.flags = flags;
   ctx->c.tuned[TuneKey{(int)ring, ilog2(n)}] = v;
   return FCIRC_OK;
 }
@@ -65,11 +66,11 @@ fcirc_status fcirc_tune(fcirc_ctx* ctx, uint64_t n, fcirc_ring ring, void* strea
       continue;
     }
     for (int tl = 10; tl <= 13; ++tl)
-      for (int xc = 0; xc <= 1; ++xc) {
+      for (int fl = 0; fl <= 3; ++fl) {
         TuneVal v;
         v.top = top;
         v.tile_log = tl;
-        v.xcd = xc;
+        v.flags = fl;
         cands.push_back(v);
       }
   }
@@ -114,17 +115,17 @@ fcirc_status fcirc_tune(fcirc_ctx* ctx, uint64_t n, fcirc_ring ring, void* strea
   (void)hipFree(x);
   (void)hipFree(y);
   if (std::getenv("FCIRC_LOG"))
-    std::fprintf(stderr, "fcirc_tune ring=%d L=%d: top=%d tile_log=%d xcd=%d (%.2f us/call)\n", (int)ring, L, bestv.top,
-                 bestv.tile_log, bestv.xcd, 1000.0 * best / reps);
+    std::fprintf(stderr, "fcirc_tune ring=%d L=%d: top=%d tile_log=%d flags=%d (%.2f us/call)\n", (int)ring, L, bestv.top,
+                 bestv.tile_log, bestv.flags, 1000.0 * best / reps);
   return st;
 }
 
-int fcirc_get_schedule(fcirc_ctx* ctx, fcirc_ring ring, uint64_t n, int* top_levels, int* tile_log, int* xcd) {
+int fcirc_get_schedule(fcirc_ctx* ctx, fcirc_ring ring, uint64_t n, int* top_levels, int* tile_log, int* flags) {
   if (!ctx || n == 0 || (n & (n - 1))) return -1;
   const Schedule S = schedule_for(ctx->c, ring, ilog2(n));
   if (top_levels) *top_levels = S.L - S.block_levels;
   if (tile_log) *tile_log = S.ntop ? S.top_r[0] + S.top_c[0] : -1;
-  if (xcd) *xcd = S.xcd;
+  if (flags) *flags = S.flags;
   return S.ntop;
 }
 

@@ -204,12 +204,68 @@ fcirc_status zp_tables(Ctx& c, uint32_t p, uint32_t f, int L, const ZpTables** o
       (void)hipFree(old.tw);
       (void)hipFree(old.twi);
       (void)hipFree(old.dU);
+      for (int l = 0; l < 27; ++l) {  // first-twiddle tables depend on (p, f, L) only
+        t.ft[l] = old.ft[l];
+        t.fti[l] = old.fti[l];
+      }
       old = t;
       *out = &old;
       return FCIRC_OK;
     }
   c.zp.push_back(t);
   *out = &c.zp.back();
+  return FCIRC_OK;
+}
+
+fcirc_status zp_first_tables(Ctx& c, const ZpTables* Tc, int L, const ZpTw** ft, const ZpTw** fti) {
+  ZpTables* T = const_cast<ZpTables*>(Tc);
+  *ft = *fti = nullptr;
+  if (L < 4 || L > 26) return FCIRC_OK;
+  if (!T->ft[L]) {
+    // g_{dd+j, b0 2^j} = r_{dd+j+1} rho_{dd+j}^{brev_dd(b0)} for the node b0 at depth dd = L - 4
+    const uint32_t p = T->p, f = T->f, gen = generator(p);
+    const int dd = L - 4;
+    std::vector<uint32_t> r(L + 1);
+    r[0] = f;
+    for (int k = 1; k <= L; ++k) {
+      if (f == 1)
+        r[k] = 1;
+      else if (f == p - 1)
+        r[k] = powmod(gen, (uint64_t)(p - 1) >> (k + 1), p);
+      else
+        r[k] = sqrtmod(r[k - 1], p, gen);
+    }
+    const size_t nb = (size_t)1 << dd;
+    std::vector<ZpTw> h(4 * nb), hi(4 * nb);
+    std::vector<uint32_t> pw(nb), pwi(nb);
+    for (int j = 0; j < 4; ++j) {
+      const uint32_t rho = powmod(gen, (uint64_t)(p - 1) >> (dd + j + 1), p), rhoi = invmod(rho, p);
+      pw[0] = pwi[0] = 1;
+      for (size_t k = 1; k < nb; ++k) {
+        pw[k] = mulmod(pw[k - 1], rho, p);
+        pwi[k] = mulmod(pwi[k - 1], rhoi, p);
+      }
+      const uint32_t rr = r[dd + j + 1], rri = invmod(rr, p);
+      for (size_t b0 = 0; b0 < nb; ++b0) {
+        const uint32_t k = brev((uint32_t)b0, dd);
+        h[4 * b0 + j] = shoup_tw(mulmod(rr, pw[k], p), p);
+        hi[4 * b0 + j] = shoup_tw(mulmod(rri, pwi[k], p), p);
+      }
+    }
+    ZpTw *d = nullptr, *di = nullptr;
+    if (hipMalloc(&d, 4 * nb * sizeof(ZpTw)) != hipSuccess || hipMalloc(&di, 4 * nb * sizeof(ZpTw)) != hipSuccess) {
+      (void)hipGetLastError();
+      if (d) (void)hipFree(d);
+      return FCIRC_ENOMEM;
+    }
+    if (hipMemcpy(d, h.data(), 4 * nb * sizeof(ZpTw), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(di, hi.data(), 4 * nb * sizeof(ZpTw), hipMemcpyHostToDevice) != hipSuccess)
+      return FCIRC_EDEVICE;
+    T->ft[L] = d;
+    T->fti[L] = di;
+  }
+  *ft = T->ft[L];
+  *fti = T->fti[L];
   return FCIRC_OK;
 }
 
@@ -231,7 +287,12 @@ fcirc_status zp_matvec(Ctx& c, const uint32_t* a, const uint32_t* x, uint32_t* y
   const ZpTw* twi[3] = {T->twi, T->twi, T->twi};
   const uint64_t n = (uint64_t)1 << L;
   const ZpTw* U[3] = {T->dU, T->dU, T->dU};
-  return hip_status(run_product<Zp>(c, S, count, rps, tw, twi, U, false, LdPlain<uint32_t>{a, n},
+  const ZpTw *ft = nullptr, *fti = nullptr;
+  st = zp_first_tables(c, T, L, &ft, &fti);
+  if (st != FCIRC_OK) return st;
+  const ZpTw* FT[3] = {ft, ft, ft};
+  const ZpTw* FTI[3] = {fti, fti, fti};
+  return hip_status(run_product<Zp>(c, S, count, rps, tw, twi, U, ft ? FT : nullptr, ft ? FTI : nullptr, false, LdPlain<uint32_t>{a, n},
                                     LdPlain<uint32_t>{x, n}, StPlain<uint32_t>{y, n}, y, (uint32_t*)c.ws, s));
 }
 

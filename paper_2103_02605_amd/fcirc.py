@@ -174,15 +174,19 @@ def tune(n: int, ring: int, device=None):
             "fcirc_tune")
 
 
-def set_schedule(n: int, ring: int, top_levels: int = -1, tile_log: int = -1, xcd: int = 1, device=None):
+SCHED_XCD = 1       # XCD-aware tile order in the top passes
+SCHED_SEPARATE = 2  # split passes take the row and the vector in separate workgroups
+
+
+def set_schedule(n: int, ring: int, top_levels: int = -1, tile_log: int = -1, flags: int = SCHED_XCD, device=None):
     """Fix the pass schedule for (ring, n): see fcirc_set_schedule in include/fcirc.h."""
-    L.check(L.lib().fcirc_set_schedule(context(device).handle, ring, n, top_levels, tile_log, xcd), "fcirc_set_schedule")
+    L.check(L.lib().fcirc_set_schedule(context(device).handle, ring, n, top_levels, tile_log, flags), "fcirc_set_schedule")
 
 
 def get_schedule(n: int, ring: int, device=None) -> dict:
-    top, tile, xcd = C.c_int(), C.c_int(), C.c_int()
-    ntop = L.lib().fcirc_get_schedule(context(device).handle, ring, n, C.byref(top), C.byref(tile), C.byref(xcd))
-    return {"top_passes": ntop, "top_levels": top.value, "tile_log": tile.value, "xcd": xcd.value}
+    top, tile, flags = C.c_int(), C.c_int(), C.c_int()
+    ntop = L.lib().fcirc_get_schedule(context(device).handle, ring, n, C.byref(top), C.byref(tile), C.byref(flags))
+    return {"top_passes": ntop, "top_levels": top.value, "tile_log": tile.value, "flags": flags.value}
 
 
 # -------------------------------------------------------------------------------------

@@ -198,7 +198,8 @@ def test_errors(F):
 
 @pytest.mark.parametrize("L", [14, 18, 21])
 def test_schedule_variants_bit_exact(F, L):
-    """Every top-pass tile size and tile order the tuner may pick gives the same bits."""
+    """Every top-pass tile size, tile order and row/vector grouping the tuner may pick gives
+    the same bits."""
     from paper_2103_02605_amd import _lib
     n = 1 << L
     a, x = W.modp_pair(n, P3, seed=L)
@@ -208,11 +209,11 @@ def test_schedule_variants_bit_exact(F, L):
     try:
         for top in (L - 13, L - 11, L - 9):
             for tile_log in (10, 11, 12, 13):
-                for xcd in (0, 1):
-                    F.set_schedule(n, ring, top, tile_log, xcd)
+                for flags in (0, 1, 2, 3):
+                    F.set_schedule(n, ring, top, tile_log, flags)
                     got = host_u32(F.matvec(dev(a), dev(x), f=1, p=P3))
                     if want is not None:
-                        np.testing.assert_array_equal(got, want, err_msg=f"{top} {tile_log} {xcd}")
+                        np.testing.assert_array_equal(got, want, err_msg=f"{top} {tile_log} {flags}")
                     if base is None:
                         base = got
                     np.testing.assert_array_equal(got, base)
