@@ -61,6 +61,35 @@ struct BatchArgs {
   typename Ring::Tw const* U;    // uniform radix-16 factors: tu[15] then tui[15]
 };
 
+// Data passed between workgroups (the top-split workspace and the block results) goes
+// through device-coherent accesses: relaxed agent-scope atomic loads and stores, which
+// read and write at the level shared by all XCDs. With every such store coherent, a
+// producer only has to wait for its stores to complete before it bumps a counter, and a
+// consumer only has to read the counter; neither needs an agent-scope fence, which on
+// this chip writes back or invalidates the whole L2 of an XCD.
+template <class T>
+struct Coh;
+template <>
+struct Coh<uint32_t> {
+  static __device__ __forceinline__ uint32_t ld(const uint32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  static __device__ __forceinline__ void st(uint32_t* p, uint32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+};
+template <>
+struct Coh<float2> {
+  static __device__ __forceinline__ float2 ld(const float2* p) {
+    const uint64_t u = __hip_atomic_load(reinterpret_cast<const uint64_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return make_float2(__uint_as_float((uint32_t)u), __uint_as_float((uint32_t)(u >> 32)));
+  }
+  static __device__ __forceinline__ void st(float2* p, float2 v) {
+    const uint64_t u = (uint64_t)__float_as_uint(v.x) | ((uint64_t)__float_as_uint(v.y) << 32);
+    __hip_atomic_store(reinterpret_cast<uint64_t*>(p), u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+};
+
 // Element access for one instance (uniform per workgroup).
 template <class T>
 struct LdInst {
@@ -79,36 +108,44 @@ struct StInstY {
   const BInst* insts;
   __device__ __forceinline__ void operator()(uint32_t inst, uint32_t i, T v) const { base[insts[inst].y + i] = v; }
 };
-template <class T>
-struct LdInstY {
-  const T* base;
-  const BInst* insts;
+// One large instance's y, written by its BLOCK items and read by its MERGE items (coherent),
+// or written plainly by the last merge pass.
+template <class T, bool COH>
+struct InstY {
+  T* p;  // y of the instance
   template <class R>
-  __device__ __forceinline__ T operator()(const R&, uint32_t inst, uint32_t i) const {
-    return base[insts[inst].y + i];
+  __device__ __forceinline__ T operator()(const R&, uint32_t, uint32_t i) const {
+    if constexpr (COH) return Coh<T>::ld(p + i);
+    else return p[i];
+  }
+  __device__ __forceinline__ void operator()(uint32_t, uint32_t i, T v) const {
+    if constexpr (COH) Coh<T>::st(p + i, v);
+    else p[i] = v;
   }
 };
-// Workspace of a large instance: row at [ws, ws + n), vector at [ws + n, ws + 2n).
+// Workspace of a large instance: row at [ws, ws + n), vector at [ws + n, ws + 2n) (coherent).
 template <class T>
-struct WsInst {
-  T* ws;
-  const BInst* insts;
-  int which;
+struct WsArr {
+  T* p;
   template <class R>
-  __device__ __forceinline__ T operator()(const R&, uint32_t inst, uint32_t i) const {
-    const BInst& b = insts[inst];
-    return ws[b.ws + ((uint64_t)which << b.L) + i];
-  }
-  __device__ __forceinline__ void operator()(uint32_t inst, uint32_t i, T v) const {
-    const BInst& b = insts[inst];
-    ws[b.ws + ((uint64_t)which << b.L) + i] = v;
-  }
+  __device__ __forceinline__ T operator()(const R&, uint32_t, uint32_t i) const { return Coh<T>::ld(p + i); }
+  __device__ __forceinline__ void operator()(uint32_t, uint32_t i, T v) const { Coh<T>::st(p + i, v); }
+};
+// Plain input of one instance.
+template <class T>
+struct InstIn {
+  const T* p;
+  template <class R>
+  __device__ __forceinline__ T operator()(const R&, uint32_t, uint32_t i) const { return p[i]; }
 };
 
+// Counters: every thread waits for its own (coherent) stores, the workgroup meets, then one
+// thread publishes with a relaxed agent-scope add. A waiter polls with relaxed loads; the
+// workgroup barrier after the poll orders the item's loads after it.
 __device__ __forceinline__ void wait_count(uint32_t* c, uint32_t target, uint32_t* status) {
   if (threadIdx.x == 0) {
     uint32_t spins = 0;
-    while (__hip_atomic_load(c, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    while (__hip_atomic_load(c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
       __builtin_amdgcn_s_sleep(2);
       if (++spins > SPIN_LIMIT) {
         atomicOr(status, 2u);
@@ -117,13 +154,12 @@ __device__ __forceinline__ void wait_count(uint32_t* c, uint32_t target, uint32_
     }
   }
   __syncthreads();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
 }
 
 __device__ __forceinline__ void signal_done(uint32_t* c) {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __builtin_amdgcn_s_waitcnt(0);  // this thread's stores have completed
   __syncthreads();
-  if (threadIdx.x == 0) __hip_atomic_fetch_add(c, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  if (threadIdx.x == 0) __hip_atomic_fetch_add(c, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 template <class Ring>
@@ -142,7 +178,7 @@ __device__ __forceinline__ PassArgs<Ring> batch_pass_args(const BatchArgs<Ring>&
 }
 
 template <class Ring, int L>
-__device__ __forceinline__ void do_full(const BatchArgs<Ring>& B, const BItem& it, unsigned char* smem) {
+__device__ __forceinline__ void do_full(const BatchArgs<Ring>& B, const BItem& it, uint32_t tid, unsigned char* smem) {
   PassArgs<Ring> A = batch_pass_args(B);
   A.logn = L;
   A.d0 = 0;
@@ -152,12 +188,12 @@ __device__ __forceinline__ void do_full(const BatchArgs<Ring>& B, const BItem& i
   A.ninst = it.inst + it.arg;
   A.final_store = 1;
   const typename Ring::Params& rp = B.rp[L];
-  block_pass<Ring, L, BT>(A, it.inst, smem, rp, rp, rp, LdInst<typename Ring::T>{B.a, B.insts, 0},
+  block_pass<Ring, L, BT>(A, it.inst, tid, smem, rp, rp, rp, LdInst<typename Ring::T>{B.a, B.insts, 0},
                           LdInst<typename Ring::T>{B.x, B.insts, 1}, StInstY<typename Ring::T>{B.y, B.insts});
 }
 
 template <class Ring, int R>
-__device__ __forceinline__ void do_split(const BatchArgs<Ring>& B, const BItem& it, unsigned char* smem) {
+__device__ __forceinline__ void do_split(const BatchArgs<Ring>& B, const BItem& it, uint32_t tid, unsigned char* smem) {
   const uint32_t L = it.L;
   PassArgs<Ring> A = batch_pass_args(B);
   A.logn = L;
@@ -169,15 +205,16 @@ __device__ __forceinline__ void do_split(const BatchArgs<Ring>& B, const BItem& 
   A.ninst = 1;
   A.final_store = 0;
   TilePos P = tile_pos(A, it.arg);
-  P.inst = it.inst;
+  P.inst = 0;
   const Ring Rg(B.rp[L]);
   using T = typename Ring::T;
-  split_pass<Ring, R>(A, P, Rg, 0, BT, reinterpret_cast<T*>(smem), LdInst<T>{B.a, B.insts, 0}, LdInst<T>{B.x, B.insts, 1},
-                      WsInst<T>{B.ws, B.insts, 0}, WsInst<T>{B.ws, B.insts, 1});
+  const BInst bi = B.insts[it.inst];
+  split_pass<Ring, R>(A, P, Rg, 0, BT, tid, reinterpret_cast<T*>(smem), InstIn<T>{B.a + bi.a}, InstIn<T>{B.x + bi.x},
+                      WsArr<T>{B.ws + bi.ws}, WsArr<T>{B.ws + bi.ws + (1ull << L)});
 }
 
 template <class Ring, int R>
-__device__ __forceinline__ void do_merge(const BatchArgs<Ring>& B, const BItem& it, unsigned char* smem) {
+__device__ __forceinline__ void do_merge(const BatchArgs<Ring>& B, const BItem& it, uint32_t tid, unsigned char* smem) {
   const uint32_t L = it.L;
   PassArgs<Ring> A = batch_pass_args(B);
   A.logn = L;
@@ -188,14 +225,15 @@ __device__ __forceinline__ void do_merge(const BatchArgs<Ring>& B, const BItem& 
   A.ninst = 1;
   A.final_store = 1;
   TilePos P = tile_pos(A, it.arg);
-  P.inst = it.inst;
+  P.inst = 0;
   const Ring Rg(B.rp[L]);
   using T = typename Ring::T;
-  merge_pass<Ring, R>(A, P, Rg, 0, BT, reinterpret_cast<T*>(smem), LdInstY<T>{B.y, B.insts}, StInstY<T>{B.y, B.insts});
+  T* y = B.y + B.insts[it.inst].y;
+  merge_pass<Ring, R>(A, P, Rg, 0, BT, tid, reinterpret_cast<T*>(smem), InstY<T, true>{y}, InstY<T, false>{y});
 }
 
 template <class Ring>
-__device__ __forceinline__ void do_block(const BatchArgs<Ring>& B, const BItem& it, unsigned char* smem) {
+__device__ __forceinline__ void do_block(const BatchArgs<Ring>& B, const BItem& it, uint32_t tid, unsigned char* smem) {
   const uint32_t L = it.L;
   PassArgs<Ring> A = batch_pass_args(B);
   A.logn = L;
@@ -203,13 +241,14 @@ __device__ __forceinline__ void do_block(const BatchArgs<Ring>& B, const BItem& 
   A.logr = BLOCK_LOG;
   A.logc = 0;
   A.tiles = 1u << A.d0;
-  A.ninst = it.inst + 1;
+  A.ninst = 1;
   A.final_store = 0;
   using T = typename Ring::T;
   const typename Ring::Params& rp = B.rp[L];
-  // virtual workgroup (block it.arg of instance it.inst) = inst * tiles + block
-  block_pass<Ring, BLOCK_LOG, BT>(A, it.inst * A.tiles + it.arg, smem, rp, rp, rp, WsInst<T>{B.ws, B.insts, 0},
-                                  WsInst<T>{B.ws, B.insts, 1}, StInstY<T>{B.y, B.insts});
+  const BInst bi = B.insts[it.inst];
+  // virtual workgroup = block it.arg of the (single) instance
+  block_pass<Ring, BLOCK_LOG, BT>(A, it.arg, tid, smem, rp, rp, rp, WsArr<T>{B.ws + bi.ws}, WsArr<T>{B.ws + bi.ws + (1ull << L)},
+                                  InstY<T, true>{B.y + bi.y});
 }
 
 template <class Ring>
@@ -223,10 +262,14 @@ __global__ void __launch_bounds__(BT) k_batched(BatchArgs<Ring> B) {
     __syncthreads();
     if (id >= B.nitems) break;
     const BItem it = B.items[id];
+    // A fresh, opaque copy of the thread index per item: index arithmetic then stays inside
+    // the item's own code path instead of being hoisted out of the loop for every path.
+    uint32_t tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
     if (it.type == IT_FULL) {
       switch (it.L) {
 #define FCIRC_FULL(l) \
-  case l: do_full<Ring, l>(B, it, smem); break;
+  case l: do_full<Ring, l>(B, it, tid, smem); break;
         FCIRC_FULL(0) FCIRC_FULL(1) FCIRC_FULL(2) FCIRC_FULL(3) FCIRC_FULL(4) FCIRC_FULL(5) FCIRC_FULL(6)
         FCIRC_FULL(7) FCIRC_FULL(8) FCIRC_FULL(9) FCIRC_FULL(10) FCIRC_FULL(11) FCIRC_FULL(12)
 #undef FCIRC_FULL
@@ -234,25 +277,25 @@ __global__ void __launch_bounds__(BT) k_batched(BatchArgs<Ring> B) {
       }
     } else if (it.type == IT_SPLIT) {
       switch (it.L - BLOCK_LOG) {
-        case 1: do_split<Ring, 1>(B, it, smem); break;
-        case 2: do_split<Ring, 2>(B, it, smem); break;
-        case 3: do_split<Ring, 3>(B, it, smem); break;
-        case 4: do_split<Ring, 4>(B, it, smem); break;
+        case 1: do_split<Ring, 1>(B, it, tid, smem); break;
+        case 2: do_split<Ring, 2>(B, it, tid, smem); break;
+        case 3: do_split<Ring, 3>(B, it, tid, smem); break;
+        case 4: do_split<Ring, 4>(B, it, tid, smem); break;
         default: break;
       }
       signal_done(&B.cnt[2 * B.insts[it.inst].big]);
     } else if (it.type == IT_BLOCK) {
       const uint32_t tiles = 1u << (it.L - TILE_LOG);
       wait_count(&B.cnt[2 * B.insts[it.inst].big], 2 * tiles, B.status);
-      do_block<Ring>(B, it, smem);
+      do_block<Ring>(B, it, tid, smem);
       signal_done(&B.cnt[2 * B.insts[it.inst].big + 1]);
     } else {
       wait_count(&B.cnt[2 * B.insts[it.inst].big + 1], 1u << (it.L - BLOCK_LOG), B.status);
       switch (it.L - BLOCK_LOG) {
-        case 1: do_merge<Ring, 1>(B, it, smem); break;
-        case 2: do_merge<Ring, 2>(B, it, smem); break;
-        case 3: do_merge<Ring, 3>(B, it, smem); break;
-        case 4: do_merge<Ring, 4>(B, it, smem); break;
+        case 1: do_merge<Ring, 1>(B, it, tid, smem); break;
+        case 2: do_merge<Ring, 2>(B, it, tid, smem); break;
+        case 3: do_merge<Ring, 3>(B, it, tid, smem); break;
+        case 4: do_merge<Ring, 4>(B, it, tid, smem); break;
         default: break;
       }
     }

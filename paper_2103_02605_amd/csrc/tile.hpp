@@ -239,7 +239,7 @@ __device__ __forceinline__ Ring make_ring(const PassArgs<Ring>& A, uint32_t inst
 template <class Ring, int K, bool FIRST, bool LAST, bool IS_X, class Src, class Dst>
 __device__ __forceinline__ void split_stage(const PassArgs<Ring>& A, const TilePos& P, const Ring& R,
                                             typename Ring::Tw const* tw, typename Ring::T* lds, uint32_t l0,
-                                            uint32_t nt, const Src& src, const Dst& dst) {
+                                            uint32_t nt, uint32_t tid, const Src& src, const Dst& dst) {
   using T = typename Ring::T;
   using Tw = typename Ring::Tw;
   constexpr int IPT = 1 << (EPT_LOG - K);
@@ -249,7 +249,7 @@ __device__ __forceinline__ void split_stage(const PassArgs<Ring>& A, const TileP
   Item it[IPT];
 #pragma unroll
   for (int u = 0; u < IPT; ++u) {
-    it[u] = item_at(threadIdx.x + u * nt, A.logr, A.logc, l0, K);
+    it[u] = item_at(tid + u * nt, A.logr, A.logc, l0, K);
     load_tw<Ring, K>(t[u], tw, A.d0, P.blk, l0, it[u].sb);
   }
 #pragma unroll
@@ -299,17 +299,17 @@ __device__ __forceinline__ void static_for(F&& f) {
 // ---------------------------------------------------------------------------------------
 template <class Ring, int R, class SrcA, class SrcX, class Dst>
 __device__ __forceinline__ void split_pass(const PassArgs<Ring>& A, const TilePos& P, const Ring& Rg, uint32_t rsel,
-                                           uint32_t nt, typename Ring::T* lds, const SrcA& srca, const SrcX& srcx,
-                                           const Dst& dsta, const Dst& dstx) {
+                                           uint32_t nt, uint32_t tid, typename Ring::T* lds, const SrcA& srca,
+                                           const SrcX& srcx, const Dst& dsta, const Dst& dstx) {
   using SP = StagePlan<R>;
   const typename Ring::Tw* tw = A.tw[rsel];
   static_for<SP::NST>([&](auto sc) {
     constexpr int s = decltype(sc)::value;
     constexpr bool first = s == 0, last = s + 1 == SP::NST;
     if (P.arr == 0)
-      split_stage<Ring, SP::k(s), first, last, false>(A, P, Rg, tw, lds, SP::l0(s), nt, srca, dsta);
+      split_stage<Ring, SP::k(s), first, last, false>(A, P, Rg, tw, lds, SP::l0(s), nt, tid, srca, dsta);
     else
-      split_stage<Ring, SP::k(s), first, last, true>(A, P, Rg, tw, lds, SP::l0(s), nt, srcx, dstx);
+      split_stage<Ring, SP::k(s), first, last, true>(A, P, Rg, tw, lds, SP::l0(s), nt, tid, srcx, dstx);
     if constexpr (!last) __syncthreads();
   });
 }
@@ -321,7 +321,8 @@ __global__ void __launch_bounds__(512) k_split(PassArgs<Ring> A, typename Ring::
   const TilePos P = tile_pos(A, A.xcd ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x);
   uint32_t rsel;
   const Ring Rg = make_ring(A, P.inst, rp0, rp1, rp2, &rsel);
-  split_pass<Ring, R>(A, P, Rg, rsel, blockDim.x, reinterpret_cast<typename Ring::T*>(smem_raw), srca, srcx, dsta, dstx);
+  split_pass<Ring, R>(A, P, Rg, rsel, blockDim.x, threadIdx.x, reinterpret_cast<typename Ring::T*>(smem_raw), srca, srcx,
+                      dsta, dstx);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -333,8 +334,8 @@ __global__ void __launch_bounds__(512) k_split(PassArgs<Ring> A, typename Ring::
 template <class Ring, int K, bool FIRST, bool LAST, class SrcA, class SrcX, class Dst>
 __device__ __forceinline__ void split_stage_ax(const PassArgs<Ring>& A, const TilePos& P, const Ring& R,
                                                typename Ring::Tw const* tw, typename Ring::T* lda, typename Ring::T* ldx,
-                                               uint32_t l0, uint32_t nt, const SrcA& srca, const SrcX& srcx,
-                                               const Dst& dsta, const Dst& dstx) {
+                                               uint32_t l0, uint32_t nt, uint32_t tid, const SrcA& srca,
+                                               const SrcX& srcx, const Dst& dsta, const Dst& dstx) {
   using T = typename Ring::T;
   using Tw = typename Ring::Tw;
   constexpr int IPT = 1 << (EPT_LOG - K);
@@ -344,7 +345,7 @@ __device__ __forceinline__ void split_stage_ax(const PassArgs<Ring>& A, const Ti
   Item it[IPT];
 #pragma unroll
   for (int u = 0; u < IPT; ++u) {
-    it[u] = item_at(threadIdx.x + u * nt, A.logr, A.logc, l0, K);
+    it[u] = item_at(tid + u * nt, A.logr, A.logc, l0, K);
     load_tw<Ring, K>(t[u], tw, A.d0, P.blk, l0, it[u].sb);
   }
 #pragma unroll
@@ -410,7 +411,8 @@ __global__ void __launch_bounds__(512) k_split_ax(PassArgs<Ring> A, typename Rin
   static_for<SP::NST>([&](auto sc) {
     constexpr int s = decltype(sc)::value;
     constexpr bool first = s == 0, last = s + 1 == SP::NST;
-    split_stage_ax<Ring, SP::k(s), first, last>(A, P, Rg, tw, lda, ldx, SP::l0(s), blockDim.x, srca, srcx, dsta, dstx);
+    split_stage_ax<Ring, SP::k(s), first, last>(A, P, Rg, tw, lda, ldx, SP::l0(s), blockDim.x, threadIdx.x, srca, srcx,
+                                                dsta, dstx);
     if constexpr (!last) __syncthreads();
   });
 }
@@ -421,7 +423,7 @@ __global__ void __launch_bounds__(512) k_split_ax(PassArgs<Ring> A, typename Rin
 template <class Ring, int K, bool FIRST, bool LAST, class Src, class Dst>
 __device__ __forceinline__ void merge_stage(const PassArgs<Ring>& A, const TilePos& P, const Ring& R,
                                             typename Ring::Tw const* twi, typename Ring::T* lds, uint32_t l0,
-                                            uint32_t nt, const Src& src, const Dst& dst) {
+                                            uint32_t nt, uint32_t tid, const Src& src, const Dst& dst) {
   using T = typename Ring::T;
   using Tw = typename Ring::Tw;
   constexpr int IPT = 1 << (EPT_LOG - K);
@@ -431,7 +433,7 @@ __device__ __forceinline__ void merge_stage(const PassArgs<Ring>& A, const TileP
   Item it[IPT];
 #pragma unroll
   for (int u = 0; u < IPT; ++u) {
-    it[u] = item_at(threadIdx.x + u * nt, A.logr, A.logc, l0, K);
+    it[u] = item_at(tid + u * nt, A.logr, A.logc, l0, K);
     load_tw<Ring, K>(t[u], twi, A.d0, P.blk, l0, it[u].sb);
   }
 #pragma unroll
@@ -464,13 +466,13 @@ __device__ __forceinline__ void merge_stage(const PassArgs<Ring>& A, const TileP
 // ---------------------------------------------------------------------------------------
 template <class Ring, int R, class Src, class Dst>
 __device__ __forceinline__ void merge_pass(const PassArgs<Ring>& A, const TilePos& P, const Ring& Rg, uint32_t rsel,
-                                           uint32_t nt, typename Ring::T* lds, const Src& src, const Dst& dst) {
+                                           uint32_t nt, uint32_t tid, typename Ring::T* lds, const Src& src, const Dst& dst) {
   using SP = StagePlan<R>;
   const typename Ring::Tw* twi = A.twi[rsel];
   static_for<SP::NST>([&](auto sc) {
     constexpr int s = SP::NST - 1 - decltype(sc)::value;  // deepest stage first
     constexpr bool first = s + 1 == SP::NST, last = s == 0;
-    merge_stage<Ring, SP::k(s), first, last>(A, P, Rg, twi, lds, SP::l0(s), nt, src, dst);
+    merge_stage<Ring, SP::k(s), first, last>(A, P, Rg, twi, lds, SP::l0(s), nt, tid, src, dst);
     if constexpr (!last) __syncthreads();
   });
 }
@@ -482,7 +484,7 @@ __global__ void __launch_bounds__(512) k_merge(PassArgs<Ring> A, typename Ring::
   const TilePos P = tile_pos(A, A.xcd ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x);
   uint32_t rsel;
   const Ring Rg = make_ring(A, P.inst, rp0, rp1, rp2, &rsel);
-  merge_pass<Ring, R>(A, P, Rg, rsel, blockDim.x, reinterpret_cast<typename Ring::T*>(smem_raw), src, dst);
+  merge_pass<Ring, R>(A, P, Rg, rsel, blockDim.x, threadIdx.x, reinterpret_cast<typename Ring::T*>(smem_raw), src, dst);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -679,17 +681,17 @@ __device__ __forceinline__ void block_merge_stage(const PassArgs<Ring>& A, const
 
 // The block pass for workgroup-local virtual workgroups vwg0 .. vwg0 + GROUPS - 1 (NT threads;
 // each group of 2^(LOGR-4) threads owns one block). smem_raw holds block_lds_bytes<Ring,
-// LOGR, NT>() bytes.
+// LOGR, NT>() bytes. tid is the thread's index in the workgroup.
 template <class Ring, int LOGR, int NT, class SrcA, class SrcX, class Dst>
-__device__ __forceinline__ void block_pass(const PassArgs<Ring>& A, uint32_t vwg0, unsigned char* smem_raw,
+__device__ __forceinline__ void block_pass(const PassArgs<Ring>& A, uint32_t vwg0, uint32_t tid, unsigned char* smem_raw,
                                            const typename Ring::Params& rp0, const typename Ring::Params& rp1,
                                            const typename Ring::Params& rp2, const SrcA& srca, const SrcX& srcx,
                                            const Dst& dst) {
   using T = typename Ring::T;
   using Tw = typename Ring::Tw;
   using S = BlockShape<LOGR, NT>;
-  const uint32_t group = threadIdx.x >> S::ACTIVE_LOG;
-  const uint32_t ltid = threadIdx.x & ((1u << S::ACTIVE_LOG) - 1);
+  const uint32_t group = tid >> S::ACTIVE_LOG;
+  const uint32_t ltid = tid & ((1u << S::ACTIVE_LOG) - 1);
   const uint32_t vwg = vwg0 + group;
   const bool active = group < S::GROUPS && vwg < A.tiles * A.ninst;
   T* sa = reinterpret_cast<T*>(smem_raw) + ((size_t)group << (LOGR + 1));
@@ -756,7 +758,7 @@ __global__ void __launch_bounds__(BlockShape<LOGR>::NT) k_block(PassArgs<Ring> A
                                                                  SrcA srca, SrcX srcx, Dst dst) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   using S = BlockShape<LOGR>;
-  block_pass<Ring, LOGR, S::NT>(A, blockIdx.x * S::GROUPS, smem_raw, rp0, rp1, rp2, srca, srcx, dst);
+  block_pass<Ring, LOGR, S::NT>(A, blockIdx.x * S::GROUPS, threadIdx.x, smem_raw, rp0, rp1, rp2, srca, srcx, dst);
 }
 
 }  // namespace fcirc
