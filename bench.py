@@ -4,7 +4,7 @@
 Headline workload: one f-circulant product over Z/998244353 of size n = 2^21 with f = 1
 (defining row a and vector x uniform in [0, p), seed 3). One step = one fcirc_matvec
 call, i.e. the whole path: top split passes -> LDS block pass -> top merge passes.
-Inputs rotate over 16 resident (a, x, y) sets (384 MiB, more than the 256 MB
+Inputs rotate over 24 resident (a, x, y) sets (576 MiB, more than twice the 256 MB
 Infinity Cache), so each step reads its inputs from HBM.
 
 Printed (rank 0, one JSON line): throughput in output coefficients per second, the
@@ -32,11 +32,13 @@ HBM_PEAK_GBS = 8000.0
 # 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz: 32-bit VALU lane-operations per second (T/s)
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 
-# Algorithmic cost model (lane-operations): one modular multiply by a precomputed constant
-# (Shoup: mul_hi, mul_lo, mad) = 3, one lazy modular add/sub = 1, so one butterfly pair =
-# 3 + 2 = 5 and one coefficient per level per transform = 2.5; the leaf (product of two
-# variables, Montgomery, times the constant 1/n) = 5 + 3 = 8.
-OPS_PER_COEF_LEVEL = 2.5
+# Algorithmic cost model (lane-operations), from the operation counts of a product of
+# length n = 2^L: (1.5 L + 1) n modular multiplies and 3 L n modular additions. A multiply
+# by a precomputed constant (Shoup: mul_hi, mul_lo, mul_lo, sub) = 4, a lazy modular
+# add/sub (add, conditional correction) = 2; one coefficient per level per transform does
+# half a multiply and one add/sub = 4; the leaf (product of two variables, then the
+# constant 1/n) = 2 multiplies = 8. For n = 2^21 that is 3 * 21 * 4 + 8 = 260 per coefficient.
+OPS_PER_COEF_LEVEL = 4.0
 OPS_LEAF = 8.0
 # Schedule bytes per coefficient of each kernel (uint32 data): split reads a, x and writes
 # both; the block reads both and writes y; the merge reads and writes y.
@@ -93,7 +95,7 @@ def time_steps(torch, fn, steps, warmup):
     return e0.elapsed_time(e1) / steps  # ms per step
 
 
-def headline(torch, F, W, steps, warmup, nsets=16):
+def headline(torch, F, W, steps, warmup, nsets=24):
     L = 21
     n = 1 << L
     sets = []
@@ -107,6 +109,15 @@ def headline(torch, F, W, steps, warmup, nsets=16):
         F.matvec(a, x, f=1, p=P1, out=y)
 
     ms = time_steps(torch, step, steps, warmup)
+    # per-step spread (separate pass: one event pair per step)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(100)]
+    for i, (e0, e1) in enumerate(evs):
+        e0.record()
+        step(i)
+        e1.record()
+    torch.cuda.synchronize()
+    per = sorted(e0.elapsed_time(e1) * 1e3 for e0, e1 in evs)
+    spread = {"median_us": round(per[len(per) // 2], 2), "min_us": round(per[0], 2), "steps": len(per)}
     # per-kernel durations: HIP events around each kernel, on the stream it runs on
     F.set_timing(True)
     for i in range(steps):
@@ -114,7 +125,35 @@ def headline(torch, F, W, steps, warmup, nsets=16):
     stages = F.stage_times()
     F.set_timing(False)
     T = F.get_split(n, 0)
-    return n, ms, stages, T, sets
+    return n, ms, stages, T, spread
+
+
+def copy_ceiling(torch) -> float:
+    """GB/s (read + write) of a plain 64 MiB device copy: the same-box HBM reference."""
+    src = torch.ones(1 << 24, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    ms = time_steps(torch, lambda i: dst.copy_(src), 50, 5)
+    return 2 * src.numel() * 4 / (ms * 1e-3) / 1e9
+
+
+def c1_latency(torch, F, W):
+    """n = 1024 over Z/998244353 (seeds 1 and 2 for f = 1 and f = p - 1): one call per
+    product, and 1024 products of that size (seed 11) in one batched launch."""
+    from paper_2103_02605_amd.batched import BatchPlan
+    out = {}
+    for f, seed, name in ((1, W.SEED_C1_CYCLIC, "f1"), (P1 - 1, W.SEED_C1_NEGACYCLIC, "f_pm1")):
+        a, x = W.modp_pair(1024, P1, seed=seed)
+        ta, tx = torch.from_numpy(a.view(np.int32)).cuda(), torch.from_numpy(x.view(np.int32)).cuda()
+        ty = torch.empty_like(ta)
+        ms = time_steps(torch, lambda i: F.matvec(ta, tx, f=f, p=P1, out=ty), 200, 20)
+        out[f"plain_us_per_call_{name}"] = round(ms * 1e3, 3)
+    ab, xb = W.modp_batch(1024, 1024, P1)
+    al, xl = list(ab), list(xb)
+    plan = BatchPlan(al, xl, p=P1, f=1)
+    ms = time_steps(torch, lambda i: plan.run(), 50, 5)
+    out["batched_1024x1024_us_per_product"] = round(ms * 1e3 / 1024, 4)
+    out["batched_1024x1024_us_per_launch"] = round(ms * 1e3, 2)
+    return out
 
 
 def secondary(torch, F, W, quick: bool):
@@ -131,6 +170,7 @@ def secondary(torch, F, W, quick: bool):
     c = torch.empty(1 << 21, dtype=torch.int16, device="cuda")
     ms = time_steps(torch, lambda i: F.bigint_mul(ta, tb, out=c), 20 if quick else 100, 5)
     out["bigint_mul_2x2^24bit"] = {"ms": ms, "Glimb_per_s": (1 << 21) / ms / 1e6}
+    out["c1_n1024_latency"] = c1_latency(torch, F, W)
     out["batched_c64_4096"] = batched_vs_plain(torch, F, W, quick)
     out["layer_fwd_bwd_256x2^14"] = layer_vs_plain(torch, F, W, quick)
     return out
@@ -226,7 +266,8 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    n, ms, stages, T, _ = headline(torch, F, W, args.steps, args.warmup)
+    n, ms, stages, T, spread = headline(torch, F, W, args.steps, args.warmup)
+    copy_gbs = copy_ceiling(torch)
     value = n / ms / 1e6  # Gcoeff/s
     L = 21
     B = L - T
@@ -249,15 +290,16 @@ def main():
                 "per_unit": f"{ops_coef[dom]} lane-ops per coefficient x {n} coefficients per launch",
                 "hbm": {"achieved_GBs": round(12 * n / (ms * 1e-3) / 1e9, 1), "peak_GBs": HBM_PEAK_GBS,
                         "frac": round(12 * n / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                        "copy_ceiling_GBs": round(copy_gbs, 1),
                         "per_unit": "12 compulsory bytes per coefficient (a, x read, y written), whole step"},
                 "kernels": {k: {kk: round(vv, 3) for kk, vv in v.items()} for k, v in kern.items()},
                 "source_digest": digest}
     line = {"metric": "Gcoeff/s for n=2^21 mod-p product, % HBM roofline; batched/fwd+bwd vs plain",
             "value": round(value, 3), "unit": "Gcoeff/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-            "ms_per_step": round(ms, 5), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "ms_per_step": round(ms, 5), "step_spread": spread, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
             "dtype": "u32", "data": "synthetic",
             "config": {"workload": "fcirc_matvec over Z/998244353, n=2^21, f=1, a and x uniform in [0,p) (seed 3), "
-                                   "16 rotating input sets", "n": n, "ring": "Z/998244353", "f": 1,
+                                   "24 rotating input sets", "n": n, "ring": "Z/998244353", "f": 1,
                        "split": {"top_levels": T, "block_levels": B}},
             "roofline": roofline}
     if not args.no_secondary:

@@ -3,6 +3,7 @@
 // batch of equal-size products) as top split passes -> block pass -> top merge passes.
 #pragma once
 #include <hip/hip_ext.h>
+#include <algorithm>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -241,13 +242,19 @@ inline Schedule make_schedule(int L, int elem_log, int top_levels, int tile_log_
   Schedule s;
   s.L = L;
   s.flags = flags;
-  const int block_max = elem_log == 2 ? 12 : 11;  // 32 KiB of LDS for row + vector
-  const int tile_max = 13;                        // 512 threads x 16 elements per workgroup
-  int tile_log = tile_log_in >= 0 ? tile_log_in : (elem_log == 2 ? 13 : 12);
+  // Largest block pass: row + vector of 2^B elements in LDS (64 KiB Z/p at B = 13, 64 KiB
+  // complex at B = 12) plus its staged twiddles.
+  const int block_max = elem_log == 2 ? 13 : 12;
+  const int tile_max = 13;  // 512 threads x 16 elements per workgroup
+  // Defaults measured on MI355X: at least 2^8 blocks (one per CU) once n allows it, blocks
+  // of at most 2^block_max and at least 2^10 elements; top-pass tiles of 2^(L-8) elements,
+  // within [2^11, 2^13], so that a top pass also has about 2^8 workgroups.
+  int tile_log = tile_log_in >= 0 ? tile_log_in : std::min(13, std::max(11, L - 8));
   if (tile_log > tile_max) tile_log = tile_max;
   if (tile_log < 4) tile_log = 4;
   const int top_max = 10;
-  int T = top_levels >= 0 ? top_levels : (L > block_max ? L - block_max : 0);
+  int T = top_levels;
+  if (T < 0) T = L <= 12 ? 0 : std::max(L - block_max, std::min(8, L - 10));
   if (T > L) T = L;
   if (L < 5) T = 0;                                // too small for a column tile of 16 elements
   if (L - T > 13 - (elem_log - 2)) T = L - (13 - (elem_log - 2));  // block must fit LDS
