@@ -16,6 +16,7 @@
 // vector side is conjugated, which leaves sum(C(gy_0) x_0 + C(gy_1) x_1) in the real part.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 
 #include "host.hpp"
@@ -210,6 +211,138 @@ hipError_t merge_leaves(Ctx& c, const C32Tables* T, int L, uint32_t count, float
   return hipSuccess;
 }
 
+// The row's leaves, shared by every instance (optionally conjugated).
+struct LeafRow {
+  const float2* p;
+  template <bool CONJ>
+  __device__ __forceinline__ float2 get(uint32_t i) const {
+    const float2 v = p[i];
+    return CONJ ? make_float2(v.x, -v.y) : v;
+  }
+};
+
+// Levels [0, T) of `count` vectors (arr 1) or rows (arr 0): HBM tile passes of at most 10
+// levels, tiles of 2^12 elements.
+template <class Src>
+hipError_t split_top(Ctx& c, const C32Tables* T, int L, int top, uint32_t count, int arr, Src src, float2* out,
+                     hipStream_t s) {
+  const uint64_t n = 1ull << L;
+  const C32Params rp[3] = {{1.f}, {1.f}, {1.f}};
+  PassArgs<C32> A = layer_args(T, L, count);
+  A.arr0 = arr;
+  A.final_store = 0;
+  const LdPlain<float2> lo{out, n};
+  const StPlain<float2> so{out, n};
+  const int npass = (top + 9) / 10;
+  int d0 = 0;
+  for (int i = 0; i < npass; ++i) {
+    const int r = (top - d0) / (npass - i);
+    A.d0 = d0;
+    A.logr = r;
+    A.logc = std::min(12 - r, L - d0 - r);
+    A.tiles = (uint32_t)(n >> (A.logr + A.logc));
+    const size_t tile = (size_t)1 << (A.logr + A.logc);
+    const uint32_t grid = A.tiles * count, nt = (uint32_t)(tile >> EPT_LOG);
+    const hipError_t e = i == 0 ? split_pass_any(c, A, rp, src, so, grid, nt, tile * sizeof(float2), s)
+                                : split_pass_any(c, A, rp, lo, so, grid, nt, tile * sizeof(float2), s);
+    if (e != hipSuccess) return e;
+    d0 += r;
+  }
+  return hipSuccess;
+}
+
+// Merge levels [0, T) of `count` vectors in ws (deepest first); the last pass writes dst.
+template <class Dst>
+hipError_t merge_top(Ctx& c, const C32Tables* T, int L, int top, uint32_t count, float2* ws, Dst dst, hipStream_t s) {
+  const uint64_t n = 1ull << L;
+  const C32Params rp[3] = {{1.f}, {1.f}, {1.f}};
+  PassArgs<C32> A = layer_args(T, L, count);
+  const LdPlain<float2> lo{ws, n};
+  const StPlain<float2> so{ws, n};
+  const int npass = (top + 9) / 10;
+  int d0s[4], rs[4];
+  int d0 = 0;
+  for (int i = 0; i < npass; ++i) {
+    rs[i] = (top - d0) / (npass - i);
+    d0s[i] = d0;
+    d0 += rs[i];
+  }
+  for (int i = npass - 1; i >= 0; --i) {
+    A.d0 = d0s[i];
+    A.logr = rs[i];
+    A.logc = std::min(12 - rs[i], L - d0s[i] - rs[i]);
+    A.tiles = (uint32_t)(n >> (A.logr + A.logc));
+    A.final_store = i == 0;
+    const size_t tile = (size_t)1 << (A.logr + A.logc);
+    const uint32_t grid = A.tiles * count, nt = (uint32_t)(tile >> EPT_LOG);
+    const hipError_t e = i == 0 ? merge_pass_any(c, A, rp, lo, dst, grid, nt, tile * sizeof(float2), s)
+                                : merge_pass_any(c, A, rp, lo, so, grid, nt, tile * sizeof(float2), s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// Levels below `top` of every instance in one leaf-domain block launch: split the vector,
+// multiply by the row's leaves (conjugated if conj) and 1/n, merge back to level `top`.
+template <int B, bool CONJ, class Src, class Dst>
+hipError_t lf_block_b(Ctx& c, const PassArgs<C32>& A, float scale, Src src, const float2* ahat, Dst dst, hipStream_t s) {
+  using S = BlockShape<B>;
+  const uint64_t vwgs = (uint64_t)A.tiles * A.ninst;
+  const uint32_t grid = (uint32_t)((vwgs + S::GROUPS - 1) / S::GROUPS);
+  const size_t lds = lf_block_lds_bytes<C32, B>();
+  auto k = k_lf_block<C32, B, CONJ, Src, LeafRow, Dst>;
+  allow_lds(k, lds);
+  const C32Params rp{scale};
+  return launch(c, "fcirc_lf_block", s, [&](hipEvent_t e0_, hipEvent_t e1_) {
+    FCIRC_LAUNCH(e0_, e1_, k, dim3(grid), dim3(S::NT), lds, s, A, rp, src, LeafRow{ahat}, dst);
+  });
+}
+
+template <class Src, class Dst>
+hipError_t lf_block(Ctx& c, const C32Tables* T, int L, int top, uint32_t count, bool conj, Src src, const float2* ahat,
+                    Dst dst, hipStream_t s) {
+  PassArgs<C32> A = layer_args(T, L, count);
+  A.d0 = top;
+  A.logr = L - top;
+  A.logc = 0;
+  A.tiles = 1u << top;
+  A.final_store = top == 0 ? 1 : 0;
+  const float scale = (float)std::ldexp(1.0, -L);
+#define FCIRC_LF(b)                                                                           \
+  case b:                                                                                     \
+    return conj ? lf_block_b<b, true>(c, A, scale, src, ahat, dst, s)                         \
+                : lf_block_b<b, false>(c, A, scale, src, ahat, dst, s);
+  switch (L - top) {
+    FCIRC_LF(1) FCIRC_LF(2) FCIRC_LF(3) FCIRC_LF(4) FCIRC_LF(5) FCIRC_LF(6) FCIRC_LF(7)
+    FCIRC_LF(8) FCIRC_LF(9) FCIRC_LF(10) FCIRC_LF(11) FCIRC_LF(12) FCIRC_LF(13)
+    default: return hipErrorInvalidValue;
+  }
+#undef FCIRC_LF
+}
+
+// Top levels of the leaf-domain product: at most 13 levels stay in the block (64 KiB of
+// LDS for the vector), and the block shrinks to 2^10 while that keeps more workgroups busy.
+int lf_top(int L, uint32_t count) {
+  int b = std::min(L, 13);
+  while (b > 10 && ((uint64_t)count << (L - b)) < 512) --b;
+  return L - b;
+}
+
+// y_b = M(ahat (or its conjugate) * Fx(x_b)) for every instance: top split of the vectors,
+// one leaf-domain block launch, top merge.
+template <class Src, class Dst>
+hipError_t lf_product(Ctx& c, const C32Tables* T, int L, uint32_t count, bool conj, Src src, const float2* ahat,
+                      float2* ws, Dst dst, hipStream_t s) {
+  const int top = lf_top(L, count);
+  if (top == 0) return lf_block(c, T, L, 0, count, conj, src, ahat, dst, s);
+  const uint64_t n = 1ull << L;
+  hipError_t e = split_top(c, T, L, top, count, 1, src, ws, s);
+  if (e == hipSuccess)
+    e = lf_block(c, T, L, top, count, conj, LdPlain<float2>{ws, n}, ahat, StPlain<float2>{ws, n}, s);
+  if (e == hipSuccess) e = merge_top(c, T, L, top, count, ws, dst, s);
+  return e;
+}
+
 hipError_t leaf_mul(Ctx& c, const float2* A, float2* X, uint32_t n, uint32_t count, bool conj_a, float scale, hipStream_t s) {
   const uint64_t total = (uint64_t)n * count;
   const uint32_t grid = (uint32_t)std::min<uint64_t>((total + 255) / 256, 8192);
@@ -217,18 +350,152 @@ hipError_t leaf_mul(Ctx& c, const float2* A, float2* X, uint32_t n, uint32_t cou
 }
 
 struct LayerWs {
-  float2 *ahat, *v1, *v2;
+  float2 *ahat, *v1, *v2, *part;
 };
 
-fcirc_status layer_ws(Ctx& c, uint64_t n, uint32_t count, LayerWs* w) {
-  const uint64_t elems = n + 2 * n * (uint64_t)count;
+// ahat (n) | v1 (count n) | v2 (count n) | partial leaf sums (chunks n)
+fcirc_status layer_ws(Ctx& c, uint64_t n, uint32_t count, uint32_t chunks, LayerWs* w) {
+  const uint64_t elems = n + 2 * n * (uint64_t)count + n * (uint64_t)chunks;
   const fcirc_status st = ws_reserve(c, elems * sizeof(float2));
   if (st != FCIRC_OK) return st;
   float2* base = (float2*)c.ws;
   w->ahat = base;
   w->v1 = base + n;
   w->v2 = base + n + n * (uint64_t)count;
+  w->part = base + n + 2 * n * (uint64_t)count;
   return FCIRC_OK;
+}
+
+// grad_a of the layer for n >= 2^10: the batch sum is taken in registers.
+//   joint top split of g (row split) and conj x (vector split), levels [0, top);
+//   k_acc_block: workgroup (block, chunk) splits both sides of the chunk's instances down
+//   to the leaves and sums their leaf products; writes one partial per chunk;
+//   k_chunk_sum: sums the partials in chunk order; then one merge.
+struct PartialOut {
+  float2* p;
+  uint64_t n;
+  __device__ __forceinline__ void operator()(uint32_t chunk, uint32_t i, float2 v) const { p[chunk * n + i] = v; }
+};
+
+// S[i] = sum over chunks of P[chunk][i], in chunk order: 32 leaves x 8 chunk ranges per
+// workgroup, ranges combined in order through LDS.
+__global__ void __launch_bounds__(256) k_chunk_sum(const float2* __restrict__ P, float2* __restrict__ S, uint32_t n,
+                                                    uint32_t chunks) {
+  __shared__ float2 part[8][32];
+  const uint32_t li = threadIdx.x & 31, r = threadIdx.x >> 5;
+  const uint32_t i = blockIdx.x * 32 + li;
+  const uint32_t per = (chunks + 7) / 8, c0 = r * per, c1 = min(chunks, c0 + per);
+  float sx = 0.f, sy = 0.f;
+  if (i < n)
+    for (uint32_t ch = c0; ch < c1; ++ch) {
+      const float2 v = P[(uint64_t)ch * n + i];
+      sx += v.x;
+      sy += v.y;
+    }
+  part[r][li] = make_float2(sx, sy);
+  __syncthreads();
+  if (r == 0 && i < n) {
+    float tx = 0.f, ty = 0.f;
+    for (int q = 0; q < 8; ++q) {
+      tx += part[q][li].x;
+      ty += part[q][li].y;
+    }
+    S[i] = make_float2(tx, ty);
+  }
+}
+
+template <class SrcA, class SrcX>
+hipError_t split_top_ax(Ctx& c, const C32Tables* T, int L, int top, uint32_t count, SrcA srca, SrcX srcx, float2* outa,
+                        float2* outx, hipStream_t s) {
+  const uint64_t n = 1ull << L;
+  const C32Params rp[3] = {{1.f}, {1.f}, {1.f}};
+  PassArgs<C32> A = layer_args(T, L, count);
+  A.final_store = 0;
+  const LdPlain<float2> la{outa, n}, lx{outx, n};
+  const StPlain<float2> sa{outa, n}, sx{outx, n};
+  const int npass = (top + 9) / 10;
+  int d0 = 0;
+  for (int i = 0; i < npass; ++i) {
+    const int r = (top - d0) / (npass - i);
+    A.d0 = d0;
+    A.logr = r;
+    A.logc = std::min(12 - r, L - d0 - r);
+    A.tiles = (uint32_t)(n >> (A.logr + A.logc));
+    const size_t tile = (size_t)1 << (A.logr + A.logc);
+    const uint32_t grid = A.tiles * count, nt = (uint32_t)(tile >> EPT_LOG);
+    hipError_t e;
+#define FCIRC_CALL(rr) launch_split_ax_r<C32, rr>(c, A, rp, srca, srcx, sa, sx, grid, nt, 2 * tile * sizeof(float2), s)
+#define FCIRC_CALL2(rr) launch_split_ax_r<C32, rr>(c, A, rp, la, lx, sa, sx, grid, nt, 2 * tile * sizeof(float2), s)
+    if (i == 0) {
+      e = [&]() -> hipError_t { FCIRC_R12_SWITCH(r, FCIRC_CALL) }();
+    } else {
+      e = [&]() -> hipError_t { FCIRC_R12_SWITCH(r, FCIRC_CALL2) }();
+    }
+#undef FCIRC_CALL
+#undef FCIRC_CALL2
+    if (e != hipSuccess) return e;
+    d0 += r;
+  }
+  return hipSuccess;
+}
+
+template <int B, class SrcA, class SrcX>
+hipError_t acc_block_b(Ctx& c, const PassArgs<C32>& A, float scale, uint32_t chunks, uint32_t per_chunk, SrcA sa, SrcX sx,
+                       float2* part, hipStream_t s) {
+  using S = BlockShape<B>;
+  const size_t lds = block_lds_bytes<C32, B>();
+  auto k = k_acc_block<C32, B, SrcA, SrcX, PartialOut>;
+  allow_lds(k, lds);
+  const C32Params rp{scale};
+  const uint32_t grid = A.tiles * chunks;
+  return launch(c, "fcirc_acc_block", s, [&](hipEvent_t e0_, hipEvent_t e1_) {
+    FCIRC_LAUNCH(e0_, e1_, k, dim3(grid), dim3(S::NT), lds, s, A, rp, per_chunk, sa, sx, PartialOut{part, (uint64_t)1 << A.logn});
+  });
+}
+
+// Chunks of the batch for grad_a: about 256 workgroups over (block, chunk).
+uint32_t ga_chunks(int L, uint32_t count) {
+  const uint32_t blocks = 1u << lf_top(L, count);
+  return std::min<uint32_t>(count, std::max<uint32_t>(1, 256 / blocks));
+}
+
+template <class SrcA, class SrcX, class Dst>
+hipError_t grad_a_acc(Ctx& c, const C32Tables* T, int L, uint32_t count, SrcA srca, SrcX srcx, const LayerWs& w, Dst dst,
+                      hipStream_t s) {
+  const uint64_t n = 1ull << L;
+  const int top = lf_top(L, count);
+  const uint32_t chunks = ga_chunks(L, count), per_chunk = (count + chunks - 1) / chunks;
+  PassArgs<C32> A = layer_args(T, L, count);
+  A.d0 = top;
+  A.logr = L - top;
+  A.logc = 0;
+  A.tiles = 1u << top;
+  A.final_store = 0;
+  const float scale = (float)std::ldexp(1.0, -L);
+  hipError_t e = hipSuccess;
+  auto run = [&](auto sa, auto sx) -> hipError_t {
+    switch (L - top) {
+      case 10: return acc_block_b<10>(c, A, scale, chunks, per_chunk, sa, sx, w.part, s);
+      case 11: return acc_block_b<11>(c, A, scale, chunks, per_chunk, sa, sx, w.part, s);
+      case 12: return acc_block_b<12>(c, A, scale, chunks, per_chunk, sa, sx, w.part, s);
+      case 13: return acc_block_b<13>(c, A, scale, chunks, per_chunk, sa, sx, w.part, s);
+      default: return hipErrorInvalidValue;
+    }
+  };
+  if (top > 0) {
+    e = split_top_ax(c, T, L, top, count, srca, srcx, w.v1, w.v2, s);
+    if (e == hipSuccess) e = run(LdPlain<float2>{w.v1, n}, LdPlain<float2>{w.v2, n});
+  } else {
+    e = run(srca, srcx);
+  }
+  if (e == hipSuccess) {
+    const uint32_t grid = (uint32_t)((n + 31) / 32);
+    e = launch(c, "fcirc_chunk_sum", s, [&](hipEvent_t e0_, hipEvent_t e1_) {
+      FCIRC_LAUNCH(e0_, e1_, k_chunk_sum, dim3(grid), dim3(256), 0, s, w.part, w.ahat, (uint32_t)n, chunks);
+    });
+  }
+  if (e == hipSuccess) e = merge_leaves(c, T, L, 1, w.ahat, dst, s);
+  return e;
 }
 
 fcirc_status check_layer(fcirc_ctx* ctx, const void* a, uint64_t n, uint32_t batch, fcirc_ring ring, int* L) {
@@ -260,21 +527,18 @@ extern "C" fcirc_status fcirc_matvec_fwd_shared(fcirc_ctx* ctx, const void* a, c
   const bool real = ring == FCIRC_R32;
   const uint32_t count = real ? (batch + 1) / 2 : batch;
   LayerWs w;
-  st = layer_ws(c, n, count, &w);
+  st = layer_ws(c, n, count, 0, &w);
   if (st != FCIRC_OK) return st;
   const float scale = (float)std::ldexp(1.0, -L);
   hipError_t e;
-  if (real) {
-    e = transform(c, T, L, 1, 0, LdR32{(const float*)a, n}, w.ahat, s);
-    if (e == hipSuccess) e = transform(c, T, L, count, 1, LdPair{(const float*)x, batch, (uint32_t)n, 1.f}, w.v1, s);
-  } else {
-    e = transform(c, T, L, 1, 0, LdPlain<float2>{(const float2*)a, n}, w.ahat, s);
-    if (e == hipSuccess) e = transform(c, T, L, count, 1, LdPlain<float2>{(const float2*)x, n}, w.v1, s);
-  }
-  if (e == hipSuccess) e = leaf_mul(c, w.ahat, w.v1, (uint32_t)n, count, false, scale, s);
+  (void)scale;
+  e = real ? transform(c, T, L, 1, 0, LdR32{(const float*)a, n}, w.ahat, s)
+           : transform(c, T, L, 1, 0, LdPlain<float2>{(const float2*)a, n}, w.ahat, s);
   if (e == hipSuccess)
-    e = real ? merge_leaves(c, T, L, count, w.v1, StPair{(float*)y, batch, (uint32_t)n}, s)
-             : merge_leaves(c, T, L, count, w.v1, StPlain<float2>{(float2*)y, n}, s);
+    e = real ? lf_product(c, T, L, count, false, LdPair{(const float*)x, batch, (uint32_t)n, 1.f}, w.ahat, w.v1,
+                          StPair{(float*)y, batch, (uint32_t)n}, s)
+             : lf_product(c, T, L, count, false, LdPlain<float2>{(const float2*)x, n}, w.ahat, w.v1,
+                          StPlain<float2>{(float2*)y, n}, s);
   return hip_status(e);
 }
 
@@ -293,7 +557,7 @@ extern "C" fcirc_status fcirc_matvec_backward(fcirc_ctx* ctx, const void* a, con
   const bool real = ring == FCIRC_R32;
   const uint32_t count = real ? (batch + 1) / 2 : batch;
   LayerWs w;
-  st = layer_ws(c, n, count, &w);
+  st = layer_ws(c, n, count, (ga && L >= 10) ? ga_chunks(L, count) : 0, &w);
   if (st != FCIRC_OK) return st;
   const float scale = (float)std::ldexp(1.0, -L);
   hipError_t e = hipSuccess;
@@ -302,15 +566,19 @@ extern "C" fcirc_status fcirc_matvec_backward(fcirc_ctx* ctx, const void* a, con
     e = real ? transform(c, T, L, 1, 0, LdR32{(const float*)a, n}, w.ahat, s)
              : transform(c, T, L, 1, 0, LdPlain<float2>{(const float2*)a, n}, w.ahat, s);
     if (e == hipSuccess)
-      e = real ? transform(c, T, L, count, 1, LdPair{(const float*)gy, batch, (uint32_t)n, 1.f}, w.v1, s)
-               : transform(c, T, L, count, 1, LdPlain<float2>{(const float2*)gy, n}, w.v1, s);
-    if (e == hipSuccess) e = leaf_mul(c, w.ahat, w.v1, (uint32_t)n, count, true, scale, s);
-    if (e == hipSuccess)
-      e = real ? merge_leaves(c, T, L, count, w.v1, StPair{(float*)gx, batch, (uint32_t)n}, s)
-               : merge_leaves(c, T, L, count, w.v1, StPlain<float2>{(float2*)gx, n}, s);
+      e = real ? lf_product(c, T, L, count, true, LdPair{(const float*)gy, batch, (uint32_t)n, 1.f}, w.ahat, w.v1,
+                            StPair{(float*)gx, batch, (uint32_t)n}, s)
+               : lf_product(c, T, L, count, true, LdPlain<float2>{(const float2*)gy, n}, w.ahat, w.v1,
+                            StPlain<float2>{(float2*)gx, n}, s);
   }
-  if (ga && e == hipSuccess) {
-    // ga = M(sum_b Fa(gy_b) * Fx(conj x_b))
+  if (ga && e == hipSuccess && L >= 10) {
+    // ga = M(sum_b Fa(gy_b) * Fx(conj x_b)), batch sum in registers
+    e = real ? grad_a_acc(c, T, L, count, LdPair{(const float*)gy, batch, (uint32_t)n, 1.f},
+                          LdPair{(const float*)x, batch, (uint32_t)n, -1.f}, w, StR32{(float*)ga, n}, s)
+             : grad_a_acc(c, T, L, count, LdPlain<float2>{(const float2*)gy, n}, LdConj{(const float2*)x, n}, w,
+                          StPlain<float2>{(float2*)ga, n}, s);
+  } else if (ga && e == hipSuccess) {
+    // small n: leaves of both sides, then the ordered batch sum
     e = real ? transform(c, T, L, count, 0, LdPair{(const float*)gy, batch, (uint32_t)n, 1.f}, w.v1, s)
              : transform(c, T, L, count, 0, LdPlain<float2>{(const float2*)gy, n}, w.v1, s);
     if (e == hipSuccess)

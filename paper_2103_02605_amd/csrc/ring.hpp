@@ -167,6 +167,7 @@ struct C32 {
     const float2 t = cmul(a, x);
     return make_float2(t.x * scale, t.y * scale);
   }
+  static __device__ __forceinline__ T add(T a, T b) { return make_float2(a.x + b.x, a.y + b.y); }
   __device__ __forceinline__ T canon(T v) const { return v; }
 };
 

@@ -132,8 +132,9 @@ __device__ __forceinline__ void load_tw_first(typename Ring::Tw* t, typename Rin
   for (int j = 0; j < K; ++j) t[j] = tw[tw_index(d0, blk, l0, j, sb)];
 }
 
-// K split levels from the first twiddle per level and the uniform factors tu.
-template <class Ring, int K>
+// K split levels from the first twiddle per level and the uniform factors tu, on the row
+// (DA) and/or the vector (DX).
+template <class Ring, int K, bool DA = true, bool DX = true>
 __device__ __forceinline__ void split_levels_first(const Ring& R, typename Ring::T* va, typename Ring::T* vx,
                                                    const typename Ring::Tw* c, const typename Ring::Tw* tu) {
 #pragma unroll
@@ -146,15 +147,15 @@ __device__ __forceinline__ void split_levels_first(const Ring& R, typename Ring:
 #pragma unroll
         for (int q = 0; q < h; ++q) {
           const int i = g * 2 * h + q;
-          R.split_a(va[i], va[i + h], t);
-          R.split_x(vx[i], vx[i + h], t);
+          if constexpr (DA) R.split_a(va[i], va[i + h], t);
+          if constexpr (DX) R.split_x(vx[i], vx[i + h], t);
         }
       } else {
 #pragma unroll
         for (int q = 0; q < h; ++q) {
           const int i = g * 2 * h + q;
-          R.split_a2(va[i], va[i + h], tu[(1 << j) - 1 + g], c[j]);
-          R.split_x2(vx[i], vx[i + h], tu[(1 << j) - 1 + g], c[j]);
+          if constexpr (DA) R.split_a2(va[i], va[i + h], tu[(1 << j) - 1 + g], c[j]);
+          if constexpr (DX) R.split_x2(vx[i], vx[i + h], tu[(1 << j) - 1 + g], c[j]);
         }
       }
     }
@@ -750,6 +751,242 @@ __device__ __forceinline__ void block_pass(const PassArgs<Ring>& A, uint32_t vwg
       if (active) block_merge_stage<Ring, LOGR, K0, true>(A, P, R, stwi, sa, 0, ltid, dst);
     }
   }
+}
+
+// ---------------------------------------------------------------------------------------
+// Leaf-domain block pass: the row's leaves are given (the row transform of the whole
+// product, shared by every instance), so a block only splits the vector, multiplies each
+// leaf by the row's leaf (conjugated if CONJ) and 1/n, and merges back up. Same stage plan
+// and twiddle staging as block_pass; LDS holds the vector only.
+// ---------------------------------------------------------------------------------------
+template <class Ring, int LOGR, int NT = 0>
+constexpr size_t lf_block_lds_bytes() {
+  using S = BlockShape<LOGR, NT>;
+  return (size_t)S::GROUPS * ((sizeof(typename Ring::T) << LOGR) + 2 * (size_t)S::NTW * sizeof(typename Ring::Tw));
+}
+
+template <class Ring, int LOGR, int K, bool FIRST, bool DEEPEST, bool CONJ, class SrcX, class Lv, class Dst>
+__device__ __forceinline__ void lf_split_stage(const PassArgs<Ring>& A, const TilePos& P, const Ring& R, uint32_t rsel,
+                                               typename Ring::Tw const* tw, typename Ring::Tw const* twi,
+                                               const typename Ring::Tw* stw, const DeepTw<Ring>& D, typename Ring::T* sx,
+                                               uint32_t l0, uint32_t ltid, const SrcX& srcx, const Lv& leaves,
+                                               const Dst& dst) {
+  using T = typename Ring::T;
+  using Tw = typename Ring::Tw;
+  using S = BlockShape<LOGR>;
+  constexpr int E = 1 << K;
+  constexpr int IPT = S::EPT / E;
+  constexpr uint32_t ACTIVE = 1u << S::ACTIVE_LOG;
+  constexpr bool FROM_D = DEEPEST && !FIRST;
+  constexpr bool FIRSTS = DEEPEST && K == EPT_LOG;
+  static_assert(!FROM_D || K == EPT_LOG, "deepest stage of a multi-stage block pass is radix 16");
+  T vx[IPT][E];
+  Tw t[FROM_D ? 1 : IPT][FIRSTS ? K : E - 1];
+  Tw ti[(DEEPEST && !FROM_D) ? IPT : 1][FIRSTS ? K : E - 1];
+  Item it[IPT];
+#pragma unroll
+  for (int u = 0; u < IPT; ++u) {
+    it[u] = item_at(ltid + u * ACTIVE, LOGR, 0, l0, K);
+    if constexpr (FIRST) {
+      if constexpr (FIRSTS) {
+        load_tw_first<Ring, K>(t[u], tw, A.d0, P.blk, l0, it[u].sb);
+        load_tw_first<Ring, K>(ti[u], twi, A.d0, P.blk, l0, it[u].sb);
+      } else {
+        load_tw<Ring, K>(t[u], tw, A.d0, P.blk, l0, it[u].sb);
+        if constexpr (DEEPEST) load_tw<Ring, K>(ti[u], twi, A.d0, P.blk, l0, it[u].sb);
+      }
+    } else if constexpr (!DEEPEST) {
+      lds_tw<Ring, K>(t[u], stw, l0, it[u].sb);
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < IPT; ++u)
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      const uint32_t row = it[u].row0 + ((uint32_t)i << it[u].sh);
+      if constexpr (FIRST)
+        vx[u][i] = srcx(R, P.inst, P.base + row);
+      else
+        vx[u][i] = sx[row];
+    }
+#pragma unroll
+  for (int u = 0; u < IPT; ++u) {
+    if constexpr (FROM_D)
+      split_levels_first<Ring, K, false, true>(R, vx[u], vx[u], D.t, A.tu[rsel]);
+    else if constexpr (FIRSTS)
+      split_levels_first<Ring, K, false, true>(R, vx[u], vx[u], t[u], A.tu[rsel]);
+    else
+      split_levels<Ring, K, false, true>(R, vx[u], vx[u], t[u]);
+  }
+  if constexpr (DEEPEST) {
+#pragma unroll
+    for (int u = 0; u < IPT; ++u)
+#pragma unroll
+      for (int i = 0; i < E; ++i) {
+        const uint32_t row = it[u].row0 + ((uint32_t)i << it[u].sh);
+        vx[u][i] = R.leaf(leaves.template get<CONJ>(P.base + row), vx[u][i]);
+      }
+#pragma unroll
+    for (int u = 0; u < IPT; ++u) {
+      if constexpr (FROM_D)
+        merge_levels_first<Ring, K>(R, vx[u], D.ti, A.tui[rsel]);
+      else if constexpr (FIRSTS)
+        merge_levels_first<Ring, K>(R, vx[u], ti[u], A.tui[rsel]);
+      else
+        merge_levels<Ring, K>(R, vx[u], ti[u]);
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < IPT; ++u)
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      const uint32_t row = it[u].row0 + ((uint32_t)i << it[u].sh);
+      if constexpr (DEEPEST && FIRST)
+        dst(P.inst, P.base + row, A.final_store ? R.canon(vx[u][i]) : vx[u][i]);
+      else
+        sx[row] = vx[u][i];
+    }
+}
+
+template <class Ring, int LOGR, int NT, bool CONJ, class SrcX, class Lv, class Dst>
+__device__ __forceinline__ void lf_block_pass(const PassArgs<Ring>& A, uint32_t vwg0, uint32_t tid, unsigned char* smem_raw,
+                                              const typename Ring::Params& rp, const SrcX& srcx, const Lv& leaves,
+                                              const Dst& dst) {
+  using T = typename Ring::T;
+  using Tw = typename Ring::Tw;
+  using S = BlockShape<LOGR, NT>;
+  static_assert(LOGR >= 1, "at least one level");
+  const uint32_t group = tid >> S::ACTIVE_LOG;
+  const uint32_t ltid = tid & ((1u << S::ACTIVE_LOG) - 1);
+  const uint32_t vwg = vwg0 + group;
+  const bool active = group < S::GROUPS && vwg < A.tiles * A.ninst;
+  T* sx = reinterpret_cast<T*>(smem_raw) + ((size_t)group << LOGR);
+  Tw* stw = reinterpret_cast<Tw*>(smem_raw + (size_t)S::GROUPS * (sizeof(T) << LOGR)) + (size_t)group * 2 * S::NTW;
+  Tw* stwi = stw + S::NTW;
+  const TilePos P = tile_pos(A, active ? vwg : 0);
+  const uint32_t rsel = 0;
+  const Ring R(rp);
+  const Tw* tw = A.tw[0];
+  const Tw* twi = A.twi[0];
+  constexpr int NST = S::NST, K0 = S::K0;
+  DeepTw<Ring> D;
+  if constexpr (NST > 1) {
+    if (active) {
+      for (uint32_t e = ltid; e < (uint32_t)S::NTW; e += 1u << S::ACTIVE_LOG) {
+        const uint32_t l = 31u - __clz(e + 1);
+        const uint32_t gi = (1u << (A.d0 + l)) + (P.blk << l) + (e + 1 - (1u << l));
+        stw[e] = tw[gi];
+        stwi[e] = twi[gi];
+      }
+      load_deep_tw<Ring, LOGR>(D, A, P, rsel, tw, twi, ltid);
+    }
+  }
+  if (active) lf_split_stage<Ring, LOGR, K0, true, NST == 1, CONJ>(A, P, R, rsel, tw, twi, stw, D, sx, 0, ltid, srcx, leaves, dst);
+  if constexpr (NST > 1) {
+    __syncthreads();
+#pragma unroll
+    for (int s = 1; s < NST; ++s) {
+      const uint32_t l0 = K0 + EPT_LOG * (s - 1);
+      if (active) {
+        if (s + 1 == NST)
+          lf_split_stage<Ring, LOGR, EPT_LOG, false, true, CONJ>(A, P, R, rsel, tw, twi, stw, D, sx, l0, ltid, srcx, leaves, dst);
+        else
+          lf_split_stage<Ring, LOGR, EPT_LOG, false, false, CONJ>(A, P, R, rsel, tw, twi, stw, D, sx, l0, ltid, srcx, leaves, dst);
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int s = NST - 2; s >= 1; --s) {
+      const uint32_t l0 = K0 + EPT_LOG * (s - 1);
+      if (active) block_merge_stage<Ring, LOGR, EPT_LOG, false>(A, P, R, stwi, sx, l0, ltid, dst);
+      __syncthreads();
+    }
+    if (active) block_merge_stage<Ring, LOGR, K0, true>(A, P, R, stwi, sx, 0, ltid, dst);
+  }
+}
+
+template <class Ring, int LOGR, bool CONJ, class SrcX, class Lv, class Dst>
+__global__ void __launch_bounds__(BlockShape<LOGR>::NT) k_lf_block(PassArgs<Ring> A, typename Ring::Params rp, SrcX srcx,
+                                                                    Lv leaves, Dst dst) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  using S = BlockShape<LOGR>;
+  lf_block_pass<Ring, LOGR, S::NT, CONJ>(A, blockIdx.x * S::GROUPS, threadIdx.x, smem_raw, rp, srcx, leaves, dst);
+}
+
+// ---------------------------------------------------------------------------------------
+// Accumulating block pass: for one depth-(logn - LOGR) block and instances [b0, b1), split
+// the row and the vector of each instance down to the leaves and add their leaf products
+// into per-thread accumulators; no merge. Writes the sums for the block's leaves through
+// out(chunk, index, value). One thread group per workgroup (LOGR >= 10).
+// ---------------------------------------------------------------------------------------
+template <class Ring, int LOGR, class SrcA, class SrcX, class Out>
+__device__ __forceinline__ void acc_block_pass(const PassArgs<Ring>& A, uint32_t blk, uint32_t b0, uint32_t b1,
+                                               uint32_t chunk, uint32_t tid, unsigned char* smem_raw,
+                                               const typename Ring::Params& rp, const SrcA& srca, const SrcX& srcx,
+                                               const Out& out) {
+  using T = typename Ring::T;
+  using Tw = typename Ring::Tw;
+  using S = BlockShape<LOGR>;
+  static_assert(S::GROUPS == 1 && S::NST > 1, "one block of at least 2^10 elements per workgroup");
+  constexpr int NST = S::NST, K0 = S::K0;
+  constexpr int K = EPT_LOG, E = 1 << K;
+  const uint32_t ltid = tid;
+  T* sa = reinterpret_cast<T*>(smem_raw);
+  T* sx = sa + ((size_t)1 << LOGR);
+  Tw* stw = reinterpret_cast<Tw*>(smem_raw + 2 * (sizeof(T) << LOGR));
+  Tw* stwi = stw + S::NTW;
+  const Ring R(rp);
+  const Tw* tw = A.tw[0];
+  const Tw* twi = A.twi[0];
+  const TilePos P0 = tile_pos(A, blk);  // block position (instance 0)
+  for (uint32_t e = ltid; e < (uint32_t)S::NTW; e += 1u << S::ACTIVE_LOG) {
+    const uint32_t l = 31u - __clz(e + 1);
+    const uint32_t gi = (1u << (A.d0 + l)) + (P0.blk << l) + (e + 1 - (1u << l));
+    stw[e] = tw[gi];
+    stwi[e] = twi[gi];
+  }
+  DeepTw<Ring> D;
+  load_deep_tw<Ring, LOGR>(D, A, P0, 0, tw, twi, ltid);
+  constexpr uint32_t l0d = LOGR - EPT_LOG;
+  const Item itd = item_at(ltid, LOGR, 0, l0d, K);
+  T acc[E];
+#pragma unroll
+  for (int i = 0; i < E; ++i) acc[i] = T{};
+  for (uint32_t b = b0; b < b1; ++b) {
+    TilePos P = P0;
+    P.inst = b;
+    block_split_stage<Ring, LOGR, K0, true, false>(A, P, R, 0, tw, twi, stw, D, sa, sx, 0, ltid, srca, srcx, out);
+    __syncthreads();
+#pragma unroll
+    for (int s = 1; s + 1 < NST; ++s) {
+      block_split_stage<Ring, LOGR, EPT_LOG, false, false>(A, P, R, 0, tw, twi, stw, D, sa, sx, K0 + EPT_LOG * (s - 1), ltid,
+                                                           srca, srcx, out);
+      __syncthreads();
+    }
+    // deepest stage: split both, add the leaf products
+    T va[E], vx[E];
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      const uint32_t row = itd.row0 + ((uint32_t)i << itd.sh);
+      va[i] = sa[row];
+      vx[i] = sx[row];
+    }
+    split_levels_first<Ring, K>(R, va, vx, D.t, A.tu[0]);
+#pragma unroll
+    for (int i = 0; i < E; ++i) acc[i] = R.add(acc[i], R.leaf(va[i], vx[i]));
+    __syncthreads();  // LDS is refilled by the next instance
+  }
+#pragma unroll
+  for (int i = 0; i < E; ++i) out(chunk, P0.base + itd.row0 + ((uint32_t)i << itd.sh), acc[i]);
+}
+
+template <class Ring, int LOGR, class SrcA, class SrcX, class Out>
+__global__ void __launch_bounds__(BlockShape<LOGR>::NT) k_acc_block(PassArgs<Ring> A, typename Ring::Params rp,
+                                                                     uint32_t per_chunk, SrcA srca, SrcX srcx, Out out) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const uint32_t blk = blockIdx.x % A.tiles, chunk = blockIdx.x / A.tiles;
+  const uint32_t b0 = chunk * per_chunk, b1 = min(A.ninst, b0 + per_chunk);
+  acc_block_pass<Ring, LOGR>(A, blk, b0, b1, chunk, threadIdx.x, smem_raw, rp, srca, srcx, out);
 }
 
 template <class Ring, int LOGR, class SrcA, class SrcX, class Dst>
