@@ -113,97 +113,135 @@ constexpr int CARRY_PER_THREAD = 16;
 constexpr int CARRY_NT = 256;
 constexpr int CARRY_BLOCK = CARRY_PER_THREAD * CARRY_NT;  // limbs per workgroup
 
-__device__ __forceinline__ uint32_t digit(const uint64_t* c, int64_t k, uint64_t nc, int t) {
-  if (k < 0 || (uint64_t)k >= nc) return 0;
-  return (uint32_t)(c[k] >> (16 * t)) & 0xFFFFu;
-}
-__device__ __forceinline__ uint32_t s_at(const uint64_t* c, int64_t j, uint64_t nc) {
-  return digit(c, j, nc, 0) + digit(c, j - 1, nc, 1) + digit(c, j - 2, nc, 2) + digit(c, j - 3, nc, 3);
-}
-
-// (generate, propagate) composition: right = later limb.
+// (generate, propagate) composition: right = later limb. Identity: (0, 1).
 struct GP {
   uint32_t g, p;
 };
 __device__ __forceinline__ GP gp_combine(GP first, GP later) { return GP{later.g | (later.p & first.g), later.p & first.p}; }
+__device__ __forceinline__ uint32_t gp_pack(GP a) { return a.g | (a.p << 1); }
+__device__ __forceinline__ GP gp_unpack(uint32_t v) { return GP{v & 1u, (v >> 1) & 1u}; }
+__device__ __forceinline__ GP gp_of(uint32_t u) { return GP{u >= 0x10000u ? 1u : 0u, u == 0xFFFFu ? 1u : 0u}; }
 
-// Pass 1: u_j into `u`, and each workgroup's (G, P) summary.
+// Ordered inclusive scan of one GP per thread over the workgroup (thread order): wave64
+// shuffles, then the wave totals in order. sh holds CARRY_NT / 64 words. *total = the
+// composition over all threads.
+__device__ __forceinline__ GP block_scan_gp(GP v, uint32_t* sh, GP* total) {
+  constexpr int NW = CARRY_NT / 64;
+  const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  uint32_t x = gp_pack(v);
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t y = __shfl_up(x, d, 64);
+    if (lane >= (uint32_t)d) x = gp_pack(gp_combine(gp_unpack(y), gp_unpack(x)));
+  }
+  if (lane == 63) sh[w] = x;
+  __syncthreads();
+  GP pre{0u, 1u}, tot{0u, 1u};
+#pragma unroll
+  for (int q = 0; q < NW; ++q) {
+    const GP t = gp_unpack(sh[q]);
+    if ((uint32_t)q < w) pre = gp_combine(pre, t);
+    tot = gp_combine(tot, t);
+  }
+  *total = tot;
+  return gp_combine(pre, gp_unpack(x));
+}
+
+// LDS index of limb k of a block with one pad word per 16 (conflict-free per-thread runs).
+__device__ __forceinline__ uint32_t padk(uint32_t k) { return k + (k >> 4); }
+constexpr int CARRY_PAD = CARRY_BLOCK + CARRY_BLOCK / 16;
+
+// Pass 1: u_j into `u`, and each workgroup's (G, P) summary. The block's coefficients
+// (plus 4 before it) are staged in LDS with coalesced loads; thread t computes u for limbs
+// t + 256 i (consecutive lanes, consecutive words), then takes the GP summary of its own
+// contiguous run of 16.
 __global__ void __launch_bounds__(CARRY_NT) k_carry_scan1(const uint64_t* __restrict__ c, uint64_t nc, uint64_t nl,
                                                           uint32_t* __restrict__ u, uint32_t* __restrict__ summ) {
-  __shared__ uint32_t sg[CARRY_NT], sp[CARRY_NT];
-  const uint64_t j0 = (uint64_t)blockIdx.x * CARRY_BLOCK + threadIdx.x * CARRY_PER_THREAD;
-  GP acc{0u, 1u};
-  uint32_t sprev = j0 < nl ? s_at(c, (int64_t)j0 - 1, nc) : 0;
-  for (int i = 0; i < CARRY_PER_THREAD; ++i) {
-    const uint64_t j = j0 + i;
-    if (j >= nl) break;
-    const uint32_t s = s_at(c, (int64_t)j, nc);
-    const uint32_t uj = (s & 0xFFFFu) + (sprev >> 16);
-    sprev = s;
-    u[j] = uj;
-    acc = gp_combine(acc, GP{uj >= 0x10000u ? 1u : 0u, uj == 0xFFFFu ? 1u : 0u});
+  __shared__ uint64_t sc[CARRY_BLOCK + 4];
+  __shared__ uint32_t su[CARRY_PAD];
+  __shared__ uint32_t sh[CARRY_NT / 64];
+  const uint64_t jb = (uint64_t)blockIdx.x * CARRY_BLOCK;
+  for (uint32_t k = threadIdx.x; k < CARRY_BLOCK + 4; k += CARRY_NT) {
+    const int64_t idx = (int64_t)jb + (int64_t)k - 4;
+    sc[k] = (idx >= 0 && (uint64_t)idx < nc) ? c[idx] : 0ull;
   }
-  sg[threadIdx.x] = acc.g;
-  sp[threadIdx.x] = acc.p;
   __syncthreads();
+#pragma unroll
+  for (int i = 0; i < CARRY_PER_THREAD; ++i) {
+    const uint32_t k = threadIdx.x + (uint32_t)i * CARRY_NT;  // limb jb + k, coefficient sc[k + 4]
+    const uint64_t c0 = sc[k + 4], c1 = sc[k + 3], c2 = sc[k + 2], c3 = sc[k + 1], c4 = sc[k];
+    const uint32_t s = (uint32_t)(c0 & 0xFFFFu) + (uint32_t)((c1 >> 16) & 0xFFFFu) + (uint32_t)((c2 >> 32) & 0xFFFFu) +
+                       (uint32_t)((c3 >> 48) & 0xFFFFu);
+    const uint32_t sp = (uint32_t)(c1 & 0xFFFFu) + (uint32_t)((c2 >> 16) & 0xFFFFu) + (uint32_t)((c3 >> 32) & 0xFFFFu) +
+                        (uint32_t)((c4 >> 48) & 0xFFFFu);
+    su[padk(k)] = (s & 0xFFFFu) + (sp >> 16);
+  }
+  __syncthreads();
+  GP acc{0u, 1u};
+#pragma unroll
+  for (int i = 0; i < CARRY_PER_THREAD; ++i) {
+    const uint32_t k = threadIdx.x * CARRY_PER_THREAD + i;
+    if (jb + k < nl) acc = gp_combine(acc, gp_of(su[padk(k)]));
+  }
+  for (uint32_t k = threadIdx.x; k < CARRY_BLOCK; k += CARRY_NT)
+    if (jb + k < nl) u[jb + k] = su[padk(k)];
+  GP tot;
+  (void)block_scan_gp(acc, sh, &tot);
   if (threadIdx.x == 0) {
-    GP b{0u, 1u};
-    for (int t = 0; t < CARRY_NT; ++t) b = gp_combine(b, GP{sg[t], sp[t]});
-    summ[2 * blockIdx.x] = b.g;
-    summ[2 * blockIdx.x + 1] = b.p;
+    summ[2 * blockIdx.x] = tot.g;
+    summ[2 * blockIdx.x + 1] = tot.p;
   }
 }
 
-// Pass 2: carry into each workgroup from all earlier summaries, then limbs.
+// Pass 2: carry into each workgroup from all earlier summaries (ordered), then limbs.
 __global__ void __launch_bounds__(CARRY_NT) k_carry_scan2(const uint32_t* __restrict__ u, uint64_t nl,
                                                           const uint32_t* __restrict__ summ, uint16_t* __restrict__ out) {
-  __shared__ uint32_t sg[CARRY_NT], sp[CARRY_NT];
-  __shared__ uint32_t cin_blk;
-  // Carry into this block: ordered reduction of the summaries of blocks [0, blockIdx.x).
-  GP part{0u, 1u};
+  __shared__ uint32_t su[CARRY_PAD];
+  __shared__ uint32_t sh[CARRY_NT / 64];
+  const uint64_t jb = (uint64_t)blockIdx.x * CARRY_BLOCK;
+  for (uint32_t k = threadIdx.x; k < CARRY_BLOCK; k += CARRY_NT) su[padk(k)] = jb + k < nl ? u[jb + k] : 0u;
+  // summaries of blocks [0, blockIdx.x): thread t composes its contiguous share in order
   const uint32_t nb = blockIdx.x;
   const uint32_t per = (nb + CARRY_NT - 1) / CARRY_NT;
-  const uint32_t b0 = threadIdx.x * per;
-  for (uint32_t b = b0; b < b0 + per && b < nb; ++b) part = gp_combine(part, GP{summ[2 * b], summ[2 * b + 1]});
-  sg[threadIdx.x] = part.g;
-  sp[threadIdx.x] = part.p;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    GP b{0u, 1u};
-    for (int t = 0; t < CARRY_NT; ++t) b = gp_combine(b, GP{sg[t], sp[t]});
-    cin_blk = b.g;  // carry out of everything before (initial carry 0)
-  }
-  __syncthreads();
-  // Per-thread segment summaries, then an ordered exclusive scan by one thread.
-  const uint64_t j0 = (uint64_t)blockIdx.x * CARRY_BLOCK + threadIdx.x * CARRY_PER_THREAD;
+  GP part{0u, 1u};
+  for (uint32_t b = threadIdx.x * per; b < (threadIdx.x + 1) * per && b < nb; ++b)
+    part = gp_combine(part, GP{summ[2 * b], summ[2 * b + 1]});
+  GP before;
+  (void)block_scan_gp(part, sh, &before);
+  const uint32_t cin_blk = before.g;  // carry out of all earlier limbs (initial carry 0)
+  __syncthreads();                    // sh is reused, su is complete
   GP acc{0u, 1u};
   uint32_t uv[CARRY_PER_THREAD];
+#pragma unroll
   for (int i = 0; i < CARRY_PER_THREAD; ++i) {
-    const uint64_t j = j0 + i;
-    uv[i] = j < nl ? u[j] : 0u;
-    acc = gp_combine(acc, GP{uv[i] >= 0x10000u ? 1u : 0u, uv[i] == 0xFFFFu ? 1u : 0u});
+    uv[i] = su[padk(threadIdx.x * CARRY_PER_THREAD + i)];
+    acc = gp_combine(acc, gp_of(uv[i]));
   }
-  __syncthreads();
-  sg[threadIdx.x] = acc.g;
-  sp[threadIdx.x] = acc.p;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t carry = cin_blk;
-    for (int t = 0; t < CARRY_NT; ++t) {
-      const uint32_t g = sg[t], p = sp[t];
-      sg[t] = carry;  // carry into segment t
-      carry = g | (p & carry);
-    }
+  GP tot;
+  const GP incl = block_scan_gp(acc, sh, &tot);
+  // exclusive prefix of this thread = inclusive prefix of the previous thread
+  const uint32_t prev = __shfl_up(gp_pack(incl), 1, 64);
+  GP excl;
+  if ((threadIdx.x & 63) != 0) {
+    excl = gp_unpack(prev);
+    // the wave scan is already offset by earlier waves (incl includes them)
+  } else {
+    // first lane of a wave: composition of the earlier waves only
+    excl = GP{0u, 1u};
+    const uint32_t w = threadIdx.x >> 6;
+    for (uint32_t q = 0; q < w; ++q) excl = gp_combine(excl, gp_unpack(sh[q]));
   }
-  __syncthreads();
-  uint32_t carry = sg[threadIdx.x];
+  uint32_t carry = excl.g | (excl.p & cin_blk);
+  __syncthreads();  // every thread has read su and sh
+#pragma unroll
   for (int i = 0; i < CARRY_PER_THREAD; ++i) {
-    const uint64_t j = j0 + i;
-    if (j >= nl) break;
     const uint32_t v = uv[i] + carry;
-    out[j] = (uint16_t)(v & 0xFFFFu);
+    su[padk(threadIdx.x * CARRY_PER_THREAD + i)] = v & 0xFFFFu;
     carry = v >> 16;
   }
+  __syncthreads();
+  for (uint32_t k = threadIdx.x; k < CARRY_BLOCK; k += CARRY_NT)
+    if (jb + k < nl) out[jb + k] = (uint16_t)su[padk(k)];
 }
 
 uint32_t pw(uint64_t b, uint64_t e, uint32_t p) {

@@ -85,7 +85,7 @@ def test_bigint_small(F, na, nb):
     np.testing.assert_array_equal(got, OB.bigint_mul_pyint(a, b))
 
 
-@pytest.mark.parametrize("n", [1, 3, 4096, 5000, 1 << 16])
+@pytest.mark.parametrize("n", [1, 3, 4096, 5000, 1 << 16, 1 << 18])
 def test_bigint_carry_chains(F, n):
     """All-ones limbs give the longest carry chains; (2^k - 1)^2 = 2^2k - 2^(k+1) + 1."""
     a = np.full(n, 0xFFFF, dtype=np.uint16)
