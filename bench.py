@@ -171,9 +171,30 @@ def secondary(torch, F, W, quick: bool):
     ms = time_steps(torch, lambda i: F.bigint_mul(ta, tb, out=c), 20 if quick else 100, 5)
     out["bigint_mul_2x2^24bit"] = {"ms": ms, "Glimb_per_s": (1 << 21) / ms / 1e6}
     out["c1_n1024_latency"] = c1_latency(torch, F, W)
+    out["circulant_vs_fft_c64_2^21"] = circulant_vs_fft(torch, F, W, quick)
     out["batched_c64_4096"] = batched_vs_plain(torch, F, W, quick)
     out["layer_fwd_bwd_256x2^14"] = layer_vs_plain(torch, F, W, quick)
     return out
+
+
+def circulant_vs_fft(torch, F, W, quick: bool):
+    """The paper's comparison (circulant product against the classic three-FFT cyclic
+    convolution), on this GPU: complex64, n = 2^21, f = 1 (seed 3). The classic side is
+    torch.fft (hipFFT): y = ifft(fft(b) * fft(x)) with b_k = a_(-k mod n)."""
+    n = 1 << 21
+    a, x = W.complex_pair(n, seed=W.SEED_HEADLINE)
+    ta, tx = torch.from_numpy(a).cuda(), torch.from_numpy(x).cuda()
+    ty = torch.empty_like(ta)
+    idx = (-torch.arange(n, device="cuda")) % n
+    tb = ta[idx].contiguous()
+    ms_c = time_steps(torch, lambda i: F.matvec(ta, tx, out=ty), 20 if quick else 200, 10)
+
+    def classic(i):
+        return torch.fft.ifft(torch.fft.fft(tb) * torch.fft.fft(tx))
+    ms_f = time_steps(torch, classic, 20 if quick else 200, 10)
+    yc = classic(0)
+    rel = float(torch.linalg.vector_norm(ty - yc) / torch.linalg.vector_norm(yc))
+    return {"circulant_ms": ms_c, "fft_ms": ms_f, "fft_over_circulant": ms_f / ms_c, "rel_l2_between": rel}
 
 
 def batched_vs_plain(torch, F, W, quick: bool):

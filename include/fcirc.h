@@ -81,6 +81,35 @@ fcirc_status fcirc_matvec_many(fcirc_ctx *ctx, const void *a, const void *x, voi
                                uint32_t count, const void *f, fcirc_ring ring, void *stream);
 
 /*
+ * y = A(a, f) x for an f-circulant A of ANY size n >= 1 (Corollary 1, section 2).
+ *   a, x, y, f : as for fcirc_matvec, with n elements each (n need not be a power of two).
+ * A power-of-two n with an f that has the needed roots runs fcirc_matvec directly.
+ * Otherwise the product is embedded in one cyclic product of size N, the smallest power
+ * of two >= 2n-1 (for n not a power of two this is the corollary's N = 2^(d+1) with
+ * 2^d > n): row (a_0 .. a_(n-1), 0 .. 0, f a_1 .. f a_(n-1)), vector (x, 0 .. 0); the
+ * first n entries are y. Here f = 0 is allowed (the upper-triangular Toeplitz part).
+ * The library holds 3N elements of workspace for the embedded operands.
+ * Errors: EINVAL (null pointer, y overlapping a or x, Z/p f >= p), ESIZE (n = 0, or N
+ * above the ring's limit: 2^23 / 2^26 / 2^25 for the three primes, 2^26 complex).
+ */
+fcirc_status fcirc_matvec_any(fcirc_ctx *ctx, const void *a, const void *x, void *y, uint64_t n,
+                              const void *f, fcirc_ring ring, void *stream);
+
+/*
+ * y = T x for the n x n Toeplitz matrix T[i][j] = t_(j-i), any n >= 1 (the introduction
+ * recalls that a Toeplitz product is a circulant product after embedding; Corollary 1
+ * uses the same embedding).
+ *   row : device, n elements, row[k] = t_k (the first row).
+ *   col : device, n elements, col[k] = t_-k (the first column; col[0] is ignored).
+ *   x, y : device, n elements each; y must not overlap row, col or x.
+ * Embedded in one cyclic product of size N = smallest power of two >= 2n-1 with row
+ * (t_0 .. t_(n-1), 0 .. 0, t_-(n-1) .. t_-1). Same rings, limits and errors as
+ * fcirc_matvec_any (no f).
+ */
+fcirc_status fcirc_toeplitz_matvec(fcirc_ctx *ctx, const void *row, const void *col, const void *x, void *y,
+                                   uint64_t n, fcirc_ring ring, void *stream);
+
+/*
  * Exact product of two integer polynomials (section 3.1: a polynomial product is a
  * circulant product after filling up to a power of two).
  *   a : device int32[na], b : device int32[nb], coefficients of degree 0 first.

@@ -133,6 +133,7 @@ void fcirc_destroy(fcirc_ctx* ctx) {
   }
   release_graphs(ctx->c);
   if (ctx->c.ws) (void)hipFree(ctx->c.ws);
+  if (ctx->c.ws2) (void)hipFree(ctx->c.ws2);
   if (ctx->c.d_status) (void)hipFree(ctx->c.d_status);
   delete ctx;
 }
@@ -153,6 +154,49 @@ fcirc_status fcirc_matvec_many(fcirc_ctx* ctx, const void* a, const void* x, voi
   if (st != FCIRC_OK) return st;
   if ((uint64_t)count * (n >> 12 ? (n >> 12) : 1) * 2 > 0x7fffffffull) return FCIRC_ESIZE;  // grid limit
   return dispatch(ctx, a, x, y, L, count, f, ring, (hipStream_t)stream);
+}
+
+// Shared validation of the embedded products: size limit of the cyclic length, f range.
+static fcirc_status check_embed(fcirc_ctx* ctx, const void* a, const void* x, const void* y, uint64_t n, const void* f,
+                                fcirc_ring ring) {
+  if (!ctx || !a || !x || !y || !known_ring(ring)) return FCIRC_EINVAL;
+  if (n == 0 || n > (1ull << 25)) return FCIRC_ESIZE;
+  int L = 0;
+  while ((1ull << L) < 2 * n - 1) ++L;
+  if (ring <= FCIRC_ZP_167772161) {
+    const uint32_t p = zp_prime(ring);
+    if (L > zp_two_adic(p)) return FCIRC_ESIZE;
+    if (f && *(const uint32_t*)f >= p) return FCIRC_EINVAL;
+  } else if (L > 26) {
+    return FCIRC_ESIZE;
+  }
+  const size_t bytes = (size_t)n * elem_bytes(ring);
+  if (overlaps(y, bytes, a, bytes) || overlaps(y, bytes, x, bytes)) return FCIRC_EINVAL;
+  return FCIRC_OK;
+}
+
+fcirc_status fcirc_matvec_any(fcirc_ctx* ctx, const void* a, const void* x, void* y, uint64_t n, const void* f,
+                              fcirc_ring ring, void* stream) {
+  if (!f) return FCIRC_EINVAL;
+  fcirc_status st = check_embed(ctx, a, x, y, n, f, ring);
+  if (st != FCIRC_OK) return st;
+  int L = 0;
+  if (is_pow2(n) && check_product(ctx, a, x, y, n, 1, f, ring, &L) == FCIRC_OK) {
+    st = dispatch(ctx, a, x, y, L, 1, f, ring, (hipStream_t)stream);
+    if (st != FCIRC_ENOROOT) return st;  // f without the needed root: embed instead
+  }
+  if (hipSetDevice(ctx->c.device) != hipSuccess) return FCIRC_EDEVICE;
+  return embed_product(ctx->c, ring, a, nullptr, f, x, y, n, (hipStream_t)stream);
+}
+
+fcirc_status fcirc_toeplitz_matvec(fcirc_ctx* ctx, const void* row, const void* col, const void* x, void* y, uint64_t n,
+                                   fcirc_ring ring, void* stream) {
+  if (!col) return FCIRC_EINVAL;
+  fcirc_status st = check_embed(ctx, row, x, y, n, nullptr, ring);
+  if (st != FCIRC_OK) return st;
+  if (overlaps(y, (size_t)n * elem_bytes(ring), col, (size_t)n * elem_bytes(ring))) return FCIRC_EINVAL;
+  if (hipSetDevice(ctx->c.device) != hipSuccess) return FCIRC_EDEVICE;
+  return embed_product(ctx->c, ring, row, col, nullptr, x, y, n, (hipStream_t)stream);
 }
 
 fcirc_status fcirc_polymul_i64(fcirc_ctx* ctx, const int32_t* a, uint64_t na, const int32_t* b, uint64_t nb, int64_t* c,

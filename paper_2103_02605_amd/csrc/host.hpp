@@ -137,7 +137,9 @@ struct Ctx {
   std::deque<C32Tables> c32;
   void* ws = nullptr;
   size_t ws_bytes = 0;
-  size_t ws_limit = SIZE_MAX;
+  void* ws2 = nullptr;  // operands of the embedded (arbitrary-n, Toeplitz) products
+  size_t ws2_bytes = 0;
+  size_t ws_limit = SIZE_MAX;  // bound on ws_bytes + ws2_bytes
   uint32_t* d_status = nullptr;
   int forced_top = -1;
   std::map<TuneKey, TuneVal> tuned;
@@ -174,24 +176,27 @@ inline hipError_t launch(Ctx& c, const char* name, hipStream_t s, F&& fn) {
 
 // Workspace: grows on demand, never shrinks while the context lives. Callers must have
 // synchronised nothing: growth frees the old buffer only after a device synchronise.
-inline fcirc_status ws_reserve(Ctx& c, size_t bytes) {
-  if (bytes <= c.ws_bytes) return FCIRC_OK;
-  if (bytes > c.ws_limit) return FCIRC_ENOMEM;
-  if (c.ws) {
+// Grow one of the context's workspaces to at least `bytes` (contents are not kept).
+inline fcirc_status ws_grow(Ctx& c, void** buf, size_t* have, size_t other, size_t bytes) {
+  if (bytes <= *have) return FCIRC_OK;
+  if (bytes > c.ws_limit || other > c.ws_limit - bytes) return FCIRC_ENOMEM;
+  if (*buf) {
     if (hipDeviceSynchronize() != hipSuccess) return FCIRC_EDEVICE;
-    (void)hipFree(c.ws);
-    c.ws = nullptr;
-    c.ws_bytes = 0;
+    (void)hipFree(*buf);
+    *buf = nullptr;
+    *have = 0;
   }
   size_t want = bytes + bytes / 4;
-  if (want > c.ws_limit) want = bytes;
-  if (hipMalloc(&c.ws, want) != hipSuccess) {
+  if (want > c.ws_limit - other) want = bytes;
+  if (hipMalloc(buf, want) != hipSuccess) {
     (void)hipGetLastError();
     return FCIRC_ENOMEM;
   }
-  c.ws_bytes = want;
+  *have = want;
   return FCIRC_OK;
 }
+inline fcirc_status ws_reserve(Ctx& c, size_t bytes) { return ws_grow(c, &c.ws, &c.ws_bytes, c.ws2_bytes, bytes); }
+inline fcirc_status ws2_reserve(Ctx& c, size_t bytes) { return ws_grow(c, &c.ws2, &c.ws2_bytes, c.ws_bytes, bytes); }
 
 // ----------------------------------------------------------------------------------------
 // Elementwise global access functors used by the tile kernels.
@@ -495,6 +500,8 @@ fcirc_status zp_matvec(Ctx& c, const uint32_t* a, const uint32_t* x, uint32_t* y
 fcirc_status c32_matvec(Ctx& c, const void* a, const void* x, void* y, int L, uint32_t count, double fre, double fim,
                         bool real_io, hipStream_t s);
 
+fcirc_status embed_product(Ctx& c, fcirc_ring ring, const void* r, const void* col, const void* f, const void* x, void* y,
+                           uint64_t n, hipStream_t s);
 fcirc_status polymul_i64(Ctx& c, const int32_t* a, uint64_t na, const int32_t* b, uint64_t nb, int64_t* out, hipStream_t s);
 fcirc_status bigint_mul(Ctx& c, const uint16_t* a, uint64_t na, const uint16_t* b, uint64_t nb, uint16_t* out, hipStream_t s);
 void release_graphs(Ctx& c);

@@ -100,6 +100,38 @@ def matvec(a: torch.Tensor, x: torch.Tensor, f=None, p: int | None = None, out: 
     return y
 
 
+def matvec_any(a: torch.Tensor, x: torch.Tensor, f=None, p: int | None = None, out: torch.Tensor | None = None):
+    """y = A(a, f) x for any size n >= 1 (Corollary 1's embedding when n is not a power of
+    two, or when f lacks the roots the direct recursion needs)."""
+    _need(a, "a")
+    _need(x, "x")
+    if a.shape != x.shape or a.dim() != 1 or a.dtype != x.dtype:
+        raise ValueError("a and x must be 1-D tensors of the same shape and dtype")
+    ring, fv = _ring_and_f(a, f, p)
+    y = torch.empty_like(a) if out is None else out
+    _need(y, "out")
+    ctx = context(a.device)
+    L.check(L.lib().fcirc_matvec_any(ctx.handle, _ptr(a), _ptr(x), _ptr(y), a.numel(), C.byref(fv), ring, _stream(a)),
+            "fcirc_matvec_any")
+    return y
+
+
+def toeplitz_matvec(row: torch.Tensor, col: torch.Tensor, x: torch.Tensor, p: int | None = None,
+                    out: torch.Tensor | None = None):
+    """y = T x with T[i][j] = row[j - i] for j >= i and col[i - j] for j < i (col[0] unused)."""
+    for t, name in ((row, "row"), (col, "col"), (x, "x")):
+        _need(t, name)
+    if not (row.shape == col.shape == x.shape) or row.dim() != 1 or not (row.dtype == col.dtype == x.dtype):
+        raise ValueError("row, col and x must be 1-D tensors of the same shape and dtype")
+    ring, _ = _ring_and_f(row, None, p)
+    y = torch.empty_like(row) if out is None else out
+    _need(y, "out")
+    ctx = context(row.device)
+    L.check(L.lib().fcirc_toeplitz_matvec(ctx.handle, _ptr(row), _ptr(col), _ptr(x), _ptr(y), row.numel(), ring,
+                                          _stream(row)), "fcirc_toeplitz_matvec")
+    return y
+
+
 def matvec_many(a: torch.Tensor, x: torch.Tensor, f=None, p: int | None = None, out: torch.Tensor | None = None):
     """Row k of the result is A(a[k], f) x[k]; a and x have shape (count, n)."""
     _need(a, "a")

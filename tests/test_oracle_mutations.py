@@ -101,3 +101,54 @@ def _mut_definition_shift_left(mp):
 def test_pins_catch_mutation(mutation, monkeypatch):
     mutation(monkeypatch)
     assert not _pins_pass()
+
+
+# Embedding (Corollary 1, Toeplitz): the same idea, with its own compact pin set.
+from oracle import embed as OE  # noqa: E402
+
+
+def _embed_pins_pass() -> bool:
+    rng = random.Random(5)
+    try:
+        for n in (3, 5, 6):
+            row = [rng.randrange(P) for _ in range(n)]
+            col = [rng.randrange(P) for _ in range(n)]
+            x = [rng.randrange(P) for _ in range(n)]
+            want = [sum((row[j - i] if j >= i else col[i - j]) * x[j] for j in range(n)) % P for i in range(n)]
+            if OE.toeplitz_matvec_modp(row, col, x, P).tolist() != want:
+                return False
+            for f in (1, 7):
+                want_f = [sum((row[j - i] if j >= i else f * row[n + j - i]) * x[j] for j in range(n)) % P
+                          for i in range(n)]
+                if OE.fcirc_any_matvec_modp(row, x, f, P).tolist() != want_f:
+                    return False
+        return True
+    except (ValueError, AssertionError, IndexError):
+        return False
+
+
+def test_unmutated_embedding_passes():
+    assert _embed_pins_pass()
+
+
+def _mut_embed_tail_not_reversed(mp):
+    real = OE.embedded_row
+    def bad(row, col, N):
+        r = real(row, col, N)
+        n = len(row)
+        return r[: N - n + 1] + r[N - n + 1:][::-1]
+    mp.setattr(OE, "embedded_row", bad)
+
+
+def _mut_embed_drops_f(mp):
+    mp.setattr(OE, "fcirc_col", lambda a, f, p=None: [a[0]] + [a[len(a) - m] % P for m in range(1, len(a))])
+
+
+def _mut_embed_short_length(mp):
+    mp.setattr(OE, "cyclic_length", lambda n: max(1, 1 << ((n - 1).bit_length())))
+
+
+@pytest.mark.parametrize("mutation", [_mut_embed_tail_not_reversed, _mut_embed_drops_f, _mut_embed_short_length])
+def test_embedding_pins_catch_mutation(mutation, monkeypatch):
+    mutation(monkeypatch)
+    assert not _embed_pins_pass()

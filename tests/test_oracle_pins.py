@@ -12,6 +12,7 @@ from oracle import ring
 from oracle import polymul as OP
 from oracle import bigint as OB
 from oracle import grad as OG
+from oracle import embed as OE
 
 P1, P2, P3 = 998244353, 469762049, 167772161
 PRIMES = (P1, P2, P3)
@@ -397,3 +398,53 @@ def test_fft_grads_match_dense_autograd(cplx):
     y2, ga2, gx2 = OG.grads_fft(a, x, g)
     for u, v in ((y, y2), (ga, ga2), (gx, gx2)):
         np.testing.assert_allclose(v, u, rtol=1e-10, atol=1e-10)
+
+
+# P9b: Toeplitz products and the f-circulant of any size by embedding ----------------------
+
+def test_p9b_toeplitz_matrix_is_scipy_toeplitz():
+    import scipy.linalg
+    rng = np.random.default_rng(91)
+    for n in (1, 2, 5, 12):
+        row = rng.standard_normal(n)
+        col = rng.standard_normal(n)
+        col[0] = row[0]
+        assert np.array_equal(np.array(OE.toeplitz_matrix(row, col)), scipy.linalg.toeplitz(col, row))
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 6, 7, 9, 12])
+def test_p9b_fcirc_is_toeplitz_with_wrapped_column(n):
+    """Definition 2's builder (any n) equals the Toeplitz matrix whose first column is
+    f times the row's tail in reverse."""
+    rng = random.Random(9 * n)
+    p = P2
+    a = [rng.randrange(p) for _ in range(n)]
+    for f in (1, p - 1, rng.randrange(2, p), 0):
+        assert O.fcirc_matrix(a, f, p) == OE.toeplitz_matrix(a, OE.fcirc_col(a, f, p), p)
+
+
+def test_p9b_library_length_is_the_corollarys():
+    for n in range(2, 5000):
+        if n & (n - 1):
+            assert OE.cyclic_length(n) == OE.corollary_length(n)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 7, 17, 100, 333])
+def test_p9b_embedded_products_match_the_definition(n):
+    rng = np.random.default_rng(700 + n)
+    for p in PRIMES:
+        row = rng.integers(0, p, n)
+        col = rng.integers(0, p, n)
+        x = rng.integers(0, p, n)
+        want = OE.toeplitz_matvec_dense(row, col, x, p)
+        assert np.array_equal(OE.toeplitz_matvec_modp(row, col, x, p), want)
+        for f in (1, p - 1, int(rng.integers(2, p)), 0):
+            want_f = np.array(O.dense_matvec_py([int(v) for v in row], [int(v) for v in x], f, p))
+            assert np.array_equal(OE.fcirc_any_matvec_modp(row, x, f, p), want_f)
+    c = lambda: rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    row, col, x = c(), c(), c()
+    np.testing.assert_allclose(OE.toeplitz_matvec_c128(row, col, x), OE.toeplitz_matvec_dense(row, col, x),
+                               rtol=1e-9, atol=1e-9)
+    for f in (1.0, 1j, 0.5 - 2j):
+        np.testing.assert_allclose(OE.fcirc_any_matvec_c128(row, x, f), O.dense_matvec_c128(row, x, f),
+                                   rtol=1e-9, atol=1e-9)
