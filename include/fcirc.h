@@ -186,7 +186,8 @@ fcirc_status fcirc_set_split(fcirc_ctx *ctx, int top_levels);
 int fcirc_get_split(fcirc_ctx *ctx, uint64_t n, fcirc_ring ring);
 /*
  * Set the schedule for (ring, n) explicitly, as fcirc_tune would: top_levels (-1 default),
- * tile_log = log2 elements of a top-pass tile (-1 default, at most 13), flags = a bitwise
+ * tile_log = log2 elements of a top-pass tile (-1 default, at most 14 for Z/p and 13 for the
+ * complex rings), flags = a bitwise
  * OR of FCIRC_SCHED_* (0..3; the default is FCIRC_SCHED_XCD). fcirc_get_schedule reports
  * the schedule in use and returns the number of top passes.
  *   FCIRC_SCHED_XCD       top-pass tiles in XCD-aware order (neighbouring column tiles on

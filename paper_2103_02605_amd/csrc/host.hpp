@@ -250,7 +250,7 @@ inline Schedule make_schedule(int L, int elem_log, int top_levels, int tile_log_
   // Largest block pass: row + vector of 2^B elements in LDS (64 KiB Z/p at B = 13, 64 KiB
   // complex at B = 12) plus its staged twiddles.
   const int block_max = elem_log == 2 ? 13 : 12;
-  const int tile_max = 13;  // 512 threads x 16 elements per workgroup
+  const int tile_max = elem_log == 2 ? 14 : 13;  // 1024 (512) threads x 16 elements per workgroup
   // Defaults measured on MI355X: at least 2^8 blocks (one per CU) once n allows it, blocks
   // of at most 2^block_max and at least 2^10 elements; top-pass tiles of 2^(L-8) elements,
   // within [2^11, 2^13], so that a top pass also has about 2^8 workgroups.

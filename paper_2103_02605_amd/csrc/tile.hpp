@@ -31,6 +31,13 @@ namespace fcirc {
 
 constexpr int EPT_LOG = 4;  // log2 elements per thread per stage
 
+// Largest top-pass workgroup: 1024 threads (2^14-element tiles) for 32-bit rings, whose
+// top-pass kernels fit the 128 registers that allows; 512 for the complex ring.
+template <class Ring>
+struct TopThreads {
+  static constexpr int value = sizeof(typename Ring::T) == 4 ? 1024 : 512;
+};
+
 template <class Ring>
 struct PassArgs {
   typename Ring::Tw const* tw[3];   // split twiddles per ring instance (heap order)
@@ -316,7 +323,7 @@ __device__ __forceinline__ void split_pass(const PassArgs<Ring>& A, const TilePo
 }
 
 template <class Ring, int R, class SrcA, class SrcX, class Dst>
-__global__ void __launch_bounds__(512) k_split(PassArgs<Ring> A, typename Ring::Params rp0, typename Ring::Params rp1,
+__global__ void __launch_bounds__(TopThreads<Ring>::value) k_split(PassArgs<Ring> A, typename Ring::Params rp0, typename Ring::Params rp1,
                                                typename Ring::Params rp2, SrcA srca, SrcX srcx, Dst dsta, Dst dstx) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const TilePos P = tile_pos(A, A.xcd ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x);
@@ -398,7 +405,7 @@ __device__ __forceinline__ void split_stage_ax(const PassArgs<Ring>& A, const Ti
 }
 
 template <class Ring, int R, class SrcA, class SrcX, class Dst>
-__global__ void __launch_bounds__(512) k_split_ax(PassArgs<Ring> A, typename Ring::Params rp0, typename Ring::Params rp1,
+__global__ void __launch_bounds__(TopThreads<Ring>::value) k_split_ax(PassArgs<Ring> A, typename Ring::Params rp0, typename Ring::Params rp1,
                                                   typename Ring::Params rp2, SrcA srca, SrcX srcx, Dst dsta, Dst dstx) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   using T = typename Ring::T;
@@ -479,13 +486,36 @@ __device__ __forceinline__ void merge_pass(const PassArgs<Ring>& A, const TilePo
 }
 
 template <class Ring, int R, class Src, class Dst>
-__global__ void __launch_bounds__(512) k_merge(PassArgs<Ring> A, typename Ring::Params rp0, typename Ring::Params rp1,
+__global__ void __launch_bounds__(TopThreads<Ring>::value) k_merge(PassArgs<Ring> A, typename Ring::Params rp0, typename Ring::Params rp1,
                                                typename Ring::Params rp2, Src src, Dst dst) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const TilePos P = tile_pos(A, A.xcd ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x);
   uint32_t rsel;
   const Ring Rg = make_ring(A, P.inst, rp0, rp1, rp2, &rsel);
   merge_pass<Ring, R>(A, P, Rg, rsel, blockDim.x, threadIdx.x, reinterpret_cast<typename Ring::T*>(smem_raw), src, dst);
+}
+
+// Synchronisation between two stages of a block pass. In a radix-16 stage whose items (one
+// per thread) have their elements 2^sh <= 64 rows apart, the 64 items of a wave cover the
+// 1024 consecutive rows [1024 w, 1024 w + 1024) of the block, and that wave's items cover
+// the same rows in every deeper stage: an exchange between such stages stays inside the
+// wave, and only the wave's own LDS operations have to complete. A block of at most 2^10
+// elements (at most 64 threads) lies in one wave altogether.
+template <int LOGR>
+constexpr bool block_in_one_wave() {
+  return LOGR - EPT_LOG <= 6;
+}
+template <int LOGR>
+constexpr bool wave_region(int l0) {  // radix-16 stage at level l0
+  return block_in_one_wave<LOGR>() || LOGR - l0 - EPT_LOG <= 6;
+}
+__device__ __forceinline__ void stage_sync(bool wave_local) {
+  if (wave_local) {
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    __builtin_amdgcn_wave_barrier();
+  } else {
+    __syncthreads();
+  }
 }
 
 // ---------------------------------------------------------------------------------------
@@ -729,7 +759,7 @@ __device__ __forceinline__ void block_pass(const PassArgs<Ring>& A, uint32_t vwg
     // split stages (first takes K0 levels), the deepest also runs leaf + its merge levels
     if (active) block_split_stage<Ring, LOGR, K0, true, NST == 1>(A, P, R, rsel, tw, twi, stw, D, sa, sx, 0, ltid, srca, srcx, dst);
     if constexpr (NST > 1) {
-      __syncthreads();
+      stage_sync(block_in_one_wave<LOGR>());  // also publishes the LDS twiddles
 #pragma unroll
       for (int s = 1; s < NST; ++s) {
         const uint32_t l0 = K0 + EPT_LOG * (s - 1);
@@ -739,14 +769,16 @@ __device__ __forceinline__ void block_pass(const PassArgs<Ring>& A, uint32_t vwg
           else
             block_split_stage<Ring, LOGR, EPT_LOG, false, false>(A, P, R, rsel, tw, twi, stw, D, sa, sx, l0, ltid, srca, srcx, dst);
         }
-        __syncthreads();
+        // next: split stage s + 1, or (after the deepest) merge stage NST - 2 in its layout
+        const int nxt = s + 1 < NST ? s : NST - 2;
+        stage_sync(nxt >= 1 && wave_region<LOGR>(K0 + EPT_LOG * (nxt - 1)) ? true : block_in_one_wave<LOGR>());
       }
       // merge stages above the deepest one, then the first stage's K0 levels to dst
 #pragma unroll
       for (int s = NST - 2; s >= 1; --s) {
         const uint32_t l0 = K0 + EPT_LOG * (s - 1);
         if (active) block_merge_stage<Ring, LOGR, EPT_LOG, false>(A, P, R, stwi, sa, l0, ltid, dst);
-        __syncthreads();
+        stage_sync(s - 1 >= 1 && wave_region<LOGR>(K0 + EPT_LOG * (s - 2)) ? true : block_in_one_wave<LOGR>());
       }
       if (active) block_merge_stage<Ring, LOGR, K0, true>(A, P, R, stwi, sa, 0, ltid, dst);
     }
@@ -883,7 +915,7 @@ __device__ __forceinline__ void lf_block_pass(const PassArgs<Ring>& A, uint32_t 
   }
   if (active) lf_split_stage<Ring, LOGR, K0, true, NST == 1, CONJ>(A, P, R, rsel, tw, twi, stw, D, sx, 0, ltid, srcx, leaves, dst);
   if constexpr (NST > 1) {
-    __syncthreads();
+    stage_sync(block_in_one_wave<LOGR>());
 #pragma unroll
     for (int s = 1; s < NST; ++s) {
       const uint32_t l0 = K0 + EPT_LOG * (s - 1);
@@ -893,13 +925,14 @@ __device__ __forceinline__ void lf_block_pass(const PassArgs<Ring>& A, uint32_t 
         else
           lf_split_stage<Ring, LOGR, EPT_LOG, false, false, CONJ>(A, P, R, rsel, tw, twi, stw, D, sx, l0, ltid, srcx, leaves, dst);
       }
-      __syncthreads();
+      const int nxt = s + 1 < NST ? s : NST - 2;
+      stage_sync(nxt >= 1 && wave_region<LOGR>(K0 + EPT_LOG * (nxt - 1)) ? true : block_in_one_wave<LOGR>());
     }
 #pragma unroll
     for (int s = NST - 2; s >= 1; --s) {
       const uint32_t l0 = K0 + EPT_LOG * (s - 1);
       if (active) block_merge_stage<Ring, LOGR, EPT_LOG, false>(A, P, R, stwi, sx, l0, ltid, dst);
-      __syncthreads();
+      stage_sync(s - 1 >= 1 && wave_region<LOGR>(K0 + EPT_LOG * (s - 2)) ? true : block_in_one_wave<LOGR>());
     }
     if (active) block_merge_stage<Ring, LOGR, K0, true>(A, P, R, stwi, sx, 0, ltid, dst);
   }
@@ -956,12 +989,12 @@ __device__ __forceinline__ void acc_block_pass(const PassArgs<Ring>& A, uint32_t
     TilePos P = P0;
     P.inst = b;
     block_split_stage<Ring, LOGR, K0, true, false>(A, P, R, 0, tw, twi, stw, D, sa, sx, 0, ltid, srca, srcx, out);
-    __syncthreads();
+    stage_sync(block_in_one_wave<LOGR>());
 #pragma unroll
     for (int s = 1; s + 1 < NST; ++s) {
       block_split_stage<Ring, LOGR, EPT_LOG, false, false>(A, P, R, 0, tw, twi, stw, D, sa, sx, K0 + EPT_LOG * (s - 1), ltid,
                                                            srca, srcx, out);
-      __syncthreads();
+      stage_sync(wave_region<LOGR>(K0 + EPT_LOG * (s - 1)));
     }
     // deepest stage: split both, add the leaf products
     T va[E], vx[E];

@@ -26,7 +26,7 @@ extern "C" {
 
 fcirc_status fcirc_set_schedule(fcirc_ctx* ctx, fcirc_ring ring, uint64_t n, int top_levels, int tile_log, int flags) {
   if (!ctx || n == 0 || (n & (n - 1)) || ring < FCIRC_ZP_998244353 || ring > FCIRC_R32) return FCIRC_EINVAL;
-  if (top_levels < -1 || top_levels > 26 || tile_log < -1 || tile_log > 13 || flags < 0 || flags > 3) return FCIRC_EINVAL;
+  if (top_levels < -1 || top_levels > 26 || tile_log < -1 || tile_log > (ring <= FCIRC_ZP_167772161 ? 14 : 13) || flags < 0 || flags > 3) return FCIRC_EINVAL;
   TuneVal v;
   v.top = top_levels;
   v.tile_log = tile_log;
@@ -65,7 +65,7 @@ fcirc_status fcirc_tune(fcirc_ctx* ctx, uint64_t n, fcirc_ring ring, void* strea
       cands.push_back(v);
       continue;
     }
-    for (int tl = 10; tl <= 13; ++tl)
+    for (int tl = 10; tl <= (zp ? 14 : 13); ++tl)
       for (int fl = 0; fl <= 3; ++fl) {
         TuneVal v;
         v.top = top;

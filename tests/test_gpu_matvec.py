@@ -208,7 +208,7 @@ def test_schedule_variants_bit_exact(F, L):
     base = None
     try:
         for top in (L - 13, L - 11, L - 9):
-            for tile_log in (10, 11, 12, 13):
+            for tile_log in (10, 11, 12, 13, 14):
                 for flags in (0, 1, 2, 3):
                     F.set_schedule(n, ring, top, tile_log, flags)
                     got = host_u32(F.matvec(dev(a), dev(x), f=1, p=P3))
