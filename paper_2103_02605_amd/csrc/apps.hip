@@ -274,9 +274,9 @@ fcirc_status three_prime_products(Ctx& c, const V* a, uint64_t na, const V* b, u
   ZpParams rp[3];
   const ZpTw* tw[3];
   const ZpTw* twi[3];
-  const ZpTw* U[3];
-  const ZpTw* FT[3];
-  const ZpTw* FTI[3];
+  const uint32_t* U[3];
+  const uint32_t* FT[3];
+  const uint32_t* FTI[3];
   bool have_ft = true;
   for (int i = 0; i < 3; ++i) {
     const ZpTables* T = nullptr;

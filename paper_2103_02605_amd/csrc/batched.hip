@@ -58,7 +58,7 @@ struct BatchArgs {
   typename Ring::Tw const* tw;
   typename Ring::Tw const* twi;
   typename Ring::Params rp[17];  // per log2 size (the leaf scale depends on n)
-  typename Ring::Tw const* U;    // uniform radix-16 factors: tu[15] then tui[15]
+  typename Ring::DeepW const* U;  // uniform radix-16 factors (deepest-stage form): tu[15] then tui[15]
 };
 
 // Data passed between workgroups (the top-split workspace and the block results) goes
@@ -334,7 +334,7 @@ namespace {
 template <class Ring>
 fcirc_status build_and_launch(Ctx& c, const std::vector<uint64_t>& key, const void* a_base, const void* x_base,
                               void* y_base, const fcirc_item* items, uint32_t count, typename Ring::Tw const* tw,
-                              typename Ring::Tw const* twi, typename Ring::Tw const* U,
+                              typename Ring::Tw const* twi, typename Ring::DeepW const* U,
                               const typename Ring::Params* rp_by_L, hipStream_t s) {
   using T = typename Ring::T;
   for (GraphEntry* g : c.graphs)

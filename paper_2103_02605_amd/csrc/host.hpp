@@ -89,11 +89,11 @@ struct ZpTables {
   int levels = 0;  // covers depths d < levels
   ZpTw* tw = nullptr;
   ZpTw* twi = nullptr;
-  Uniform16<Zp> U;
-  ZpTw* dU = nullptr;  // device copy: tu[15] then tui[15]
-  // packed first twiddles of the deepest radix-16 stage, per log2 n (see PassArgs::ft)
-  ZpTw* ft[27] = {nullptr};
-  ZpTw* fti[27] = {nullptr};
+  uint32_t* dU = nullptr;  // uniform factors in Montgomery form (device): tu[15] then tui[15]
+  // last first-twiddle of the deepest radix-16 stage per item, Montgomery form, per log2 n
+  // (see PassArgs::ft)
+  uint32_t* ft[27] = {nullptr};
+  uint32_t* fti[27] = {nullptr};
 };
 
 struct C32Tables {
@@ -201,35 +201,47 @@ inline fcirc_status ws2_reserve(Ctx& c, size_t bytes) { return ws_grow(c, &c.ws2
 // ----------------------------------------------------------------------------------------
 // Elementwise global access functors used by the tile kernels.
 // ----------------------------------------------------------------------------------------
-// Element i (32-bit, within one instance) of instance `inst` (wave-uniform), so the address
-// is a uniform 64-bit base plus a 32-bit per-lane offset.
+// Element i (32-bit, within one instance) of instance `inst` (wave-uniform). The byte
+// offset of i is formed in 32 bits (an instance holds at most 2^26 elements of 8 bytes), so
+// the access is a uniform 64-bit base plus a 32-bit per-lane offset: the global load/store
+// form with a scalar base, no 64-bit address arithmetic per lane.
+template <class T>
+__device__ __forceinline__ const T* elem32(const T* base, uint32_t i) {
+  return reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + (uint32_t)(i * (uint32_t)sizeof(T)));
+}
+template <class T>
+__device__ __forceinline__ T* elem32(T* base, uint32_t i) {
+  return reinterpret_cast<T*>(reinterpret_cast<char*>(base) + (uint32_t)(i * (uint32_t)sizeof(T)));
+}
 template <class T>
 struct LdPlain {
   const T* p;
   uint64_t stride;
   template <class R>
   __device__ __forceinline__ T operator()(const R&, uint32_t inst, uint32_t i) const {
-    return (p + (uint64_t)inst * stride)[i];
+    return *elem32(p + (uint64_t)inst * stride, i);
   }
 };
 template <class T>
 struct StPlain {
   T* p;
   uint64_t stride;
-  __device__ __forceinline__ void operator()(uint32_t inst, uint32_t i, T v) const { (p + (uint64_t)inst * stride)[i] = v; }
+  __device__ __forceinline__ void operator()(uint32_t inst, uint32_t i, T v) const { *elem32(p + (uint64_t)inst * stride, i) = v; }
 };
 struct LdR32 {  // real data promoted to complex
   const float* p;
   uint64_t stride;
   template <class R>
   __device__ __forceinline__ float2 operator()(const R&, uint32_t inst, uint32_t i) const {
-    return make_float2((p + (uint64_t)inst * stride)[i], 0.f);
+    return make_float2(*elem32(p + (uint64_t)inst * stride, i), 0.f);
   }
 };
 struct StR32 {  // real part of a complex result
   float* p;
   uint64_t stride;
-  __device__ __forceinline__ void operator()(uint32_t inst, uint32_t i, float2 v) const { (p + (uint64_t)inst * stride)[i] = v.x; }
+  __device__ __forceinline__ void operator()(uint32_t inst, uint32_t i, float2 v) const {
+    *elem32(p + (uint64_t)inst * stride, i) = v.x;
+  }
 };
 
 // ----------------------------------------------------------------------------------------
@@ -385,8 +397,8 @@ inline hipError_t launch_merge(Ctx& c, const PassArgs<Ring>& A, const typename R
 template <class Ring, class SrcA, class SrcX, class Dst>
 inline hipError_t run_product(Ctx& c, const Schedule& S, uint32_t count, const typename Ring::Params* rp,
                               typename Ring::Tw const* const* tw, typename Ring::Tw const* const* twi,
-                              typename Ring::Tw const* const* U, typename Ring::Tw const* const* FT,
-                              typename Ring::Tw const* const* FTI, bool ring_per_inst, SrcA srca, SrcX srcx, Dst dst,
+                              typename Ring::DeepW const* const* U, typename Ring::DeepW const* const* FT,
+                              typename Ring::DeepW const* const* FTI, bool ring_per_inst, SrcA srca, SrcX srcx, Dst dst,
                               typename Ring::T* wy, typename Ring::T* ws, hipStream_t s) {
   using T = typename Ring::T;
   const int L = S.L;
@@ -490,7 +502,7 @@ int zp_two_adic(uint32_t p);
 // Tables for (p, f) covering at least L levels; ENOROOT if f has no 2^L-th root.
 fcirc_status zp_tables(Ctx& c, uint32_t p, uint32_t f, int L, const ZpTables** out);
 // Packed deepest-stage first twiddles for size 2^L (L >= 4), built on first use.
-fcirc_status zp_first_tables(Ctx& c, const ZpTables* T, int L, const ZpTw** ft, const ZpTw** fti);
+fcirc_status zp_first_tables(Ctx& c, const ZpTables* T, int L, const uint32_t** ft, const uint32_t** fti);
 ZpParams zp_params(uint32_t p, int L);
 fcirc_status c32_tables(Ctx& c, double fre, double fim, int L, hipStream_t s, const C32Tables** out);
 

@@ -35,6 +35,7 @@ struct ZpParams {
   ZpTw leaf;       // 2^32 / n mod p: undoes the Montgomery factor and applies 1/n
   ZpTw one;        // {1, floor(2^32 / p)}: reduces any 32-bit value to [0, 2p)
   uint32_t two31;  // 2^31 mod p
+  ZpTw r32;        // 2^32 mod p: converts a twiddle to Montgomery form
 };
 
 struct Zp {
@@ -44,9 +45,10 @@ struct Zp {
   uint32_t p, p2, pinv;
   ZpTw leafs, one;
   uint32_t two31;
+  ZpTw r32;
 
   __device__ __forceinline__ explicit Zp(const ZpParams& q)
-      : p(q.p), p2(2u * q.p), pinv(q.pinv), leafs(q.leaf), one(q.one), two31(q.two31) {}
+      : p(q.p), p2(2u * q.p), pinv(q.pinv), leafs(q.leaf), one(q.one), two31(q.two31), r32(q.r32) {}
 
   __device__ __forceinline__ uint32_t shoup(uint32_t v, ZpTw t) const {
     const uint32_t q = __umulhi(v, t.wp);
@@ -100,6 +102,39 @@ struct Zp {
     v = red2(d);
   }
   __device__ __forceinline__ Tw derive(Tw c, Tw) const { return c; }  // unused (kCheapDerive false)
+
+  // Deepest-stage twiddles in Montgomery form wM = w 2^32 mod p (in [0, p)). The product
+  // mont(v, wM) = v wM 2^-32 mod p = v w needs no per-twiddle companion, so twiddles of the
+  // deepest stage are formed once per item (a square, or the product with a uniform factor)
+  // at the cost of one multiply. For v < 4p the result lies in [0, 2p), as Shoup's does.
+  using DeepW = uint32_t;
+  __device__ __forceinline__ uint32_t mont(uint32_t v, uint32_t wM) const {
+    const uint64_t t = (uint64_t)v * wM;
+    const uint32_t m = (uint32_t)t * (0u - pinv);          // -p^-1 mod 2^32
+    return (uint32_t)(((uint64_t)m * p + t) >> 32);        // (t + m p) / 2^32, exact
+  }
+  __device__ __forceinline__ uint32_t canon1(uint32_t v) const { return min(v, v - p); }  // [0,2p) -> [0,p)
+  __device__ __forceinline__ DeepW to_deep(Tw t) const { return canon1(shoup(t.w, r32)); }
+  __device__ __forceinline__ DeepW deep_sq(DeepW c) const { return canon1(mont(c, c)); }
+  __device__ __forceinline__ DeepW deep_derive(DeepW c, DeepW u) const { return canon1(mont(c, u)); }
+  __device__ __forceinline__ void split_aD(T& u, T& v, DeepW w) const {
+    const uint32_t uu = red2(u);
+    const uint32_t t = mont(v, w);
+    u = uu + t;
+    v = uu - t + p2;
+  }
+  __device__ __forceinline__ void split_xD(T& u, T& v, DeepW w) const {
+    const uint32_t t = mont(u, w);
+    const uint32_t vv = red2(v);
+    u = t + vv;
+    v = t - vv + p2;
+  }
+  __device__ __forceinline__ void mergeD(T& u, T& v, DeepW w) const {
+    const uint32_t s = u + v;
+    const uint32_t d = u - v + p2;
+    u = mont(s, w);
+    v = red2(d);
+  }
   // a x / n for a, x in [0, 4p); result in [0, 2p)
   __device__ __forceinline__ T leaf(T a, T x) const {
     a = red2(a);
@@ -160,6 +195,14 @@ struct C32 {
   // A twiddle c * u is formed once (one complex product) and used as any other twiddle.
   static constexpr bool kCheapDerive = true;
   __device__ __forceinline__ Tw derive(Tw c, Tw u) const { return cmul(c, u); }
+  // Deepest-stage twiddles: the same values (see Zp).
+  using DeepW = float2;
+  __device__ __forceinline__ DeepW to_deep(Tw t) const { return t; }
+  __device__ __forceinline__ DeepW deep_sq(DeepW c) const { return cmul(c, c); }
+  __device__ __forceinline__ DeepW deep_derive(DeepW c, DeepW u) const { return cmul(c, u); }
+  __device__ __forceinline__ void split_aD(T& u, T& v, DeepW w) const { split_a(u, v, w); }
+  __device__ __forceinline__ void split_xD(T& u, T& v, DeepW w) const { split_x(u, v, w); }
+  __device__ __forceinline__ void mergeD(T& u, T& v, DeepW w) const { merge(u, v, w); }
   __device__ __forceinline__ void split_a2(T& u, T& v, Tw tu, Tw c) const { split_a(u, v, cmul(c, tu)); }
   __device__ __forceinline__ void split_x2(T& u, T& v, Tw tu, Tw c) const { split_x(u, v, cmul(c, tu)); }
   __device__ __forceinline__ void merge2(T& u, T& v, Tw tu, Tw c) const { merge(u, v, cmul(c, tu)); }

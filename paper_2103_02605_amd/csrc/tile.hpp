@@ -56,14 +56,16 @@ struct PassArgs {
   // Uniform factors of the deepest block stage: for the 2^j consecutive nodes of level j
   // inside one radix-16 item, twiddle g = (twiddle of the first node) * tu[2^j - 1 + g],
   // tu[2^j - 1 + g] = rho_j^brev_j(g) (a root of unity that does not depend on f, the
-  // block or the item). tui holds the inverses for the merge.
-  typename Ring::Tw const* tu[3];   // 15 entries each, in device memory
-  typename Ring::Tw const* tui[3];
-  // First twiddles of the deepest radix-16 stage, packed per item (may be null): for the
-  // node b0 at depth logn - 4, entries [4 b0 + j] = g_{logn-4+j, b0 2^j}, j < 4 (split);
-  // fti the inverses. One 32-byte load per item instead of four scattered ones.
-  typename Ring::Tw const* ft[3];
-  typename Ring::Tw const* fti[3];
+  // block or the item). tui holds the inverses for the merge. Stored in the ring's
+  // deepest-stage form (Montgomery form for Z/p).
+  typename Ring::DeepW const* tu[3];   // 15 entries each, in device memory
+  typename Ring::DeepW const* tui[3];
+  // Last first-twiddle of the deepest radix-16 stage per item (may be null), deepest-stage
+  // form: for the node b0 at depth logn - 4, ft[b0] = c_3 = g_{logn-1, 8 b0}; fti the
+  // inverses. The other first twiddles follow by squaring: c_j = c_(j+1)^2, since the
+  // first child's root is a square root of its parent's.
+  typename Ring::DeepW const* ft[3];
+  typename Ring::DeepW const* fti[3];
 };
 
 // Workgroups are dispatched round-robin over the 8 XCDs (workgroup i runs on XCD i mod 8),
@@ -113,6 +115,12 @@ __device__ __forceinline__ Item item_at(uint32_t item, uint32_t logr, uint32_t l
   return it;
 }
 
+// Global element index (within the instance) of element i of an item of a top pass:
+// (row0 + i 2^sh) rs + col + base, written as first + i step.
+__device__ __forceinline__ uint32_t gidx(uint32_t base, uint32_t rs, const Item& it, int i) {
+  return (base + it.row0 * rs + it.col) + (uint32_t)i * (rs << it.sh);
+}
+
 // Heap index of the twiddle used at tile level l0 + j by sub-group g of an item.
 __device__ __forceinline__ uint32_t tw_index(uint32_t d0, uint32_t blk, uint32_t l0, uint32_t j, uint32_t sb) {
   const uint32_t l = l0 + j;
@@ -139,31 +147,36 @@ __device__ __forceinline__ void load_tw_first(typename Ring::Tw* t, typename Rin
   for (int j = 0; j < K; ++j) t[j] = tw[tw_index(d0, blk, l0, j, sb)];
 }
 
+// The 2^K - 1 twiddles of a radix-2^K item in deepest-stage form, from the first twiddle
+// of each level (c[j]) and the uniform factors (level j, group g: c[j] * tu[2^j - 1 + g]).
+template <class Ring, int K>
+__device__ __forceinline__ void deep_twiddles(const Ring& R, typename Ring::DeepW* w, const typename Ring::DeepW* c,
+                                              const typename Ring::DeepW* tu) {
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    w[(1 << j) - 1] = c[j];
+#pragma unroll
+    for (int g = 1; g < (1 << j); ++g) w[(1 << j) - 1 + g] = R.deep_derive(c[j], tu[(1 << j) - 1 + g]);
+  }
+}
+
 // K split levels from the first twiddle per level and the uniform factors tu, on the row
 // (DA) and/or the vector (DX).
 template <class Ring, int K, bool DA = true, bool DX = true>
 __device__ __forceinline__ void split_levels_first(const Ring& R, typename Ring::T* va, typename Ring::T* vx,
-                                                   const typename Ring::Tw* c, const typename Ring::Tw* tu) {
+                                                   const typename Ring::DeepW* c, const typename Ring::DeepW* tu) {
+  typename Ring::DeepW w[(1 << K) - 1];
+  deep_twiddles<Ring, K>(R, w, c, tu);
 #pragma unroll
   for (int j = 0; j < K; ++j) {
     const int h = 1 << (K - 1 - j);
 #pragma unroll
     for (int g = 0; g < (1 << j); ++g) {
-      if (g == 0 || Ring::kCheapDerive) {
-        const typename Ring::Tw t = g == 0 ? c[j] : R.derive(c[j], tu[(1 << j) - 1 + g]);
 #pragma unroll
-        for (int q = 0; q < h; ++q) {
-          const int i = g * 2 * h + q;
-          if constexpr (DA) R.split_a(va[i], va[i + h], t);
-          if constexpr (DX) R.split_x(vx[i], vx[i + h], t);
-        }
-      } else {
-#pragma unroll
-        for (int q = 0; q < h; ++q) {
-          const int i = g * 2 * h + q;
-          if constexpr (DA) R.split_a2(va[i], va[i + h], tu[(1 << j) - 1 + g], c[j]);
-          if constexpr (DX) R.split_x2(vx[i], vx[i + h], tu[(1 << j) - 1 + g], c[j]);
-        }
+      for (int q = 0; q < h; ++q) {
+        const int i = g * 2 * h + q;
+        if constexpr (DA) R.split_aD(va[i], va[i + h], w[(1 << j) - 1 + g]);
+        if constexpr (DX) R.split_xD(vx[i], vx[i + h], w[(1 << j) - 1 + g]);
       }
     }
   }
@@ -171,26 +184,19 @@ __device__ __forceinline__ void split_levels_first(const Ring& R, typename Ring:
 
 // K merge levels (deepest first) from the first twiddle per level and the factors tui.
 template <class Ring, int K>
-__device__ __forceinline__ void merge_levels_first(const Ring& R, typename Ring::T* vy, const typename Ring::Tw* c,
-                                                   const typename Ring::Tw* tui) {
+__device__ __forceinline__ void merge_levels_first(const Ring& R, typename Ring::T* vy, const typename Ring::DeepW* c,
+                                                   const typename Ring::DeepW* tui) {
+  typename Ring::DeepW w[(1 << K) - 1];
+  deep_twiddles<Ring, K>(R, w, c, tui);
 #pragma unroll
   for (int j = K - 1; j >= 0; --j) {
     const int h = 1 << (K - 1 - j);
 #pragma unroll
     for (int g = 0; g < (1 << j); ++g) {
-      if (g == 0 || Ring::kCheapDerive) {
-        const typename Ring::Tw t = g == 0 ? c[j] : R.derive(c[j], tui[(1 << j) - 1 + g]);
 #pragma unroll
-        for (int q = 0; q < h; ++q) {
-          const int i = g * 2 * h + q;
-          R.merge(vy[i], vy[i + h], t);
-        }
-      } else {
-#pragma unroll
-        for (int q = 0; q < h; ++q) {
-          const int i = g * 2 * h + q;
-          R.merge2(vy[i], vy[i + h], tui[(1 << j) - 1 + g], c[j]);
-        }
+      for (int q = 0; q < h; ++q) {
+        const int i = g * 2 * h + q;
+        R.mergeD(vy[i], vy[i + h], w[(1 << j) - 1 + g]);
       }
     }
   }
@@ -266,7 +272,7 @@ __device__ __forceinline__ void split_stage(const PassArgs<Ring>& A, const TileP
     for (int i = 0; i < E; ++i) {
       const uint32_t row = it[u].row0 + ((uint32_t)i << it[u].sh);
       if constexpr (FIRST)
-        v[u][i] = src(R, P.inst, P.base + row * P.rs + it[u].col);
+        v[u][i] = src(R, P.inst, gidx(P.base, P.rs, it[u], i));
       else
         v[u][i] = lds[(row << A.logc) + it[u].col];
     }
@@ -278,7 +284,7 @@ __device__ __forceinline__ void split_stage(const PassArgs<Ring>& A, const TileP
     for (int i = 0; i < E; ++i) {
       const uint32_t row = it[u].row0 + ((uint32_t)i << it[u].sh);
       if constexpr (LAST)
-        dst(P.inst, P.base + row * P.rs + it[u].col, v[u][i]);
+        dst(P.inst, gidx(P.base, P.rs, it[u], i), v[u][i]);
       else
         lds[(row << A.logc) + it[u].col] = v[u][i];
     }
@@ -362,7 +368,7 @@ __device__ __forceinline__ void split_stage_ax(const PassArgs<Ring>& A, const Ti
     for (int i = 0; i < E; ++i) {
       const uint32_t row = it[u].row0 + ((uint32_t)i << it[u].sh);
       if constexpr (FIRST)
-        va[u][i] = srca(R, P.inst, P.base + row * P.rs + it[u].col);
+        va[u][i] = srca(R, P.inst, gidx(P.base, P.rs, it[u], i));
       else
         va[u][i] = lda[(row << A.logc) + it[u].col];
     }
@@ -373,7 +379,7 @@ __device__ __forceinline__ void split_stage_ax(const PassArgs<Ring>& A, const Ti
     for (int i = 0; i < E; ++i) {
       const uint32_t row = it[u].row0 + ((uint32_t)i << it[u].sh);
       if constexpr (FIRST)
-        vx[u][i] = srcx(R, P.inst, P.base + row * P.rs + it[u].col);
+        vx[u][i] = srcx(R, P.inst, gidx(P.base, P.rs, it[u], i));
       else
         vx[u][i] = ldx[(row << A.logc) + it[u].col];
     }
@@ -386,7 +392,7 @@ __device__ __forceinline__ void split_stage_ax(const PassArgs<Ring>& A, const Ti
     for (int i = 0; i < E; ++i) {
       const uint32_t row = it[u].row0 + ((uint32_t)i << it[u].sh);
       if constexpr (LAST)
-        dsta(P.inst, P.base + row * P.rs + it[u].col, va[u][i]);
+        dsta(P.inst, gidx(P.base, P.rs, it[u], i), va[u][i]);
       else
         lda[(row << A.logc) + it[u].col] = va[u][i];
     }
@@ -398,7 +404,7 @@ __device__ __forceinline__ void split_stage_ax(const PassArgs<Ring>& A, const Ti
     for (int i = 0; i < E; ++i) {
       const uint32_t row = it[u].row0 + ((uint32_t)i << it[u].sh);
       if constexpr (LAST)
-        dstx(P.inst, P.base + row * P.rs + it[u].col, vx[u][i]);
+        dstx(P.inst, gidx(P.base, P.rs, it[u], i), vx[u][i]);
       else
         ldx[(row << A.logc) + it[u].col] = vx[u][i];
     }
@@ -450,7 +456,7 @@ __device__ __forceinline__ void merge_stage(const PassArgs<Ring>& A, const TileP
     for (int i = 0; i < E; ++i) {
       const uint32_t row = it[u].row0 + ((uint32_t)i << it[u].sh);
       if constexpr (FIRST)
-        v[u][i] = src(R, P.inst, P.base + row * P.rs + it[u].col);
+        v[u][i] = src(R, P.inst, gidx(P.base, P.rs, it[u], i));
       else
         v[u][i] = lds[(row << A.logc) + it[u].col];
     }
@@ -462,7 +468,7 @@ __device__ __forceinline__ void merge_stage(const PassArgs<Ring>& A, const TileP
     for (int i = 0; i < E; ++i) {
       const uint32_t row = it[u].row0 + ((uint32_t)i << it[u].sh);
       if constexpr (LAST)
-        dst(P.inst, P.base + row * P.rs + it[u].col, A.final_store ? R.canon(v[u][i]) : v[u][i]);
+        dst(P.inst, gidx(P.base, P.rs, it[u], i), A.final_store ? R.canon(v[u][i]) : v[u][i]);
       else
         lds[(row << A.logc) + it[u].col] = v[u][i];
     }
@@ -549,27 +555,45 @@ constexpr size_t block_lds_bytes() {
   return (size_t)S::GROUPS * (2 * (sizeof(typename Ring::T) << LOGR) + 2 * (size_t)S::NTW * sizeof(typename Ring::Tw));
 }
 
-// First twiddles of the deepest radix-16 stage (one item per thread), split and merge.
+// First twiddles of the deepest radix-16 stage (one item per thread), split and merge,
+// in deepest-stage form.
 template <class Ring>
 struct DeepTw {
-  typename Ring::Tw t[EPT_LOG], ti[EPT_LOG];
+  typename Ring::DeepW t[EPT_LOG], ti[EPT_LOG];
 };
 
+// From the heap tables (any block at depth d0, levels l0 .. l0 + 3, item sub-block sb).
+template <class Ring>
+__device__ __forceinline__ void load_deep_heap(DeepTw<Ring>& D, const Ring& R, typename Ring::Tw const* tw,
+                                               typename Ring::Tw const* twi, uint32_t d0, uint32_t blk, uint32_t l0,
+                                               uint32_t sb) {
+  typename Ring::Tw c[EPT_LOG], ci[EPT_LOG];
+  load_tw_first<Ring, EPT_LOG>(c, tw, d0, blk, l0, sb);
+  load_tw_first<Ring, EPT_LOG>(ci, twi, d0, blk, l0, sb);
+#pragma unroll
+  for (int j = 0; j < EPT_LOG; ++j) {
+    D.t[j] = R.to_deep(c[j]);
+    D.ti[j] = R.to_deep(ci[j]);
+  }
+}
+
 template <class Ring, int LOGR>
-__device__ __forceinline__ void load_deep_tw(DeepTw<Ring>& D, const PassArgs<Ring>& A, const TilePos& P, uint32_t rsel,
-                                             typename Ring::Tw const* tw, typename Ring::Tw const* twi, uint32_t ltid) {
+__device__ __forceinline__ void load_deep_tw(DeepTw<Ring>& D, const Ring& R, const PassArgs<Ring>& A, const TilePos& P,
+                                             uint32_t rsel, typename Ring::Tw const* tw, typename Ring::Tw const* twi,
+                                             uint32_t ltid) {
   constexpr uint32_t l0 = LOGR - EPT_LOG;
   const Item it = item_at(ltid, LOGR, 0, l0, EPT_LOG);
   if (A.ft[rsel] != nullptr && A.d0 + (uint32_t)LOGR == A.logn) {
     const uint32_t b0 = (P.blk << l0) + it.sb;  // node at depth logn - 4
+    D.t[EPT_LOG - 1] = A.ft[rsel][b0];
+    D.ti[EPT_LOG - 1] = A.fti[rsel][b0];
 #pragma unroll
-    for (int j = 0; j < EPT_LOG; ++j) {
-      D.t[j] = A.ft[rsel][4 * b0 + j];
-      D.ti[j] = A.fti[rsel][4 * b0 + j];
+    for (int j = EPT_LOG - 2; j >= 0; --j) {
+      D.t[j] = R.deep_sq(D.t[j + 1]);
+      D.ti[j] = R.deep_sq(D.ti[j + 1]);
     }
   } else {
-    load_tw_first<Ring, EPT_LOG>(D.t, tw, A.d0, P.blk, l0, it.sb);
-    load_tw_first<Ring, EPT_LOG>(D.ti, twi, A.d0, P.blk, l0, it.sb);
+    load_deep_heap<Ring>(D, R, tw, twi, A.d0, P.blk, l0, it.sb);
   }
 }
 
@@ -604,16 +628,16 @@ __device__ __forceinline__ void block_split_stage(const PassArgs<Ring>& A, const
   constexpr bool FIRSTS = DEEPEST && K == EPT_LOG;
   static_assert(!FROM_D || K == EPT_LOG, "deepest stage of a multi-stage block pass is radix 16");
   T va[IPT][E], vx[IPT][E];
-  Tw t[FROM_D ? 1 : IPT][FIRSTS ? K : E - 1];
-  Tw ti[(DEEPEST && !FROM_D) ? IPT : 1][FIRSTS ? K : E - 1];
+  Tw t[(FROM_D || FIRSTS) ? 1 : IPT][E - 1];
+  Tw ti[(DEEPEST && !FROM_D && !FIRSTS) ? IPT : 1][E - 1];
+  DeepTw<Ring> Dl[FIRSTS && !FROM_D ? IPT : 1];  // single-stage radix-16 block: from the heap
   Item it[IPT];
 #pragma unroll
   for (int u = 0; u < IPT; ++u) {
     it[u] = item_at(ltid + u * ACTIVE, LOGR, 0, l0, K);
     if constexpr (FIRST) {
       if constexpr (FIRSTS) {
-        load_tw_first<Ring, K>(t[u], tw, A.d0, P.blk, l0, it[u].sb);
-        load_tw_first<Ring, K>(ti[u], twi, A.d0, P.blk, l0, it[u].sb);
+        load_deep_heap<Ring>(Dl[u], R, tw, twi, A.d0, P.blk, l0, it[u].sb);
       } else {
         load_tw<Ring, K>(t[u], tw, A.d0, P.blk, l0, it[u].sb);
         if constexpr (DEEPEST) load_tw<Ring, K>(ti[u], twi, A.d0, P.blk, l0, it[u].sb);
@@ -640,7 +664,7 @@ __device__ __forceinline__ void block_split_stage(const PassArgs<Ring>& A, const
     if constexpr (FROM_D)
       split_levels_first<Ring, K>(R, va[u], vx[u], D.t, A.tu[rsel]);
     else if constexpr (FIRSTS)
-      split_levels_first<Ring, K>(R, va[u], vx[u], t[u], A.tu[rsel]);
+      split_levels_first<Ring, K>(R, va[u], vx[u], Dl[u].t, A.tu[rsel]);
     else
       split_levels<Ring, K, true, true>(R, va[u], vx[u], t[u]);
   }
@@ -654,7 +678,7 @@ __device__ __forceinline__ void block_split_stage(const PassArgs<Ring>& A, const
       if constexpr (FROM_D)
         merge_levels_first<Ring, K>(R, va[u], D.ti, A.tui[rsel]);
       else if constexpr (FIRSTS)
-        merge_levels_first<Ring, K>(R, va[u], ti[u], A.tui[rsel]);
+        merge_levels_first<Ring, K>(R, va[u], Dl[u].ti, A.tui[rsel]);
       else
         merge_levels<Ring, K>(R, va[u], ti[u]);
     }
@@ -753,7 +777,7 @@ __device__ __forceinline__ void block_pass(const PassArgs<Ring>& A, uint32_t vwg
           stw[e] = tw[gi];
           stwi[e] = twi[gi];
         }
-        load_deep_tw<Ring, LOGR>(D, A, P, rsel, tw, twi, ltid);
+        load_deep_tw<Ring, LOGR>(D, R, A, P, rsel, tw, twi, ltid);
       }
     }
     // split stages (first takes K0 levels), the deepest also runs leaf + its merge levels
@@ -813,16 +837,16 @@ __device__ __forceinline__ void lf_split_stage(const PassArgs<Ring>& A, const Ti
   constexpr bool FIRSTS = DEEPEST && K == EPT_LOG;
   static_assert(!FROM_D || K == EPT_LOG, "deepest stage of a multi-stage block pass is radix 16");
   T vx[IPT][E];
-  Tw t[FROM_D ? 1 : IPT][FIRSTS ? K : E - 1];
-  Tw ti[(DEEPEST && !FROM_D) ? IPT : 1][FIRSTS ? K : E - 1];
+  Tw t[(FROM_D || FIRSTS) ? 1 : IPT][E - 1];
+  Tw ti[(DEEPEST && !FROM_D && !FIRSTS) ? IPT : 1][E - 1];
+  DeepTw<Ring> Dl[FIRSTS && !FROM_D ? IPT : 1];  // single-stage radix-16 block: from the heap
   Item it[IPT];
 #pragma unroll
   for (int u = 0; u < IPT; ++u) {
     it[u] = item_at(ltid + u * ACTIVE, LOGR, 0, l0, K);
     if constexpr (FIRST) {
       if constexpr (FIRSTS) {
-        load_tw_first<Ring, K>(t[u], tw, A.d0, P.blk, l0, it[u].sb);
-        load_tw_first<Ring, K>(ti[u], twi, A.d0, P.blk, l0, it[u].sb);
+        load_deep_heap<Ring>(Dl[u], R, tw, twi, A.d0, P.blk, l0, it[u].sb);
       } else {
         load_tw<Ring, K>(t[u], tw, A.d0, P.blk, l0, it[u].sb);
         if constexpr (DEEPEST) load_tw<Ring, K>(ti[u], twi, A.d0, P.blk, l0, it[u].sb);
@@ -846,7 +870,7 @@ __device__ __forceinline__ void lf_split_stage(const PassArgs<Ring>& A, const Ti
     if constexpr (FROM_D)
       split_levels_first<Ring, K, false, true>(R, vx[u], vx[u], D.t, A.tu[rsel]);
     else if constexpr (FIRSTS)
-      split_levels_first<Ring, K, false, true>(R, vx[u], vx[u], t[u], A.tu[rsel]);
+      split_levels_first<Ring, K, false, true>(R, vx[u], vx[u], Dl[u].t, A.tu[rsel]);
     else
       split_levels<Ring, K, false, true>(R, vx[u], vx[u], t[u]);
   }
@@ -863,7 +887,7 @@ __device__ __forceinline__ void lf_split_stage(const PassArgs<Ring>& A, const Ti
       if constexpr (FROM_D)
         merge_levels_first<Ring, K>(R, vx[u], D.ti, A.tui[rsel]);
       else if constexpr (FIRSTS)
-        merge_levels_first<Ring, K>(R, vx[u], ti[u], A.tui[rsel]);
+        merge_levels_first<Ring, K>(R, vx[u], Dl[u].ti, A.tui[rsel]);
       else
         merge_levels<Ring, K>(R, vx[u], ti[u]);
     }
@@ -910,7 +934,7 @@ __device__ __forceinline__ void lf_block_pass(const PassArgs<Ring>& A, uint32_t 
         stw[e] = tw[gi];
         stwi[e] = twi[gi];
       }
-      load_deep_tw<Ring, LOGR>(D, A, P, rsel, tw, twi, ltid);
+      load_deep_tw<Ring, LOGR>(D, R, A, P, rsel, tw, twi, ltid);
     }
   }
   if (active) lf_split_stage<Ring, LOGR, K0, true, NST == 1, CONJ>(A, P, R, rsel, tw, twi, stw, D, sx, 0, ltid, srcx, leaves, dst);
@@ -979,7 +1003,7 @@ __device__ __forceinline__ void acc_block_pass(const PassArgs<Ring>& A, uint32_t
     stwi[e] = twi[gi];
   }
   DeepTw<Ring> D;
-  load_deep_tw<Ring, LOGR>(D, A, P0, 0, tw, twi, ltid);
+  load_deep_tw<Ring, LOGR>(D, R, A, P0, 0, tw, twi, ltid);
   constexpr uint32_t l0d = LOGR - EPT_LOG;
   const Item itd = item_at(ltid, LOGR, 0, l0d, K);
   T acc[E];

@@ -113,23 +113,25 @@ ZpParams zp_params(uint32_t p, int L) {
   q.leaf = shoup_tw(mulmod(two32, ninv, p), p);
   q.one = shoup_tw(1, p);
   q.two31 = (uint32_t)(((uint64_t)1 << 31) % p);
+  q.r32 = shoup_tw(two32, p);
   return q;
 }
 
-Uniform16<Zp> zp_uniform16(uint32_t p) {
+// Uniform radix-16 factors rho_j^brev_j(g) (j < 4) and their inverses, in Montgomery form
+// (w 2^32 mod p): out[0..15) split, out[15..30) merge.
+void zp_uniform16_mont(uint32_t p, uint32_t* out) {
   // rho_j = gen^((p-1)/2^(j+1)), the same roots the tables are built from
   const uint32_t gen = generator(p);
-  Uniform16<Zp> U;
+  const uint32_t two32 = (uint32_t)(((uint64_t)1 << 32) % p);
   for (int j = 0; j < 4; ++j) {
     const uint32_t rho = powmod(gen, (uint64_t)(p - 1) >> (j + 1), p);
     for (uint32_t g = 0; g < (1u << j); ++g) {
       const uint32_t e = brev(g, j);
       const uint32_t w = powmod(rho, e, p), wi = invmod(w, p);
-      U.tu[(1 << j) - 1 + g] = shoup_tw(w, p);
-      U.tui[(1 << j) - 1 + g] = shoup_tw(wi, p);
+      out[(1 << j) - 1 + g] = mulmod(w, two32, p);
+      out[15 + (1 << j) - 1 + g] = mulmod(wi, two32, p);
     }
   }
-  return U;
 }
 
 fcirc_status zp_tables(Ctx& c, uint32_t p, uint32_t f, int L, const ZpTables** out) {
@@ -184,7 +186,6 @@ fcirc_status zp_tables(Ctx& c, uint32_t p, uint32_t f, int L, const ZpTables** o
   t.p = p;
   t.f = f;
   t.levels = levels;
-  t.U = zp_uniform16(p);
   if (hipMalloc(&t.tw, ne * sizeof(ZpTw)) != hipSuccess || hipMalloc(&t.twi, ne * sizeof(ZpTw)) != hipSuccess) {
     (void)hipGetLastError();
     if (t.tw) (void)hipFree(t.tw);
@@ -193,9 +194,9 @@ fcirc_status zp_tables(Ctx& c, uint32_t p, uint32_t f, int L, const ZpTables** o
   if (hipMemcpy(t.tw, tw.data(), ne * sizeof(ZpTw), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(t.twi, twi.data(), ne * sizeof(ZpTw), hipMemcpyHostToDevice) != hipSuccess)
     return FCIRC_EDEVICE;
-  if (hipMalloc(&t.dU, 30 * sizeof(ZpTw)) != hipSuccess ||
-      hipMemcpy(t.dU, t.U.tu, 15 * sizeof(ZpTw), hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(t.dU + 15, t.U.tui, 15 * sizeof(ZpTw), hipMemcpyHostToDevice) != hipSuccess)
+  uint32_t um[30];
+  zp_uniform16_mont(p, um);
+  if (hipMalloc(&t.dU, sizeof um) != hipSuccess || hipMemcpy(t.dU, um, sizeof um, hipMemcpyHostToDevice) != hipSuccess)
     return FCIRC_ENOMEM;
   // Replace a smaller table for the same (p, f) only after the device is idle.
   for (auto& old : c.zp)
@@ -217,13 +218,15 @@ fcirc_status zp_tables(Ctx& c, uint32_t p, uint32_t f, int L, const ZpTables** o
   return FCIRC_OK;
 }
 
-fcirc_status zp_first_tables(Ctx& c, const ZpTables* Tc, int L, const ZpTw** ft, const ZpTw** fti) {
+fcirc_status zp_first_tables(Ctx& c, const ZpTables* Tc, int L, const uint32_t** ft, const uint32_t** fti) {
   ZpTables* T = const_cast<ZpTables*>(Tc);
   *ft = *fti = nullptr;
   if (L < 4 || L > 26) return FCIRC_OK;
   if (!T->ft[L]) {
-    // g_{dd+j, b0 2^j} = r_{dd+j+1} rho_{dd+j}^{brev_dd(b0)} for the node b0 at depth dd = L - 4
+    // c_3 = g_{L-1, 8 b0} = r_L rho_{L-1}^{brev_dd(b0)} for the node b0 at depth dd = L - 4,
+    // in Montgomery form; the kernels square it for the three levels above.
     const uint32_t p = T->p, f = T->f, gen = generator(p);
+    const uint32_t two32 = (uint32_t)(((uint64_t)1 << 32) % p);
     const int dd = L - 4;
     std::vector<uint32_t> r(L + 1);
     r[0] = f;
@@ -236,30 +239,27 @@ fcirc_status zp_first_tables(Ctx& c, const ZpTables* Tc, int L, const ZpTw** ft,
         r[k] = sqrtmod(r[k - 1], p, gen);
     }
     const size_t nb = (size_t)1 << dd;
-    std::vector<ZpTw> h(4 * nb), hi(4 * nb);
-    std::vector<uint32_t> pw(nb), pwi(nb);
-    for (int j = 0; j < 4; ++j) {
-      const uint32_t rho = powmod(gen, (uint64_t)(p - 1) >> (dd + j + 1), p), rhoi = invmod(rho, p);
-      pw[0] = pwi[0] = 1;
-      for (size_t k = 1; k < nb; ++k) {
-        pw[k] = mulmod(pw[k - 1], rho, p);
-        pwi[k] = mulmod(pwi[k - 1], rhoi, p);
-      }
-      const uint32_t rr = r[dd + j + 1], rri = invmod(rr, p);
-      for (size_t b0 = 0; b0 < nb; ++b0) {
-        const uint32_t k = brev((uint32_t)b0, dd);
-        h[4 * b0 + j] = shoup_tw(mulmod(rr, pw[k], p), p);
-        hi[4 * b0 + j] = shoup_tw(mulmod(rri, pwi[k], p), p);
-      }
+    std::vector<uint32_t> h(nb), hi(nb), pw(nb), pwi(nb);
+    const uint32_t rho = powmod(gen, (uint64_t)(p - 1) >> L, p), rhoi = invmod(rho, p);  // rho_{L-1}
+    pw[0] = pwi[0] = 1;
+    for (size_t k = 1; k < nb; ++k) {
+      pw[k] = mulmod(pw[k - 1], rho, p);
+      pwi[k] = mulmod(pwi[k - 1], rhoi, p);
     }
-    ZpTw *d = nullptr, *di = nullptr;
-    if (hipMalloc(&d, 4 * nb * sizeof(ZpTw)) != hipSuccess || hipMalloc(&di, 4 * nb * sizeof(ZpTw)) != hipSuccess) {
+    const uint32_t rr = r[L], rri = invmod(rr, p);
+    for (size_t b0 = 0; b0 < nb; ++b0) {
+      const uint32_t k = brev((uint32_t)b0, dd);
+      h[b0] = mulmod(mulmod(rr, pw[k], p), two32, p);
+      hi[b0] = mulmod(mulmod(rri, pwi[k], p), two32, p);
+    }
+    uint32_t *d = nullptr, *di = nullptr;
+    if (hipMalloc(&d, nb * sizeof(uint32_t)) != hipSuccess || hipMalloc(&di, nb * sizeof(uint32_t)) != hipSuccess) {
       (void)hipGetLastError();
       if (d) (void)hipFree(d);
       return FCIRC_ENOMEM;
     }
-    if (hipMemcpy(d, h.data(), 4 * nb * sizeof(ZpTw), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(di, hi.data(), 4 * nb * sizeof(ZpTw), hipMemcpyHostToDevice) != hipSuccess)
+    if (hipMemcpy(d, h.data(), nb * sizeof(uint32_t), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(di, hi.data(), nb * sizeof(uint32_t), hipMemcpyHostToDevice) != hipSuccess)
       return FCIRC_EDEVICE;
     T->ft[L] = d;
     T->fti[L] = di;
@@ -286,12 +286,12 @@ fcirc_status zp_matvec(Ctx& c, const uint32_t* a, const uint32_t* x, uint32_t* y
   const ZpTw* tw[3] = {T->tw, T->tw, T->tw};
   const ZpTw* twi[3] = {T->twi, T->twi, T->twi};
   const uint64_t n = (uint64_t)1 << L;
-  const ZpTw* U[3] = {T->dU, T->dU, T->dU};
-  const ZpTw *ft = nullptr, *fti = nullptr;
+  const uint32_t* U[3] = {T->dU, T->dU, T->dU};
+  const uint32_t *ft = nullptr, *fti = nullptr;
   st = zp_first_tables(c, T, L, &ft, &fti);
   if (st != FCIRC_OK) return st;
-  const ZpTw* FT[3] = {ft, ft, ft};
-  const ZpTw* FTI[3] = {fti, fti, fti};
+  const uint32_t* FT[3] = {ft, ft, ft};
+  const uint32_t* FTI[3] = {fti, fti, fti};
   return hip_status(run_product<Zp>(c, S, count, rps, tw, twi, U, ft ? FT : nullptr, ft ? FTI : nullptr, false, LdPlain<uint32_t>{a, n},
                                     LdPlain<uint32_t>{x, n}, StPlain<uint32_t>{y, n}, y, (uint32_t*)c.ws, s));
 }
