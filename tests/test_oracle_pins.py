@@ -448,3 +448,71 @@ def test_p9b_embedded_products_match_the_definition(n):
     for f in (1.0, 1j, 0.5 - 2j):
         np.testing.assert_allclose(OE.fcirc_any_matvec_c128(row, x, f), O.dense_matvec_c128(row, x, f),
                                    rtol=1e-9, atol=1e-9)
+
+
+# P15: the ring of section 3.1, Z/p[sqrt 3] with p = 2^31 - 1 -----------------------------
+
+from oracle import gfp2 as OG2  # noqa: E402
+
+
+def test_p15_ring_is_a_field_and_the_generator_has_order_2_31():
+    p = OG2.P
+    assert p == 2**31 - 1 and pow(2, p - 1, p) == 1
+    assert pow(3, (p - 1) // 2, p) == p - 1          # 3 is not a square: Z/p[sqrt 3] = GF(p^2)
+    assert OG2.norm(OG2.GEN) == 1                       # 2 + sqrt 3 has norm 4 - 3 = 1
+    assert OG2.power(OG2.GEN, 1 << 31) == OG2.ONE       # order divides p + 1 = 2^31
+    assert OG2.power(OG2.GEN, 1 << 30) != OG2.ONE       # ... and is exactly 2^31
+    for k in (1, 2, 5, 16, 31):
+        w = OG2.root_of_unity(1 << k)
+        assert OG2.power(w, 1 << k) == OG2.ONE
+        assert OG2.power(w, 1 << (k - 1)) == (p - 1, 0)  # primitive: w^(N/2) = -1
+
+
+def test_p15_paper_inverse_root_identity():
+    """(fourth root of i)^-1 = -i sqrt(i) (fourth root of i), with the precomputed roots."""
+    z = OG2.root_of_unity(16)     # a fourth root of i
+    s = OG2.mul(z, z)             # a square root of i
+    i = OG2.mul(s, s)
+    assert OG2.mul(i, i) == (OG2.P - 1, 0)
+    assert OG2.inv(z) == OG2.neg(OG2.mul(OG2.mul(i, s), z))
+
+
+def test_p15_field_operations():
+    rng = random.Random(15)
+    for _ in range(200):
+        u = (rng.randrange(OG2.P), rng.randrange(OG2.P))
+        v = (rng.randrange(OG2.P), rng.randrange(OG2.P))
+        if u != (0, 0):
+            assert OG2.mul(u, OG2.inv(u)) == OG2.ONE
+        assert OG2.mul(u, v) == OG2.mul(v, u)
+        sq = OG2.mul(u, u)
+        r = OG2.sqrt(sq)
+        assert OG2.mul(r, r) == sq
+        arr_u, arr_v = OG2.as_array([u]), OG2.as_array([v])
+        assert tuple(int(c) for c in OG2.vmul(arr_u, arr_v)[0]) == OG2.mul(u, v)
+        if u != (0, 0):
+            assert tuple(int(c) for c in OG2.vinv(arr_u)[0]) == OG2.inv(u)
+    with pytest.raises(ValueError):
+        OG2.sqrt(OG2.Z_NONSQ)
+
+
+@pytest.mark.parametrize("n", [1, 2, 4, 8, 16, 32])
+def test_p15_recursion_matches_definition(n):
+    rng = random.Random(150 + n)
+    a = [(rng.randrange(OG2.P), rng.randrange(OG2.P)) for _ in range(n)]
+    x = [(rng.randrange(OG2.P), rng.randrange(OG2.P)) for _ in range(n)]
+    for f in (OG2.ONE, (OG2.P - 1, 0)):
+        want = OG2.dense_matvec(a, x, f)
+        assert O.alg1_matvec(a, x, f, OG2.GFp2(random.Random(n))) == want  # random root choices
+        assert [tuple(int(c) for c in r) for r in OG2.levels_matvec(a, x, f)] == want
+
+
+def test_p15_levels_sampled_at_2_14():
+    n = 1 << 14
+    g = np.random.default_rng(16)
+    a = g.integers(0, OG2.P, (n, 2)).astype(np.uint64)
+    x = g.integers(0, OG2.P, (n, 2)).astype(np.uint64)
+    for f in (OG2.ONE, (OG2.P - 1, 0)):
+        y = OG2.levels_matvec(a, x, f)
+        for i in (0, 1, 777, n - 1):
+            assert tuple(int(c) for c in y[i]) == OG2.matvec_entry(a, x, f, i)
