@@ -28,6 +28,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 P1 = 998244353
+W_SEED_GF = 3
 HBM_PEAK_GBS = 8000.0
 # 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz: 32-bit VALU lane-operations per second (T/s)
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
@@ -172,6 +173,7 @@ def secondary(torch, F, W, quick: bool):
     out["bigint_mul_2x2^24bit"] = {"ms": ms, "Glimb_per_s": (1 << 21) / ms / 1e6}
     out["c1_n1024_latency"] = c1_latency(torch, F, W)
     out["circulant_vs_fft_c64_2^21"] = circulant_vs_fft(torch, F, W, quick)
+    out["gfp2_section3_ring_2^21"] = gfp2_product(torch, F, quick)
     out["batched_c64_4096"] = batched_vs_plain(torch, F, W, quick)
     out["layer_fwd_bwd_256x2^14"] = layer_vs_plain(torch, F, W, quick)
     return out
@@ -195,6 +197,19 @@ def circulant_vs_fft(torch, F, W, quick: bool):
     yc = classic(0)
     rel = float(torch.linalg.vector_norm(ty - yc) / torch.linalg.vector_norm(yc))
     return {"circulant_ms": ms_c, "fft_ms": ms_f, "fft_over_circulant": ms_f / ms_c, "rel_l2_between": rel}
+
+
+def gfp2_product(torch, F, quick: bool):
+    """The ring of section 3.1, GF(p^2) = Z/p[sqrt 3] with p = 2^31 - 1: one product of
+    n = 2^21 (f = 1), inputs uniform (seed 3), 8 rotating sets."""
+    n = 1 << 21
+    p = (1 << 31) - 1
+    rng = np.random.default_rng(W_SEED_GF)
+    sets = [(torch.from_numpy(rng.integers(0, p, (n, 2)).astype(np.int32)).cuda(),
+             torch.from_numpy(rng.integers(0, p, (n, 2)).astype(np.int32)).cuda()) for _ in range(8)]
+    ty = torch.empty_like(sets[0][0])
+    ms = time_steps(torch, lambda i: F.matvec(sets[i % 8][0], sets[i % 8][1], f=1, p=p, out=ty), 20 if quick else 200, 10)
+    return {"ms": ms, "Gcoeff_per_s": n / ms / 1e6}
 
 
 def batched_vs_plain(torch, F, W, quick: bool):

@@ -38,7 +38,10 @@ typedef enum {
   FCIRC_ZP_469762049 = 1, /* Z/p, p =   7*2^26 + 1: data uint32 in [0,p), n <= 2^26     */
   FCIRC_ZP_167772161 = 2, /* Z/p, p =   5*2^25 + 1: data uint32 in [0,p), n <= 2^25     */
   FCIRC_C64 = 3,          /* complex numbers: data interleaved complex64 (float re, im)   */
-  FCIRC_R32 = 4           /* real data float32; complex arithmetic inside; f real         */
+  FCIRC_R32 = 4,          /* real data float32; complex arithmetic inside; f real         */
+  FCIRC_GFP2 = 5          /* the ring of section 3.1, Z/p[sqrt 3] = GF(p^2), p = 2^31 - 1:
+                             data uint32 pairs (a, b) = a + b sqrt 3, both in [0,p);
+                             roots of unity (2 + sqrt 3)^((p+1)/N); f = 1 or -1, n <= 2^26 */
 } fcirc_ring;
 
 typedef enum {
@@ -63,12 +66,14 @@ const char *fcirc_strerror(fcirc_status s);
  *   a : device, n elements, the FIRST ROW of A (section 1.2's row convention).
  *   x : device, n elements.  y : device, n elements (written; must not overlap a or x).
  *   f : host pointer to ONE ring element: uint32_t in [0,p) for Z/p, double[2] (re, im)
- *       for FCIRC_C64, double for FCIRC_R32.
+ *       for FCIRC_C64, double for FCIRC_R32, uint32_t[2] (a, b) for FCIRC_GFP2 (f must
+ *       be 1 = (1, 0) or -1 = (p-1, 0) there).
  *   Z/p elements must be canonical (in [0,p)); outputs are canonical.
- * Errors: EINVAL (null pointer), ESIZE (n not a power of two, or n above 2^23 / 2^26 /
- * 2^25 for the three primes and 2^26 for the complex rings), ENOROOT (f = 0 or f has no
- * n-th root in Z/p). Complex rings accept any nonzero f; the accuracy statement (relative
- * L2 error near 1e-6 for n <= 2^16) holds for |f| = 1.
+ * Errors: EINVAL (null pointer, f not canonical), ESIZE (n not a power of two, or n above
+ * 2^23 / 2^26 / 2^25 for the three primes and 2^26 for the complex rings and GF(p^2)),
+ * ENOROOT (f = 0 or f has no n-th root in Z/p; f other than 1 or -1 in GF(p^2)). Complex
+ * rings accept any nonzero f; the accuracy statement (relative L2 error near 1e-6 for
+ * n <= 2^16) holds for |f| = 1.
  */
 fcirc_status fcirc_matvec(fcirc_ctx *ctx, const void *a, const void *x, void *y, uint64_t n,
                           const void *f, fcirc_ring ring, void *stream);

@@ -14,6 +14,7 @@ FCIRC_ZP_469762049 = 1
 FCIRC_ZP_167772161 = 2
 FCIRC_C64 = 3
 FCIRC_R32 = 4
+FCIRC_GFP2 = 5
 
 STATUS = {0: "OK", 1: "EINVAL", 2: "ESIZE", 3: "ENOROOT", 4: "ERANGE", 5: "ENOMEM", 6: "EDEVICE"}
 

@@ -23,12 +23,13 @@ bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
 size_t elem_bytes(fcirc_ring r) {
   switch (r) {
     case FCIRC_C64: return 8;
+    case FCIRC_GFP2: return 8;
     case FCIRC_R32: return 4;
     default: return 4;
   }
 }
 
-bool known_ring(int r) { return r >= FCIRC_ZP_998244353 && r <= FCIRC_R32; }
+bool known_ring(int r) { return r >= FCIRC_ZP_998244353 && r <= FCIRC_GFP2; }
 
 // Common checks of a product of `count` instances of size n. Returns FCIRC_OK and L.
 fcirc_status check_product(fcirc_ctx* ctx, const void* a, const void* x, const void* y, uint64_t n, uint64_t count,
@@ -42,6 +43,11 @@ fcirc_status check_product(fcirc_ctx* ctx, const void* a, const void* x, const v
     const uint32_t fv = *(const uint32_t*)f;
     if (fv >= p) return FCIRC_EINVAL;
     if (fv == 0) return FCIRC_ENOROOT;
+  } else if (ring == FCIRC_GFP2) {
+    if (l > 26) return FCIRC_ESIZE;
+    const uint32_t* fv = (const uint32_t*)f;
+    if (fv[0] > 0x7ffffffeu || fv[1] > 0x7ffffffeu) return FCIRC_EINVAL;
+    if (fv[1] != 0 || (fv[0] != 1 && fv[0] != 0x7ffffffeu)) return FCIRC_ENOROOT;  // f = 1 or -1
   } else {
     if (l > 26) return FCIRC_ESIZE;
     if (ring == FCIRC_C64) {
@@ -67,6 +73,7 @@ fcirc_status dispatch(fcirc_ctx* ctx, const void* a, const void* x, void* y, int
     const double* fc = (const double*)f;
     return c32_matvec(ctx->c, a, x, y, L, count, fc[0], fc[1], false, s);
   }
+  if (ring == FCIRC_GFP2) return gp2_matvec(ctx->c, a, x, y, L, count, ((const uint32_t*)f)[0] != 1, s);
   return c32_matvec(ctx->c, a, x, y, L, count, *(const double*)f, 0.0, true, s);
 }
 
@@ -131,6 +138,11 @@ void fcirc_destroy(fcirc_ctx* ctx) {
     (void)hipFree(t.twi);
     (void)hipFree(t.dU);
   }
+  for (auto& t : ctx->c.gp2) {
+    (void)hipFree(t.tw);
+    (void)hipFree(t.twi);
+    (void)hipFree(t.dU);
+  }
   release_graphs(ctx->c);
   if (ctx->c.ws) (void)hipFree(ctx->c.ws);
   if (ctx->c.ws2) (void)hipFree(ctx->c.ws2);
@@ -159,7 +171,7 @@ fcirc_status fcirc_matvec_many(fcirc_ctx* ctx, const void* a, const void* x, voi
 // Shared validation of the embedded products: size limit of the cyclic length, f range.
 static fcirc_status check_embed(fcirc_ctx* ctx, const void* a, const void* x, const void* y, uint64_t n, const void* f,
                                 fcirc_ring ring) {
-  if (!ctx || !a || !x || !y || !known_ring(ring)) return FCIRC_EINVAL;
+  if (!ctx || !a || !x || !y || !known_ring(ring) || ring == FCIRC_GFP2) return FCIRC_EINVAL;
   if (n == 0 || n > (1ull << 25)) return FCIRC_ESIZE;
   int L = 0;
   while ((1ull << L) < 2 * n - 1) ++L;

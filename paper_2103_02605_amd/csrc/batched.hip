@@ -469,7 +469,7 @@ extern "C" fcirc_status fcirc_matvec_batched(fcirc_ctx* ctx, const void* a_base,
                                              const fcirc_item* items, uint32_t count, const void* f, fcirc_ring ring,
                                              void* stream) {
   if (!ctx || !a_base || !x_base || !y_base || !items || !f) return FCIRC_EINVAL;
-  if (ring == FCIRC_R32 || ring < FCIRC_ZP_998244353 || ring > FCIRC_R32) return FCIRC_EINVAL;
+  if (ring != FCIRC_C64 && (ring < FCIRC_ZP_998244353 || ring > FCIRC_ZP_167772161)) return FCIRC_EINVAL;
   if (count == 0) return FCIRC_OK;
   uint32_t maxL = 0;
   for (uint32_t i = 0; i < count; ++i) {

@@ -96,6 +96,14 @@ struct ZpTables {
   uint32_t* fti[27] = {nullptr};
 };
 
+struct Gp2Tables {
+  int fneg = 0;    // 0: f = 1, 1: f = -1
+  int levels = 0;  // covers depths d < levels
+  uint2* tw = nullptr;
+  uint2* twi = nullptr;
+  uint2* dU = nullptr;  // uniform radix-16 factors: tu[15] then tui[15]
+};
+
 struct C32Tables {
   double fre = 1.0, fim = 0.0;
   int levels = 0;
@@ -135,6 +143,7 @@ struct Ctx {
   hipDeviceProp_t prop{};
   std::deque<ZpTables> zp;   // deque: references stay valid as plans are added
   std::deque<C32Tables> c32;
+  std::deque<Gp2Tables> gp2;
   void* ws = nullptr;
   size_t ws_bytes = 0;
   void* ws2 = nullptr;  // operands of the embedded (arbitrary-n, Toeplitz) products
@@ -512,6 +521,7 @@ fcirc_status zp_matvec(Ctx& c, const uint32_t* a, const uint32_t* x, uint32_t* y
 fcirc_status c32_matvec(Ctx& c, const void* a, const void* x, void* y, int L, uint32_t count, double fre, double fim,
                         bool real_io, hipStream_t s);
 
+fcirc_status gp2_matvec(Ctx& c, const void* a, const void* x, void* y, int L, uint32_t count, int fneg, hipStream_t s);
 fcirc_status embed_product(Ctx& c, fcirc_ring ring, const void* r, const void* col, const void* f, const void* x, void* y,
                            uint64_t n, hipStream_t s);
 fcirc_status polymul_i64(Ctx& c, const int32_t* a, uint64_t na, const int32_t* b, uint64_t nb, int64_t* out, hipStream_t s);
@@ -526,7 +536,7 @@ inline fcirc_status hip_status(hipError_t e) {
 
 // Schedule for (ring, L): a forced split wins, then a tuned entry, then the defaults.
 inline Schedule schedule_for(Ctx& c, int ring, int L) {
-  const int elem_log = ring == FCIRC_C64 || ring == FCIRC_R32 ? 3 : 2;
+  const int elem_log = ring == FCIRC_C64 || ring == FCIRC_R32 || ring == FCIRC_GFP2 ? 3 : 2;
   TuneVal v;
   auto it = c.tuned.find(TuneKey{ring, L});
   if (it != c.tuned.end()) v = it->second;

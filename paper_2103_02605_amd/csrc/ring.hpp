@@ -214,4 +214,80 @@ struct C32 {
   __device__ __forceinline__ T canon(T v) const { return v; }
 };
 
+// GF(p^2) = Z/p[sqrt 3] with the Mersenne prime p = 2^31 - 1, the ring section 3.1 computes
+// in (3 is not a square mod p). An element a + b sqrt 3 is a uint2 (a, b), components
+// canonical in [0, p) at every step; products use 2^31 = 1 mod p for the reduction.
+struct Gp2Params {
+  uint32_t ninv;  // 1/n mod p (= 2^(31 - log2 n))
+};
+
+struct Gp2 {
+  using T = uint2;
+  using Tw = uint2;
+  using Params = Gp2Params;
+  static constexpr uint32_t P = 0x7fffffffu;
+  uint32_t ninv;
+
+  __device__ __forceinline__ explicit Gp2(const Gp2Params& q) : ninv(q.ninv) {}
+
+  // t < 2^64 -> t mod p
+  static __device__ __forceinline__ uint32_t red64(uint64_t t) {
+    const uint64_t s = (t & P) + (t >> 31);                      // < 2^34
+    const uint32_t r = (uint32_t)((s & P) + (s >> 31));          // < p + 8
+    return r >= P ? r - P : r;
+  }
+  static __device__ __forceinline__ uint32_t addm(uint32_t a, uint32_t b) {
+    const uint32_t s = a + b;
+    return min(s, s - P);
+  }
+  static __device__ __forceinline__ uint32_t subm(uint32_t a, uint32_t b) {
+    const uint32_t d = a - b;
+    return min(d, d + P);
+  }
+  // (a + b sqrt 3)(c + d sqrt 3) = (a c + 3 b d) + (a d + b c) sqrt 3; a c + 3 b d < 2^64
+  static __device__ __forceinline__ T mul(T u, T v) {
+    const uint64_t ac = (uint64_t)u.x * v.x, bd = (uint64_t)u.y * v.y;
+    const uint64_t ad = (uint64_t)u.x * v.y, bc = (uint64_t)u.y * v.x;
+    return make_uint2(red64(ac + 3 * bd), red64(ad + bc));
+  }
+  static __device__ __forceinline__ T add(T u, T v) { return make_uint2(addm(u.x, v.x), addm(u.y, v.y)); }
+  static __device__ __forceinline__ T sub(T u, T v) { return make_uint2(subm(u.x, v.x), subm(u.y, v.y)); }
+
+  __device__ __forceinline__ void split_a(T& u, T& v, Tw g) const {
+    const T t = mul(g, v);
+    const T uu = u;
+    u = add(uu, t);
+    v = sub(uu, t);
+  }
+  __device__ __forceinline__ void split_x(T& u, T& v, Tw g) const {
+    const T t = mul(g, u);
+    const T vv = v;
+    u = add(t, vv);
+    v = sub(t, vv);
+  }
+  __device__ __forceinline__ void merge(T& u, T& v, Tw gi) const {
+    const T s = add(u, v), d = sub(u, v);
+    u = mul(s, gi);
+    v = d;
+  }
+  static constexpr bool kCheapDerive = true;
+  __device__ __forceinline__ Tw derive(Tw c, Tw u) const { return mul(c, u); }
+  __device__ __forceinline__ void split_a2(T& u, T& v, Tw tu, Tw c) const { split_a(u, v, mul(c, tu)); }
+  __device__ __forceinline__ void split_x2(T& u, T& v, Tw tu, Tw c) const { split_x(u, v, mul(c, tu)); }
+  __device__ __forceinline__ void merge2(T& u, T& v, Tw tu, Tw c) const { merge(u, v, mul(c, tu)); }
+  using DeepW = uint2;
+  __device__ __forceinline__ DeepW to_deep(Tw t) const { return t; }
+  __device__ __forceinline__ DeepW deep_sq(DeepW c) const { return mul(c, c); }
+  __device__ __forceinline__ DeepW deep_derive(DeepW c, DeepW u) const { return mul(c, u); }
+  __device__ __forceinline__ void split_aD(T& u, T& v, DeepW w) const { split_a(u, v, w); }
+  __device__ __forceinline__ void split_xD(T& u, T& v, DeepW w) const { split_x(u, v, w); }
+  __device__ __forceinline__ void mergeD(T& u, T& v, DeepW w) const { merge(u, v, w); }
+  // a x / n
+  __device__ __forceinline__ T leaf(T a, T x) const {
+    const T t = mul(a, x);
+    return make_uint2(red64((uint64_t)t.x * ninv), red64((uint64_t)t.y * ninv));
+  }
+  __device__ __forceinline__ T canon(T v) const { return v; }
+};
+
 }  // namespace fcirc

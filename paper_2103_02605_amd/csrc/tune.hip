@@ -17,6 +17,7 @@ namespace {
 fcirc_status run_once(Ctx& c, fcirc_ring ring, int L, void* a, void* x, void* y, hipStream_t s) {
   if (ring <= FCIRC_ZP_167772161)
     return zp_matvec(c, (const uint32_t*)a, (const uint32_t*)x, (uint32_t*)y, L, 1, zp_prime(ring), 1u, s);
+  if (ring == FCIRC_GFP2) return gp2_matvec(c, a, x, y, L, 1, 0, s);
   return c32_matvec(c, a, x, y, L, 1, 1.0, 0.0, ring == FCIRC_R32, s);
 }
 
@@ -25,7 +26,7 @@ fcirc_status run_once(Ctx& c, fcirc_ring ring, int L, void* a, void* x, void* y,
 extern "C" {
 
 fcirc_status fcirc_set_schedule(fcirc_ctx* ctx, fcirc_ring ring, uint64_t n, int top_levels, int tile_log, int flags) {
-  if (!ctx || n == 0 || (n & (n - 1)) || ring < FCIRC_ZP_998244353 || ring > FCIRC_R32) return FCIRC_EINVAL;
+  if (!ctx || n == 0 || (n & (n - 1)) || ring < FCIRC_ZP_998244353 || ring > FCIRC_GFP2) return FCIRC_EINVAL;
   if (top_levels < -1 || top_levels > 26 || tile_log < -1 || tile_log > (ring <= FCIRC_ZP_167772161 ? 14 : 13) || flags < 0 || flags > 3) return FCIRC_EINVAL;
   TuneVal v;
   v.top = top_levels;
@@ -36,14 +37,14 @@ fcirc_status fcirc_set_schedule(fcirc_ctx* ctx, fcirc_ring ring, uint64_t n, int
 }
 
 fcirc_status fcirc_tune(fcirc_ctx* ctx, uint64_t n, fcirc_ring ring, void* stream) {
-  if (!ctx || n == 0 || (n & (n - 1)) || ring < FCIRC_ZP_998244353 || ring > FCIRC_R32) return FCIRC_EINVAL;
+  if (!ctx || n == 0 || (n & (n - 1)) || ring < FCIRC_ZP_998244353 || ring > FCIRC_GFP2) return FCIRC_EINVAL;
   Ctx& c = ctx->c;
   if (hipSetDevice(c.device) != hipSuccess) return FCIRC_EDEVICE;
   const int L = ilog2(n);
   if (ring <= FCIRC_ZP_167772161 && L > zp_two_adic(zp_prime(ring))) return FCIRC_ESIZE;
   if (L > 26) return FCIRC_ESIZE;
   hipStream_t s = (hipStream_t)stream;
-  const size_t eb = ring == FCIRC_C64 ? 8 : 4;
+  const size_t eb = ring == FCIRC_C64 || ring == FCIRC_GFP2 ? 8 : 4;
   void *a = nullptr, *x = nullptr, *y = nullptr;
   if (hipMalloc(&a, n * eb) != hipSuccess || hipMalloc(&x, n * eb) != hipSuccess || hipMalloc(&y, n * eb) != hipSuccess) {
     (void)hipGetLastError();

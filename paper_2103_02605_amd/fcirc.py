@@ -20,6 +20,7 @@ from . import _lib as L
 
 P1, P2, P3 = 998244353, 469762049, 167772161
 RING_OF_PRIME = {P1: L.FCIRC_ZP_998244353, P2: L.FCIRC_ZP_469762049, P3: L.FCIRC_ZP_167772161}
+P_GF = (1 << 31) - 1  # GF(p^2) = Z/p[sqrt 3] of section 3.1: tensors (..., 2) int32 holding (a, b)
 
 
 class Context:
@@ -70,6 +71,11 @@ def _need(t: torch.Tensor, name: str):
 
 def _ring_and_f(t: torch.Tensor, f, p):
     """(ring id, ctypes value of f) for a data tensor t."""
+    if p == P_GF:
+        if t.dtype != torch.int32 or t.shape[-1] != 2:
+            raise TypeError("GF(p^2) data must be int32 tensors of shape (..., 2) holding (a, b) in [0, p)")
+        fv = 1 if f is None else int(f) % P_GF
+        return L.FCIRC_GFP2, (C.c_uint32 * 2)(fv, 0)
     if p is not None:
         if p not in RING_OF_PRIME:
             raise ValueError(f"unsupported prime {p}")
@@ -86,16 +92,21 @@ def _ring_and_f(t: torch.Tensor, f, p):
 
 
 def matvec(a: torch.Tensor, x: torch.Tensor, f=None, p: int | None = None, out: torch.Tensor | None = None):
-    """y = A(a, f) x for one product of power-of-two size n (Definition 2, Algorithm 1)."""
+    """y = A(a, f) x for one product of power-of-two size n (Definition 2, Algorithm 1).
+
+    p selects Z/p (int32/uint32 tensors of n residues) or, with p = 2^31 - 1, the ring of
+    section 3.1 (int32 tensors of shape (n, 2), f = 1 or -1); otherwise complex64 or
+    float32 tensors."""
     _need(a, "a")
     _need(x, "x")
-    if a.shape != x.shape or a.dim() != 1 or a.dtype != x.dtype:
-        raise ValueError("a and x must be 1-D tensors of the same shape and dtype")
     ring, fv = _ring_and_f(a, f, p)
+    vdim = 2 if ring == L.FCIRC_GFP2 else 1
+    if a.shape != x.shape or a.dim() != vdim or a.dtype != x.dtype:
+        raise ValueError("a and x must be tensors of the same shape and dtype, one vector each")
     y = torch.empty_like(a) if out is None else out
     _need(y, "out")
     ctx = context(a.device)
-    L.check(L.lib().fcirc_matvec(ctx.handle, _ptr(a), _ptr(x), _ptr(y), a.numel(), C.byref(fv), ring, _stream(a)),
+    L.check(L.lib().fcirc_matvec(ctx.handle, _ptr(a), _ptr(x), _ptr(y), a.shape[0], C.byref(fv), ring, _stream(a)),
             "fcirc_matvec")
     return y
 
@@ -133,12 +144,14 @@ def toeplitz_matvec(row: torch.Tensor, col: torch.Tensor, x: torch.Tensor, p: in
 
 
 def matvec_many(a: torch.Tensor, x: torch.Tensor, f=None, p: int | None = None, out: torch.Tensor | None = None):
-    """Row k of the result is A(a[k], f) x[k]; a and x have shape (count, n)."""
+    """Row k of the result is A(a[k], f) x[k]; a and x have shape (count, n) (or
+    (count, n, 2) for the ring of section 3.1)."""
     _need(a, "a")
     _need(x, "x")
-    if a.shape != x.shape or a.dim() != 2 or a.dtype != x.dtype:
-        raise ValueError("a and x must be 2-D tensors (count, n) of the same shape and dtype")
     ring, fv = _ring_and_f(a, f, p)
+    vdim = 3 if ring == L.FCIRC_GFP2 else 2
+    if a.shape != x.shape or a.dim() != vdim or a.dtype != x.dtype:
+        raise ValueError("a and x must be tensors (count, n) of the same shape and dtype")
     y = torch.empty_like(a) if out is None else out
     ctx = context(a.device)
     L.check(L.lib().fcirc_matvec_many(ctx.handle, _ptr(a), _ptr(x), _ptr(y), a.shape[1], a.shape[0], C.byref(fv),
