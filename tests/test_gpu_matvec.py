@@ -141,6 +141,26 @@ def test_complex_sizes(F, L):
     assert rel_l2(got, want) <= TOL
 
 
+@pytest.mark.parametrize("L", [18, 21, 24])
+def test_complex_large(F, L):
+    """Large complex products (f = 1) against the DFT identity in complex128."""
+    n = 1 << L
+    a, x = W.complex_pair(n, seed=L)
+    want = O.cyclic_matvec_fft_c128(a.astype(np.complex128), x.astype(np.complex128))
+    got = F.matvec(dev(a), dev(x)).cpu().numpy()
+    assert rel_l2(got, want) <= TOL
+
+
+def test_complex_and_real_large_negacyclic(F):
+    n = 1 << 20
+    a, x = W.complex_pair(n, seed=20)
+    want = O.levels_matvec_c128(a.astype(np.complex128), x.astype(np.complex128), -1.0)
+    assert rel_l2(F.matvec(dev(a), dev(x), f=-1.0).cpu().numpy(), want) <= TOL
+    ar, xr = a.real.copy(), x.real.copy()
+    want = O.levels_matvec_c128(ar.astype(np.complex128), xr.astype(np.complex128), -1.0).real
+    assert rel_l2(F.matvec(dev(ar), dev(xr), f=-1.0).cpu().numpy(), want) <= TOL
+
+
 @pytest.mark.parametrize("f", [-1.0, 1j, np.exp(0.3j), np.exp(-2.0j)])
 def test_complex_unit_f(F, f):
     for L in (1, 6, 12, 15):
