@@ -19,7 +19,10 @@
  * and captured graphs, and frees them in fcirc_destroy.
  *
  * Threading: one context serves one host thread at a time (calls that share a context
- * must be serialised by the caller). Output buffers must not overlap inputs.
+ * must be serialised by the caller). The context's workspace is shared by its calls, so
+ * calls on different streams with one context must not run concurrently on the device
+ * (order the streams, or use one context per stream). Output buffers must not overlap
+ * inputs.
  */
 #ifndef FCIRC_H
 #define FCIRC_H
