@@ -174,6 +174,24 @@ fcirc_status fcirc_matvec_backward(fcirc_ctx *ctx, const void *a, const void *x,
 fcirc_status fcirc_check(fcirc_ctx *ctx, void *stream);
 
 /*
+ * Debugging checks of a context; `flags` is a set of the bits below (0 turns all off).
+ * Their defaults come from the environment at fcirc_create: FCIRC_VALIDATE=1 sets
+ * FCIRC_CHECK_INPUTS, FCIRC_DEBUG_SYNC=1 sets FCIRC_CHECK_SYNC.
+ *   FCIRC_CHECK_INPUTS: the Z/p and GF(p^2) products (fcirc_matvec, fcirc_matvec_many,
+ *     fcirc_matvec_any, fcirc_toeplitz_matvec, fcirc_matvec_batched) take canonical inputs,
+ *     every word in [0,p), and give unspecified results otherwise. With this bit, a kernel
+ *     first checks every input word of the call; the call then synchronises the stream and
+ *     returns FCIRC_EINVAL, having written no output, when a word is out of range. Because
+ *     it synchronises, it cannot be used while the stream is being captured into a graph.
+ *   FCIRC_CHECK_SYNC: synchronise the stream after every kernel the library launches and
+ *     return FCIRC_EDEVICE at the first failed one.
+ * Returns FCIRC_EINVAL for a null context or unknown bits.
+ */
+#define FCIRC_CHECK_INPUTS 1
+#define FCIRC_CHECK_SYNC 2
+fcirc_status fcirc_set_checks(fcirc_ctx *ctx, int flags);
+
+/*
  * Per-kernel timing with HIP events recorded on the caller's stream around each kernel
  * the library launches (for measurement; off by default). fcirc_stage_times
  * synchronises, then writes up to `max` entries: the kernel name, the number of launches

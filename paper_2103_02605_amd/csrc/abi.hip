@@ -3,8 +3,10 @@
 // anything is enqueued, so an error return means nothing was written.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdlib>
 #include <cstring>
+#include <initializer_list>
 
 #include "host.hpp"
 
@@ -30,6 +32,18 @@ size_t elem_bytes(fcirc_ring r) {
 }
 
 bool known_ring(int r) { return r >= FCIRC_ZP_998244353 && r <= FCIRC_GFP2; }
+
+// FCIRC_CHECK_INPUTS for a Z/p or GF(p^2) call: every 32-bit word of each buffer (`words`
+// of them) must lie in [0,p). Floating-point rings have no canonical form to check.
+fcirc_status check_inputs(Ctx& c, fcirc_ring ring, std::initializer_list<const void*> bufs, uint64_t words,
+                          hipStream_t s) {
+  if (!c.check_inputs || ring == FCIRC_C64 || ring == FCIRC_R32) return FCIRC_OK;
+  InputCheck chk(c, ring == FCIRC_GFP2 ? 0x7fffffffu : zp_prime(ring), s);
+  for (const void* b : bufs) chk.span(b, words);
+  return chk.finish();
+}
+
+uint64_t words_per_elem(fcirc_ring ring) { return ring == FCIRC_GFP2 ? 2 : 1; }
 
 // Common checks of a product of `count` instances of size n. Returns FCIRC_OK and L.
 fcirc_status check_product(fcirc_ctx* ctx, const void* a, const void* x, const void* y, uint64_t n, uint64_t count,
@@ -79,6 +93,43 @@ fcirc_status dispatch(fcirc_ctx* ctx, const void* a, const void* x, void* y, int
 
 }  // namespace
 
+namespace fcirc {
+
+// Sets *flag when a word of v[0, count) is >= bound. Global atomics only (vector memory).
+__global__ __launch_bounds__(256) void k_input_check(const uint32_t* __restrict__ v, uint64_t count, uint32_t bound,
+                                                     uint32_t* flag) {
+  const uint64_t stride = (uint64_t)gridDim.x * 256u;
+  bool bad = false;
+  for (uint64_t i = (uint64_t)blockIdx.x * 256u + threadIdx.x; i < count; i += stride) bad |= v[i] >= bound;
+  if (bad) atomicOr(flag, 1u);
+}
+
+InputCheck::InputCheck(Ctx& c, uint32_t bound, hipStream_t s) : c_(c), bound_(bound), s_(s) {
+  if (c_.check_inputs) err_ = hipMemsetAsync(c_.d_status + 1, 0, sizeof(uint32_t), s_);
+}
+
+void InputCheck::span(const void* words, uint64_t count) {
+  if (!c_.check_inputs || err_ != hipSuccess || count == 0) return;
+  const uint32_t grid = (uint32_t)std::min<uint64_t>((count + 255) / 256, 4096);
+  const uint32_t* v = (const uint32_t*)words;
+  uint32_t* flag = c_.d_status + 1;
+  const uint32_t bound = bound_;
+  err_ = launch(c_, "fcirc_input_check", s_, [&](hipEvent_t e0, hipEvent_t e1) {
+    FCIRC_LAUNCH(e0, e1, k_input_check, dim3(grid), dim3(256), 0, s_, v, count, bound, flag);
+  });
+}
+
+fcirc_status InputCheck::finish() {
+  if (!c_.check_inputs) return FCIRC_OK;
+  uint32_t bad = 0;
+  if (err_ == hipSuccess) err_ = hipMemcpyAsync(&bad, c_.d_status + 1, sizeof bad, hipMemcpyDeviceToHost, s_);
+  if (err_ == hipSuccess) err_ = hipStreamSynchronize(s_);
+  if (err_ != hipSuccess) return hip_status(err_);
+  return bad ? FCIRC_EINVAL : FCIRC_OK;
+}
+
+}  // namespace fcirc
+
 extern "C" {
 
 const char* fcirc_strerror(fcirc_status s) {
@@ -111,8 +162,9 @@ fcirc_status fcirc_create(fcirc_ctx** out, int dev) {
   ctx->c.prop = prop;
   if (const char* lim = std::getenv("FCIRC_WORKSPACE_LIMIT")) ctx->c.ws_limit = (size_t)std::strtoull(lim, nullptr, 10);
   if (const char* dbg = std::getenv("FCIRC_DEBUG_SYNC")) ctx->c.debug_sync = dbg[0] == '1';
-  if (hipMalloc(&ctx->c.d_status, sizeof(uint32_t)) != hipSuccess ||
-      hipMemset(ctx->c.d_status, 0, sizeof(uint32_t)) != hipSuccess) {
+  if (const char* val = std::getenv("FCIRC_VALIDATE")) ctx->c.check_inputs = val[0] == '1';
+  if (hipMalloc(&ctx->c.d_status, 2 * sizeof(uint32_t)) != hipSuccess ||
+      hipMemset(ctx->c.d_status, 0, 2 * sizeof(uint32_t)) != hipSuccess) {
     delete ctx;
     return FCIRC_EDEVICE;
   }
@@ -155,6 +207,9 @@ fcirc_status fcirc_matvec(fcirc_ctx* ctx, const void* a, const void* x, void* y,
   int L = 0;
   fcirc_status st = check_product(ctx, a, x, y, n, 1, f, ring, &L);
   if (st != FCIRC_OK) return st;
+  if (hipSetDevice(ctx->c.device) != hipSuccess) return FCIRC_EDEVICE;
+  st = check_inputs(ctx->c, ring, {a, x}, n * words_per_elem(ring), (hipStream_t)stream);
+  if (st != FCIRC_OK) return st;
   return dispatch(ctx, a, x, y, L, 1, f, ring, (hipStream_t)stream);
 }
 
@@ -165,6 +220,9 @@ fcirc_status fcirc_matvec_many(fcirc_ctx* ctx, const void* a, const void* x, voi
   fcirc_status st = check_product(ctx, a, x, y, n, count, f, ring, &L);
   if (st != FCIRC_OK) return st;
   if ((uint64_t)count * (n >> 12 ? (n >> 12) : 1) * 2 > 0x7fffffffull) return FCIRC_ESIZE;  // grid limit
+  if (hipSetDevice(ctx->c.device) != hipSuccess) return FCIRC_EDEVICE;
+  st = check_inputs(ctx->c, ring, {a, x}, n * count * words_per_elem(ring), (hipStream_t)stream);
+  if (st != FCIRC_OK) return st;
   return dispatch(ctx, a, x, y, L, count, f, ring, (hipStream_t)stream);
 }
 
@@ -192,6 +250,9 @@ fcirc_status fcirc_matvec_any(fcirc_ctx* ctx, const void* a, const void* x, void
   if (!f) return FCIRC_EINVAL;
   fcirc_status st = check_embed(ctx, a, x, y, n, f, ring);
   if (st != FCIRC_OK) return st;
+  if (hipSetDevice(ctx->c.device) != hipSuccess) return FCIRC_EDEVICE;
+  st = check_inputs(ctx->c, ring, {a, x}, n, (hipStream_t)stream);
+  if (st != FCIRC_OK) return st;
   int L = 0;
   if (is_pow2(n) && check_product(ctx, a, x, y, n, 1, f, ring, &L) == FCIRC_OK) {
     st = dispatch(ctx, a, x, y, L, 1, f, ring, (hipStream_t)stream);
@@ -208,6 +269,8 @@ fcirc_status fcirc_toeplitz_matvec(fcirc_ctx* ctx, const void* row, const void* 
   if (st != FCIRC_OK) return st;
   if (overlaps(y, (size_t)n * elem_bytes(ring), col, (size_t)n * elem_bytes(ring))) return FCIRC_EINVAL;
   if (hipSetDevice(ctx->c.device) != hipSuccess) return FCIRC_EDEVICE;
+  st = check_inputs(ctx->c, ring, {row, col, x}, n, (hipStream_t)stream);
+  if (st != FCIRC_OK) return st;
   return embed_product(ctx->c, ring, row, col, nullptr, x, y, n, (hipStream_t)stream);
 }
 
@@ -241,6 +304,13 @@ fcirc_status fcirc_check(fcirc_ctx* ctx, void* stream) {
     if (hipMemset(ctx->c.d_status, 0, sizeof(uint32_t)) != hipSuccess) return FCIRC_EDEVICE;
     return FCIRC_ERANGE;
   }
+  return FCIRC_OK;
+}
+
+fcirc_status fcirc_set_checks(fcirc_ctx* ctx, int flags) {
+  if (!ctx || (flags & ~(FCIRC_CHECK_INPUTS | FCIRC_CHECK_SYNC))) return FCIRC_EINVAL;
+  ctx->c.check_inputs = (flags & FCIRC_CHECK_INPUTS) != 0;
+  ctx->c.debug_sync = (flags & FCIRC_CHECK_SYNC) != 0;
   return FCIRC_OK;
 }
 

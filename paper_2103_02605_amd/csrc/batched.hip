@@ -465,6 +465,36 @@ fcirc_status build_and_launch(Ctx& c, const std::vector<uint64_t>& key, const vo
 
 using namespace fcirc;
 
+namespace {
+
+// FCIRC_CHECK_INPUTS over the union of the instances' input spans (instances may share
+// or overlap inputs; gaps between them are not inputs and are not checked).
+fcirc_status check_batched_inputs(Ctx& c, const void* a_base, const void* x_base, const fcirc_item* items,
+                                  uint32_t count, uint32_t p, hipStream_t s) {
+  InputCheck chk(c, p, s);
+  std::vector<std::pair<uint64_t, uint64_t>> iv(count);
+  for (int side = 0; side < 2; ++side) {
+    for (uint32_t i = 0; i < count; ++i) {
+      const uint64_t off = side ? items[i].x_off : items[i].a_off;
+      iv[i] = {off, off + (1ull << items[i].log2n)};
+    }
+    std::sort(iv.begin(), iv.end());
+    const uint32_t* base = (const uint32_t*)(side ? x_base : a_base);
+    uint64_t lo = iv[0].first, hi = iv[0].second;
+    for (size_t i = 1; i <= iv.size(); ++i) {
+      if (i < iv.size() && iv[i].first <= hi) {
+        hi = std::max(hi, iv[i].second);
+        continue;
+      }
+      chk.span(base + lo, hi - lo);
+      if (i < iv.size()) lo = iv[i].first, hi = iv[i].second;
+    }
+  }
+  return chk.finish();
+}
+
+}  // namespace
+
 extern "C" fcirc_status fcirc_matvec_batched(fcirc_ctx* ctx, const void* a_base, const void* x_base, void* y_base,
                                              const fcirc_item* items, uint32_t count, const void* f, fcirc_ring ring,
                                              void* stream) {
@@ -479,6 +509,10 @@ extern "C" fcirc_status fcirc_matvec_batched(fcirc_ctx* ctx, const void* a_base,
   Ctx& c = ctx->c;
   if (hipSetDevice(c.device) != hipSuccess) return FCIRC_EDEVICE;
   hipStream_t s = (hipStream_t)stream;
+  if (ring != FCIRC_C64 && c.check_inputs) {
+    fcirc_status st = check_batched_inputs(c, a_base, x_base, items, count, zp_prime(ring), s);
+    if (st != FCIRC_OK) return st;
+  }
   // key: ring, f, base pointers and the whole item list
   std::vector<uint64_t> key;
   key.reserve(8 + 4 * (size_t)count);

@@ -149,7 +149,8 @@ struct Ctx {
   void* ws2 = nullptr;  // operands of the embedded (arbitrary-n, Toeplitz) products
   size_t ws2_bytes = 0;
   size_t ws_limit = SIZE_MAX;  // bound on ws_bytes + ws2_bytes
-  uint32_t* d_status = nullptr;
+  uint32_t* d_status = nullptr;  // [0] sticky ERANGE word, [1] input-check flag
+  bool check_inputs = false;     // FCIRC_CHECK_INPUTS
   int forced_top = -1;
   std::map<TuneKey, TuneVal> tuned;
   Timer timer;
@@ -527,6 +528,22 @@ fcirc_status embed_product(Ctx& c, fcirc_ring ring, const void* r, const void* c
 fcirc_status polymul_i64(Ctx& c, const int32_t* a, uint64_t na, const int32_t* b, uint64_t nb, int64_t* out, hipStream_t s);
 fcirc_status bigint_mul(Ctx& c, const uint16_t* a, uint64_t na, const uint16_t* b, uint64_t nb, uint16_t* out, hipStream_t s);
 void release_graphs(Ctx& c);
+
+// The input range check of FCIRC_CHECK_INPUTS: one launch per span of 32-bit words,
+// then one synchronisation in finish(), which returns FCIRC_EINVAL if a word was >= bound.
+// With the check off, every member does nothing and finish() returns FCIRC_OK.
+class InputCheck {
+ public:
+  InputCheck(Ctx& c, uint32_t bound, hipStream_t s);
+  void span(const void* words, uint64_t count);
+  fcirc_status finish();
+
+ private:
+  Ctx& c_;
+  uint32_t bound_;
+  hipStream_t s_;
+  hipError_t err_ = hipSuccess;
+};
 
 inline fcirc_status hip_status(hipError_t e) {
   if (e == hipSuccess) return FCIRC_OK;

@@ -191,6 +191,15 @@ def check(device=None):
     L.check(L.lib().fcirc_check(ctx.handle, C.c_void_p(torch.cuda.current_stream().cuda_stream)), "fcirc_check")
 
 
+CHECK_INPUTS = 1  # Z/p and GF(p^2) inputs must be canonical; EINVAL otherwise (synchronises)
+CHECK_SYNC = 2    # synchronise after every kernel
+
+
+def set_checks(flags: int, device=None):
+    """Debugging checks of the device's context (defaults: FCIRC_VALIDATE, FCIRC_DEBUG_SYNC)."""
+    L.check(L.lib().fcirc_set_checks(context(device).handle, int(flags)), "fcirc_set_checks")
+
+
 def set_timing(enable: bool, device=None):
     L.check(L.lib().fcirc_set_timing(context(device).handle, int(bool(enable))), "fcirc_set_timing")
 
