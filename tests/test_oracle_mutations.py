@@ -152,3 +152,82 @@ def _mut_embed_short_length(mp):
 def test_embedding_pins_catch_mutation(mutation, monkeypatch):
     mutation(monkeypatch)
     assert not _embed_pins_pass()
+
+
+# --- section 3.2's ring Z/(2^K + 1) ------------------------------------------------------
+from oracle import fermat as OF  # noqa: E402
+
+
+def _fermat_pins_pass() -> bool:
+    """A compact re-run of the P16 pins: level form against the definition, and the
+    large-integer product against Python's."""
+    rng = random.Random(16)
+    try:
+        K, n = 64, 16
+        M = OF.modulus(K)
+        a = [rng.randrange(M) for _ in range(n)]
+        x = [rng.randrange(M) for _ in range(n)]
+        for f_exp in (0, K):
+            if OF.levels_matvec(a, x, f_exp, K) != OF.dense_matvec(a, x, pow(2, f_exp, M), K):
+                return False
+        u, v = rng.getrandbits(96 * 32), rng.getrandbits(96 * 32)
+        return OF.bigint_mul_ssa(u, v, 96, 64, 256) == u * v
+    except (ValueError, AssertionError):
+        return False
+
+
+def test_unmutated_fermat_passes():
+    assert _fermat_pins_pass()
+
+
+def _mut_fermat_second_child(mp):
+    def bad(L, f_exp, K):
+        levels = [[f_exp % (2 * K)]]
+        for _ in range(L):
+            levels.append([c for e in levels[-1] for c in (e // 2, e // 2)])  # -sqrt dropped
+        return levels
+    mp.setattr(OF, "node_exponents", bad)
+
+
+def _mut_fermat_merge_without_half(mp):
+    real_pow = pow
+
+    def levels(a, x, f_exp, K):  # the merge divides by g instead of 2g
+        M = OF.modulus(K)
+        n = len(a)
+        L = n.bit_length() - 1
+        nodes = OF.node_exponents(L, f_exp, K)
+        A, X = [v % M for v in a], [v % M for v in x]
+        for d in range(L):
+            m, h = n >> d, n >> (d + 1)
+            for b in range(1 << d):
+                g = real_pow(2, nodes[d + 1][2 * b], M)
+                for k in range(b * m, b * m + h):
+                    u, w = A[k], A[k + h]
+                    A[k], A[k + h] = (u + g * w) % M, (u - g * w) % M
+                    u, w = X[k], X[k + h]
+                    X[k], X[k + h] = (g * u + w) % M, (g * u - w) % M
+        Y = [A[k] * X[k] % M for k in range(n)]
+        for d in reversed(range(L)):
+            m, h = n >> d, n >> (d + 1)
+            for b in range(1 << d):
+                g = real_pow(2, nodes[d + 1][2 * b], M)
+                for k in range(b * m, b * m + h):
+                    s = Y[k] + Y[k + h]
+                    Y[k], Y[k + h] = s * real_pow(g, -1, M) % M, (s * real_pow(2, -1, M) - Y[k + h]) % M
+        return Y
+    mp.setattr(OF, "levels_matvec", levels)
+
+
+def _mut_fermat_row_not_reversed(mp):
+    def bad(u, v, P, N, K):
+        a, b = OF.bigint_pieces(u, P, N), OF.bigint_pieces(v, P, N)
+        return OF.bigint_recompose(OF.levels_matvec(a, b, 0, K), P)
+    mp.setattr(OF, "bigint_mul_ssa", bad)
+
+
+@pytest.mark.parametrize("mutation", [_mut_fermat_second_child, _mut_fermat_merge_without_half,
+                                      _mut_fermat_row_not_reversed])
+def test_fermat_pins_catch_mutation(mutation, monkeypatch):
+    mutation(monkeypatch)
+    assert not _fermat_pins_pass()

@@ -516,3 +516,72 @@ def test_p15_levels_sampled_at_2_14():
         y = OG2.levels_matvec(a, x, f)
         for i in (0, 1, 777, n - 1):
             assert tuple(int(c) for c in y[i]) == OG2.matvec_entry(a, x, f, i)
+
+
+# ----------------------------------------------------------------------------------
+# P16: section 3.2's ring Z/(2^K + 1), roots of unity as powers of two
+# ----------------------------------------------------------------------------------
+from oracle import fermat as OF  # noqa: E402
+
+
+@pytest.mark.parametrize("K", [8, 64, 2048])
+def test_p16_two_has_order_2k(K):
+    """2^K = -1, so 2 is a primitive 2K-th root of unity: 2^e != 1 for 0 < e < 2K
+    (checked at the divisors of 2K, which suffice since 2K is a power of two times K)."""
+    M = OF.modulus(K)
+    assert pow(2, K, M) == M - 1
+    assert pow(2, 2 * K, M) == 1
+    for e in range(1, 2 * K):
+        if (2 * K) % e == 0:
+            assert pow(2, e, M) != 1 or e == 2 * K
+
+
+def test_p16_square_roots_are_shifts():
+    K = 64
+    R = OF.Fermat(K, random.Random(1))
+    M = OF.modulus(K)
+    for e in range(0, 2 * K, 2):
+        r = R.sqrt(pow(2, e, M))
+        assert r * r % M == pow(2, e, M)
+        assert R.log2(r) in (e // 2, e // 2 + K)
+    with pytest.raises(ValueError):
+        R.sqrt(2)
+    with pytest.raises(ValueError):
+        R.sqrt(3)  # not a power of two
+
+
+@pytest.mark.parametrize("K,n", [(16, 8), (64, 16), (64, 32), (256, 32), (2048, 16)])
+def test_p16_recursion_matches_definition(K, n):
+    """Definition 2 (dense), Algorithm 1 with random choices of the roots, and the level
+    form with shift counts agree for f = 1, f = -1 = 2^K and f = 2^e (e a multiple of 2n)."""
+    rng = random.Random(K + n)
+    M = OF.modulus(K)
+    a = [rng.randrange(M) for _ in range(n)]
+    x = [rng.randrange(M) for _ in range(n)]
+    a[0], x[-1] = M - 1, M - 1  # the value 2^K itself
+    for f_exp in (0, K, 2 * n):
+        f = pow(2, f_exp, M)
+        want = OF.dense_matvec(a, x, f, K)
+        assert O.alg1_matvec(a, x, f, OF.Fermat(K, random.Random(n))) == want
+        assert OF.levels_matvec(a, x, f_exp, K) == want
+
+
+def test_p16_odd_exponent_has_no_root():
+    with pytest.raises(ValueError):
+        OF.levels_matvec([1, 2], [3, 4], 1, 64)
+    with pytest.raises(ValueError):
+        OF.node_exponents(6, 0, 16)  # 2^6 = 64 > 2K = 32: the ladder runs out of halvings
+
+
+@pytest.mark.parametrize("P,N,K", [(16, 8, 64), (64, 16, 256), (96, 64, 256), (1008, 64, 2048)])
+def test_p16_bigint_through_one_cyclic_product(P, N, K):
+    """Section 3.2: the product of two integers split into pieces of P bits is one cyclic
+    product over Z/(2^K + 1), recomposed; it equals Python's integer product."""
+    rng = random.Random(P * N)
+    for _ in range(3):
+        u = rng.getrandbits(P * (N // 2))
+        v = rng.getrandbits(P * (N // 2))
+        assert OF.bigint_mul_ssa(u, v, P, N, K) == u * v
+    top = (1 << (P * (N // 2))) - 1
+    assert OF.bigint_mul_ssa(top, top, P, N, K) == top * top
+    assert OF.bigint_mul_ssa(0, top, P, N, K) == 0
