@@ -140,6 +140,36 @@ fcirc_status fcirc_bigint_mul(fcirc_ctx *ctx, const uint16_t *a, uint64_t na, co
                               uint64_t nb, uint16_t *c, void *stream);
 
 /*
+ * The f-circulant product over Z/(2^K + 1), the ring of section 3.2: there 2^K = -1, so
+ * 2 is a root of unity of order 2K, f and every root Algorithm 1 uses are powers of two,
+ * and multiplying by a root is a shift by a known count (the roots are never computed).
+ *   K       : 2048, 4096, 8192 or 16384 bits.
+ *   a, x, y : device arrays of n elements, each K/32 + 1 uint32 words: the K/32 words of
+ *             the value (least significant first), then a top word that is 1 only for
+ *             the value 2^K. Inputs must be canonical (value in [0, 2^K]; top word 0 or 1,
+ *             and 1 only with all other words 0); y is canonical.
+ *   f       : 2^f_shift, 0 <= f_shift < 2K (f_shift = 0: cyclic, f_shift = K: f = -1).
+ *   n       : a power of two with 2^(L-1) | K (n <= 2^12 K / 2048, i.e. 2^12 .. 2^15).
+ * Algorithm 1 needs a power-of-two square root at every node: 2^L must divide f_shift,
+ * else ENOROOT. ESIZE: n not a power of two or too large for K. EINVAL: K not listed,
+ * f_shift >= 2K, null pointers, overlapping buffers.
+ */
+fcirc_status fcirc_fermat_matvec(fcirc_ctx *ctx, const uint32_t *a, const uint32_t *x, uint32_t *y,
+                                 uint64_t n, uint32_t K, uint32_t f_shift, void *stream);
+
+/*
+ * The same product as fcirc_bigint_mul, by the route section 3.2 describes: each factor is
+ * cut into pieces that become coefficients over Z/(2^K + 1), one cyclic product of
+ * fcirc_fermat_matvec's kind multiplies the two polynomials (pointwise products are full
+ * K-bit products at the leaves), and the coefficients are added back with carries. K and
+ * the number of pieces are chosen so that no coefficient reaches 2^K.
+ *   a : device uint16[na], b : device uint16[nb], c : device uint16[na+nb] (written).
+ * Requires na + nb - 1 <= 2^24; ESIZE if no parameter choice fits.
+ */
+fcirc_status fcirc_bigint_mul_fermat(fcirc_ctx *ctx, const uint16_t *a, uint64_t na, const uint16_t *b,
+                                     uint64_t nb, uint16_t *c, void *stream);
+
+/*
  * Many independent products of different power-of-two sizes in one persistent launch.
  * items (host array of `count`) give each instance's element offsets into a_base,
  * x_base and y_base and its log2 size (0 <= log2n <= 16). All instances share ring

@@ -41,6 +41,10 @@ SIGNATURES = {
                                     C.c_void_p]),
     "fcirc_bigint_mul": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint64, C.c_void_p, C.c_uint64, C.c_void_p,
                                    C.c_void_p]),
+    "fcirc_fermat_matvec": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64, C.c_uint32,
+                                      C.c_uint32, C.c_void_p]),
+    "fcirc_bigint_mul_fermat": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint64, C.c_void_p, C.c_uint64, C.c_void_p,
+                                          C.c_void_p]),
     "fcirc_matvec_batched": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(fcirc_item),
                                        C.c_uint32, C.c_void_p, C.c_int, C.c_void_p]),
     "fcirc_matvec_fwd_shared": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64, C.c_uint32,

@@ -294,6 +294,31 @@ fcirc_status fcirc_bigint_mul(fcirc_ctx* ctx, const uint16_t* a, uint64_t na, co
   return bigint_mul(ctx->c, a, na, b, nb, c, (hipStream_t)stream);
 }
 
+fcirc_status fcirc_fermat_matvec(fcirc_ctx* ctx, const uint32_t* a, const uint32_t* x, uint32_t* y, uint64_t n,
+                                 uint32_t K, uint32_t f_shift, void* stream) {
+  if (!ctx || !a || !x || !y) return FCIRC_EINVAL;
+  if (K != 2048 && K != 4096 && K != 8192 && K != 16384) return FCIRC_EINVAL;
+  if (f_shift >= 2 * K) return FCIRC_EINVAL;
+  if (!is_pow2(n)) return FCIRC_ESIZE;
+  const int L = ilog2(n);
+  if (L >= 1 && (K & ((1u << (L - 1)) - 1)) != 0) return FCIRC_ESIZE;  // 2^(L-1) | K
+  if (L >= 1 && (f_shift & ((1u << L) - 1)) != 0) return FCIRC_ENOROOT;
+  const size_t bytes = (size_t)n * (K / 32 + 1) * 4;
+  if (overlaps(y, bytes, a, bytes) || overlaps(y, bytes, x, bytes)) return FCIRC_EINVAL;
+  if (hipSetDevice(ctx->c.device) != hipSuccess) return FCIRC_EDEVICE;
+  return fermat_matvec(ctx->c, a, x, y, L, (int)(K / 2048), f_shift, (hipStream_t)stream);
+}
+
+fcirc_status fcirc_bigint_mul_fermat(fcirc_ctx* ctx, const uint16_t* a, uint64_t na, const uint16_t* b, uint64_t nb,
+                                     uint16_t* c, void* stream) {
+  if (!ctx || !a || !b || !c || na == 0 || nb == 0) return FCIRC_EINVAL;
+  const uint64_t nc = na + nb - 1;
+  if (nc > (1ull << 24)) return FCIRC_ESIZE;
+  if (overlaps(c, (nc + 1) * 2, a, na * 2) || overlaps(c, (nc + 1) * 2, b, nb * 2)) return FCIRC_EINVAL;
+  if (hipSetDevice(ctx->c.device) != hipSuccess) return FCIRC_EDEVICE;
+  return fermat_bigint_mul(ctx->c, a, na, b, nb, c, (hipStream_t)stream);
+}
+
 fcirc_status fcirc_check(fcirc_ctx* ctx, void* stream) {
   if (!ctx) return FCIRC_EINVAL;
   if (hipSetDevice(ctx->c.device) != hipSuccess) return FCIRC_EDEVICE;

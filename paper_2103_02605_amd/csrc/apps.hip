@@ -337,7 +337,15 @@ fcirc_status bigint_mul(Ctx& c, const uint16_t* a, uint64_t na, const uint16_t* 
     FCIRC_LAUNCH(e0_, e1_, k_crt_u64, dim3((uint32_t)((nc + 255) / 256)), dim3(256), 0, s, res, N, nc, K, coef, c.d_status);
   });
   if (e != hipSuccess) return hip_status(e);
-  e = launch(c, "fcirc_carry", s, [&](hipEvent_t e0_, hipEvent_t e1_) { FCIRC_LAUNCH(e0_, e1_, k_carry_scan1, dim3((uint32_t)nblk), dim3(CARRY_NT), 0, s, coef, nc, nl, u, summ); });
+  return carry_to_limbs(c, coef, nc, nl, u, summ, out, s);
+}
+
+uint64_t carry_blocks(uint64_t nl) { return (nl + CARRY_BLOCK - 1) / CARRY_BLOCK; }
+
+fcirc_status carry_to_limbs(Ctx& c, const uint64_t* coef, uint64_t nc, uint64_t nl, uint32_t* u, uint32_t* summ,
+                            uint16_t* out, hipStream_t s) {
+  const uint64_t nblk = carry_blocks(nl);
+  hipError_t e = launch(c, "fcirc_carry", s, [&](hipEvent_t e0_, hipEvent_t e1_) { FCIRC_LAUNCH(e0_, e1_, k_carry_scan1, dim3((uint32_t)nblk), dim3(CARRY_NT), 0, s, coef, nc, nl, u, summ); });
   if (e != hipSuccess) return hip_status(e);
   return hip_status(launch(c, "fcirc_carry", s, [&](hipEvent_t e0_, hipEvent_t e1_) { FCIRC_LAUNCH(e0_, e1_, k_carry_scan2, dim3((uint32_t)nblk), dim3(CARRY_NT), 0, s, u, nl, summ, out); }));
 }

@@ -1,0 +1,572 @@
+// The f-circulant product over Z/(2^K + 1), the ring that section 3.2 of Rosowski (arXiv
+// 2103.02605) proposes for Schoenhage-Strassen multiplication of large integers. There
+// 2^K = -1, so 2 has order 2K, the roots of unity are powers of two, and a multiplication
+// by a root is a shift: Algorithm 1 needs only the shift counts, no modular multiply and
+// no root tables. The pointwise products at the leaves are full K-bit products.
+//
+// Element layout in device memory: K/32 words, least significant first, then one word
+// that is 1 only for the value 2^K (= -1); canonical values lie in [0, 2^K], so an element
+// takes W + 1 words, W = K/32 = 64 Q. In registers one wave holds one element: lane l has
+// words [l Q, l Q + Q), and the top word is uniform over the wave. Carries cross lanes
+// through a carry-lookahead on wave ballots (generate / propagate bits per lane).
+//
+// Node roots: the value at node (d, b) of the recursion is 2^v with
+// v = (f_shift + 2K brev_d(b)) / 2^d mod 2K (the first child of a node 2^e takes 2^(e/2),
+// the second -2^(e/2) = 2^(e/2 + K)); node (d, b) uses the root g = 2^(v/2). This needs
+// 2^L | f_shift and 2^(L-1) | K.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "host.hpp"
+
+namespace fcirc {
+
+namespace {
+
+constexpr int FM_WAVES = 4;  // waves (elements or butterflies) per workgroup
+
+template <int Q>
+struct FE {
+  uint32_t w[Q];
+  uint32_t hi;  // uniform: 1 only for the value 2^K
+};
+
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ void wave_lds_sync() {
+  asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// r = a + b + cin over the wave's K-bit numbers; returns the carry out of bit K (uniform).
+// Each lane adds its Q words with carry-in 0; a lane generates a carry (G) or, being all
+// ones, propagates one (P). With A = G | P and B = G, the carries into the lanes are the
+// carries of the 64-bit sum A + B + cin (bit l of (A + B + cin) ^ A ^ B).
+template <int Q>
+__device__ __forceinline__ uint32_t wadd(uint32_t (&r)[Q], const uint32_t (&a)[Q], const uint32_t (&b)[Q], uint32_t cin) {
+  uint32_t c = 0, ones = 1;
+#pragma unroll
+  for (int s = 0; s < Q; ++s) {
+    const uint64_t t = (uint64_t)a[s] + b[s] + c;
+    r[s] = (uint32_t)t;
+    c = (uint32_t)(t >> 32);
+    ones &= r[s] == 0xffffffffu ? 1u : 0u;
+  }
+  const uint64_t G = __ballot(c != 0);
+  const uint64_t A = G | __ballot(ones != 0 && c == 0);
+  const uint64_t S = A + G;
+  const uint64_t S2 = S + (uint64_t)cin;
+  const uint32_t cout = (S < A ? 1u : 0u) | (S2 < S ? 1u : 0u);
+  uint32_t ci = (uint32_t)((S2 ^ A ^ G) >> lane_id()) & 1u;
+#pragma unroll
+  for (int s = 0; s < Q; ++s) {
+    const uint64_t t = (uint64_t)r[s] + ci;
+    r[s] = (uint32_t)t;
+    ci = (uint32_t)(t >> 32);
+  }
+  return cout;
+}
+
+// r = a + T, T a two's complement 96-bit value (t2:t1:t0) sign-extended to K bits.
+template <int Q>
+__device__ __forceinline__ uint32_t wadd_s96(uint32_t (&r)[Q], const uint32_t (&a)[Q], uint32_t t0, uint32_t t1,
+                                             uint32_t t2) {
+  const uint32_t ext = (int32_t)t2 < 0 ? 0xffffffffu : 0u;
+  const uint32_t base = lane_id() * Q;
+  uint32_t b[Q];
+#pragma unroll
+  for (int s = 0; s < Q; ++s) {
+    const uint32_t j = base + s;
+    b[s] = j == 0 ? t0 : (j == 1 ? t1 : (j == 2 ? t2 : ext));
+  }
+  return wadd<Q>(r, a, b, 0);
+}
+
+// The canonical element of r + T (r a K-bit number, |T| far below 2^K), using 2^K = -1:
+// r + T either fits in K bits, or overflows by 2^K (then the value is its low part - 1),
+// or goes below zero (then it is its low part + 2^K, i.e. low part + 1).
+template <int Q>
+__device__ __forceinline__ FE<Q> reduce96(const uint32_t (&r)[Q], uint32_t t0, uint32_t t1, uint32_t t2) {
+  FE<Q> o;
+  o.hi = 0;
+  const bool tneg = (int32_t)t2 < 0;
+  const uint32_t c = wadd_s96<Q>(o.w, r, t0, t1, t2);
+  const int u = (!tneg && c) ? -1 : ((tneg && !c) ? 1 : 0);
+  if (u != 0) {
+    uint32_t w2[Q];
+    const uint32_t e = u < 0 ? 0xffffffffu : 0u;
+    const uint32_t c2 = wadd_s96<Q>(w2, o.w, (uint32_t)u, e, e);
+    // -1 from 0, or +1 from 2^K - 1, lands on 2^K itself
+    const bool top = u < 0 ? c2 == 0 : c2 != 0;
+#pragma unroll
+    for (int s = 0; s < Q; ++s) o.w[s] = top ? 0u : w2[s];
+    o.hi = top ? 1u : 0u;
+  }
+  return o;
+}
+
+// The canonical element of r + h 2^K = r - h (h small).
+template <int Q>
+__device__ __forceinline__ FE<Q> reduce_hi(const uint32_t (&r)[Q], int32_t h) {
+  const uint32_t t = (uint32_t)(-h), e = -h < 0 ? 0xffffffffu : 0u;
+  return reduce96<Q>(r, t, e, e);
+}
+
+template <int Q>
+__device__ __forceinline__ FE<Q> fadd(const FE<Q>& a, const FE<Q>& b) {
+  uint32_t r[Q];
+  const uint32_t c = wadd<Q>(r, a.w, b.w, 0);
+  return reduce_hi<Q>(r, (int32_t)(c + a.hi + b.hi));
+}
+
+// a - b: a + (~b) + 1 = a - b + 2^K over K bits, with carry c: a - b = r + (c - 1) 2^K.
+template <int Q>
+__device__ __forceinline__ FE<Q> fsub(const FE<Q>& a, const FE<Q>& b) {
+  uint32_t nb[Q], r[Q];
+#pragma unroll
+  for (int s = 0; s < Q; ++s) nb[s] = ~b.w[s];
+  const uint32_t c = wadd<Q>(r, a.w, nb, 1);
+  return reduce_hi<Q>(r, (int32_t)c - 1 + (int32_t)a.hi - (int32_t)b.hi);
+}
+
+template <int Q>
+__device__ __forceinline__ FE<Q> fneg(const FE<Q>& a) {
+  FE<Q> z;
+#pragma unroll
+  for (int s = 0; s < Q; ++s) z.w[s] = 0;
+  z.hi = 0;
+  return fsub<Q>(z, a);
+}
+
+// y[s] = x[(s - ds) mod Q] for a uniform ds in [0, Q).
+template <int Q>
+__device__ __forceinline__ void rot_regs(uint32_t (&y)[Q], const uint32_t (&x)[Q], uint32_t ds) {
+#pragma unroll
+  for (int s = 0; s < Q; ++s) y[s] = x[s];
+#pragma unroll
+  for (int r = 1; r < Q; ++r)
+    if (ds == (uint32_t)r) {
+#pragma unroll
+      for (int s = 0; s < Q; ++s) y[s] = x[(s - r + Q) % Q];
+    }
+}
+
+// m[s] = word (j - d) mod W of x, where j = l Q + s is the word this lane holds (d uniform,
+// 0 <= d < W): register slot (s - d) mod Q of lane l - floor(d / Q) (one lane further
+// when s < d mod Q).
+template <int Q>
+__device__ __forceinline__ void fetch_rot(uint32_t (&m)[Q], const uint32_t (&x)[Q], uint32_t d) {
+  const uint32_t dl = d / Q, ds = d % Q, l = lane_id();
+  uint32_t y[Q];
+  rot_regs<Q>(y, x, ds);
+#pragma unroll
+  for (int s = 0; s < Q; ++s) {
+    const uint32_t delta = dl + ((uint32_t)s < ds ? 1u : 0u);
+    m[s] = __shfl(y[s], (int)((l - delta) & 63u), 64);
+  }
+}
+
+// x 2^e for 0 <= e < 2K. For e < K: x 2^e = lo + hp 2^K = lo - hp, where lo holds the low
+// K bits of the shifted value and hp the bits shifted past bit K; for e >= K the result is
+// negated (2^K = -1).
+template <int Q>
+__device__ __forceinline__ FE<Q> fshl(const FE<Q>& x, uint32_t e) {
+  constexpr uint32_t K = 32u * 64u * Q;
+  const bool negate = e >= K;
+  const uint32_t ee = negate ? e - K : e;
+  const uint32_t l = lane_id();
+  if (x.hi) {  // x = -1: x 2^ee = -2^ee
+    FE<Q> p;
+    p.hi = 0;
+#pragma unroll
+    for (int s = 0; s < Q; ++s) p.w[s] = (l * Q + s == (ee >> 5)) ? (1u << (ee & 31u)) : 0u;
+    return negate ? p : fneg<Q>(p);
+  }
+  if (ee == 0) return negate ? fneg<Q>(x) : x;
+  const uint32_t ws = ee >> 5, bs = ee & 31u;
+  uint32_t M[Q], F[Q];
+  fetch_rot<Q>(M, x.w, ws);  // word j - ws (mod W) of x
+  F[0] = __shfl(M[Q - 1], (int)((l + 63u) & 63u), 64);
+#pragma unroll
+  for (int s = 1; s < Q; ++s) F[s] = M[s - 1];  // word j - ws - 1 (mod W)
+  uint32_t lo[Q], hp[Q];
+#pragma unroll
+  for (int s = 0; s < Q; ++s) {
+    const uint32_t j = l * Q + s;
+    const bool w1 = j < ws, w2 = j <= ws;  // the source word wrapped past the top
+    const uint32_t mv = M[s] << bs;
+    const uint32_t fv = bs ? (F[s] >> (32u - bs)) : 0u;
+    lo[s] = (w1 ? 0u : mv) | (w2 ? 0u : fv);
+    hp[s] = (w1 ? mv : 0u) | (w2 ? fv : 0u);
+  }
+  uint32_t nb[Q], r[Q];
+  uint32_t c;
+  if (!negate) {
+#pragma unroll
+    for (int s = 0; s < Q; ++s) nb[s] = ~hp[s];
+    c = wadd<Q>(r, lo, nb, 1);
+  } else {
+#pragma unroll
+    for (int s = 0; s < Q; ++s) nb[s] = ~lo[s];
+    c = wadd<Q>(r, hp, nb, 1);
+  }
+  return reduce_hi<Q>(r, (int32_t)c - 1);
+}
+
+__device__ __forceinline__ void add96(uint32_t& a0, uint32_t& a1, uint32_t& a2, uint64_t p) {
+  const uint64_t t0 = (uint64_t)a0 + (uint32_t)p;
+  a0 = (uint32_t)t0;
+  const uint64_t t1 = (uint64_t)a1 + (uint32_t)(p >> 32) + (t0 >> 32);
+  a1 = (uint32_t)t1;
+  a2 += (uint32_t)(t1 >> 32);
+}
+
+// Sum of the three shifted word arrays X0 + X1 2^32 + X2 2^64 (each W words in LDS) as a
+// K-bit number r plus the part at or above 2^K, returned as a 96-bit value (uniform).
+template <int Q>
+__device__ __forceinline__ void combine3(uint32_t (&r)[Q], const uint32_t* x0, const uint32_t* x1, const uint32_t* x2,
+                                         uint32_t& s0, uint32_t& s1, uint32_t& s2) {
+  constexpr uint32_t W = 64u * Q;
+  const uint32_t l = lane_id();
+  uint32_t v0[Q], v1[Q], v2[Q], t[Q];
+#pragma unroll
+  for (int s = 0; s < Q; ++s) {
+    const uint32_t j = l * Q + s;
+    v0[s] = x0[j];
+    v1[s] = j >= 1 ? x1[j - 1] : 0u;
+    v2[s] = j >= 2 ? x2[j - 2] : 0u;
+  }
+  const uint32_t c1 = wadd<Q>(t, v0, v1, 0);
+  const uint32_t c2 = wadd<Q>(r, t, v2, 0);
+  // spill at 2^K: x1[W-1] + x2[W-2] + x2[W-1] 2^32 + the two carries
+  const uint64_t lo = (uint64_t)x1[W - 1] + x2[W - 2] + c1 + c2;
+  const uint64_t hi = (uint64_t)x2[W - 1] + (lo >> 32);
+  s0 = (uint32_t)lo;
+  s1 = (uint32_t)hi;
+  s2 = (uint32_t)(hi >> 32);
+}
+
+// a b mod 2^K + 1. The 32-bit word products are summed per column of the negacyclic
+// convolution: a_i b_j lands in column (i + j) mod W, with a minus sign when i + j >= W
+// (2^(32 W) = 2^K = -1). Lane l owns columns l + 64 m (m < Q); every column has exactly W
+// terms, so the lanes stay balanced. Positive and negative parts are kept apart in 96-bit
+// accumulators, moved to LDS, and recombined as K-bit numbers. sm: 8 W words of LDS.
+template <int Q>
+__device__ __forceinline__ FE<Q> fmul(const FE<Q>& a, const FE<Q>& b, uint32_t* sm) {
+  constexpr uint32_t W = 64u * Q;
+  const uint32_t l = lane_id();
+  if (a.hi || b.hi) {
+    if (a.hi && b.hi) {  // (-1)(-1) = 1
+      FE<Q> one;
+      one.hi = 0;
+#pragma unroll
+      for (int s = 0; s < Q; ++s) one.w[s] = (l * Q + s == 0) ? 1u : 0u;
+      return one;
+    }
+    return fneg<Q>(a.hi ? b : a);
+  }
+  uint32_t* sa = sm;
+  uint32_t* sb = sm + W;
+#pragma unroll
+  for (int s = 0; s < Q; ++s) {
+    sa[l * Q + s] = a.w[s];
+    sb[l * Q + s] = b.w[s];
+  }
+  wave_lds_sync();
+  uint32_t p0[Q], p1[Q], p2[Q], n0[Q], n1[Q], n2[Q];
+#pragma unroll
+  for (int m = 0; m < Q; ++m) p0[m] = p1[m] = p2[m] = n0[m] = n1[m] = n2[m] = 0;
+  // i = 64 t + u; column c_m = l + 64 m receives a_i b_((c_m - i) mod W), positive when
+  // i <= c_m: for t < m always, for t > m never, for t == m when u <= l.
+#pragma unroll
+  for (int t = 0; t < Q; ++t) {
+    for (uint32_t u = 0; u < 64u; ++u) {
+      const uint32_t i = 64u * t + u;
+      const uint32_t ai = sa[i];
+#pragma unroll
+      for (int m = 0; m < Q; ++m) {
+        const uint32_t j = (l + 64u * m + W - i) & (W - 1u);
+        const uint64_t pr = (uint64_t)ai * sb[j];
+        if (m > t) {
+          add96(p0[m], p1[m], p2[m], pr);
+        } else if (m < t) {
+          add96(n0[m], n1[m], n2[m], pr);
+        } else {
+          const uint64_t pp = u <= l ? pr : 0ull;
+          add96(p0[m], p1[m], p2[m], pp);
+          add96(n0[m], n1[m], n2[m], pr - pp);
+        }
+      }
+    }
+  }
+  wave_lds_sync();  // all reads of sa, sb done before the columns overwrite them
+  uint32_t* c0 = sm;  // [p0 p1 p2 n0 n1 n2], W words each
+#pragma unroll
+  for (int m = 0; m < Q; ++m) {
+    const uint32_t col = l + 64u * m;
+    c0[col] = p0[m];
+    c0[W + col] = p1[m];
+    c0[2 * W + col] = p2[m];
+    c0[3 * W + col] = n0[m];
+    c0[4 * W + col] = n1[m];
+    c0[5 * W + col] = n2[m];
+  }
+  wave_lds_sync();
+  uint32_t rp[Q], rn[Q];
+  uint32_t sp0, sp1, sp2, sn0, sn1, sn2;
+  combine3<Q>(rp, c0, c0 + W, c0 + 2 * W, sp0, sp1, sp2);
+  combine3<Q>(rn, c0 + 3 * W, c0 + 4 * W, c0 + 5 * W, sn0, sn1, sn2);
+  wave_lds_sync();  // the next call may overwrite this wave's LDS
+  // value = (rp - sp) - (rn - sn); rp - rn = d + (c - 1) 2^K = d + 1 - c
+  uint32_t nb[Q], d[Q];
+#pragma unroll
+  for (int s = 0; s < Q; ++s) nb[s] = ~rn[s];
+  const uint32_t c = wadd<Q>(d, rp, nb, 1);
+  // T = sn - sp + 1 - c as a two's complement 96-bit value
+  const unsigned __int128 spv = ((unsigned __int128)sp2 << 64) | ((uint64_t)sp1 << 32) | sp0;
+  const unsigned __int128 snv = ((unsigned __int128)sn2 << 64) | ((uint64_t)sn1 << 32) | sn0;
+  const unsigned __int128 T = snv - spv + 1u - c;
+  return reduce96<Q>(d, (uint32_t)T, (uint32_t)(T >> 32), (uint32_t)(T >> 64));
+}
+
+template <int Q>
+__device__ __forceinline__ FE<Q> fload(const uint32_t* p) {
+  FE<Q> e;
+  const uint32_t l = lane_id();
+#pragma unroll
+  for (int s = 0; s < Q; ++s) e.w[s] = p[l * Q + s];
+  e.hi = p[64u * Q];
+  return e;
+}
+
+template <int Q>
+__device__ __forceinline__ void fstore(uint32_t* p, const FE<Q>& e) {
+  const uint32_t l = lane_id();
+#pragma unroll
+  for (int s = 0; s < Q; ++s) p[l * Q + s] = e.w[s];
+  if (l == 0) p[64u * Q] = e.hi;
+}
+
+__device__ __forceinline__ uint32_t brev_bits(uint32_t v, uint32_t bits) {
+  return bits == 0 ? 0u : (__brev(v) >> (32u - bits));
+}
+
+// Shift count of the root g used at node (d, b): (f_shift + 2K brev_d(b)) / 2^(d+1) mod 2K.
+__device__ __forceinline__ uint32_t root_shift(uint32_t f_shift, uint32_t K, uint32_t d, uint32_t b) {
+  const uint32_t v = f_shift + 2u * K * brev_bits(b, d);
+  return (v >> (d + 1)) % (2u * K);
+}
+
+// One split level d: butterfly t of the row (u + g v, u - g v) and of the vector
+// (g u + v, g u - v), one wave each. src may equal dst (in place).
+template <int Q>
+__global__ void __launch_bounds__(64 * FM_WAVES) k_fm_split(const uint32_t* a_in, const uint32_t* x_in, uint32_t* wa,
+                                                            uint32_t* wx, uint32_t n, uint32_t d, uint32_t f_shift) {
+  constexpr uint32_t W = 64u * Q, K = 32u * W, S = W + 1;
+  const uint32_t t = blockIdx.x * FM_WAVES + (threadIdx.x >> 6);
+  if (t >= n / 2) return;
+  const uint32_t h = n >> (d + 1), b = t / h, k = b * 2 * h + (t - b * h);
+  const uint32_t e = root_shift(f_shift, K, d, b);
+  {
+    const FE<Q> u = fload<Q>(a_in + (size_t)k * S), v = fload<Q>(a_in + (size_t)(k + h) * S);
+    const FE<Q> gv = fshl<Q>(v, e);
+    const FE<Q> r0 = fadd<Q>(u, gv), r1 = fsub<Q>(u, gv);
+    fstore<Q>(wa + (size_t)k * S, r0);
+    fstore<Q>(wa + (size_t)(k + h) * S, r1);
+  }
+  {
+    const FE<Q> u = fload<Q>(x_in + (size_t)k * S), v = fload<Q>(x_in + (size_t)(k + h) * S);
+    const FE<Q> gu = fshl<Q>(u, e);
+    const FE<Q> r0 = fadd<Q>(gu, v), r1 = fsub<Q>(gu, v);
+    fstore<Q>(wx + (size_t)k * S, r0);
+    fstore<Q>(wx + (size_t)(k + h) * S, r1);
+  }
+}
+
+// Leaves: y_k = a_k x_k / n (1/n = 2^(2K - L)), one wave per element.
+template <int Q>
+__global__ void __launch_bounds__(64 * FM_WAVES) k_fm_leaf(const uint32_t* a, const uint32_t* x, uint32_t* y, uint32_t n,
+                                                           uint32_t L) {
+  constexpr uint32_t W = 64u * Q, K = 32u * W, S = W + 1;
+  __shared__ uint32_t sm[FM_WAVES * 8 * W];
+  const uint32_t wv = threadIdx.x >> 6;
+  const uint32_t k = blockIdx.x * FM_WAVES + wv;
+  if (k >= n) return;
+  const FE<Q> p = fmul<Q>(fload<Q>(a + (size_t)k * S), fload<Q>(x + (size_t)k * S), sm + wv * 8 * W);
+  fstore<Q>(y + (size_t)k * S, fshl<Q>(p, (2u * K - L) % (2u * K)));
+}
+
+// One merge level d (the 1/2 of each level is folded into the leaves):
+// (M1, M2) -> ((M1 + M2) / g, M1 - M2).
+template <int Q>
+__global__ void __launch_bounds__(64 * FM_WAVES) k_fm_merge(uint32_t* y, uint32_t n, uint32_t d, uint32_t f_shift) {
+  constexpr uint32_t W = 64u * Q, K = 32u * W, S = W + 1;
+  const uint32_t t = blockIdx.x * FM_WAVES + (threadIdx.x >> 6);
+  if (t >= n / 2) return;
+  const uint32_t h = n >> (d + 1), b = t / h, k = b * 2 * h + (t - b * h);
+  const uint32_t e = root_shift(f_shift, K, d, b);
+  const FE<Q> m1 = fload<Q>(y + (size_t)k * S), m2 = fload<Q>(y + (size_t)(k + h) * S);
+  const FE<Q> c1 = fshl<Q>(fadd<Q>(m1, m2), (2u * K - e) % (2u * K));
+  const FE<Q> c2 = fsub<Q>(m1, m2);
+  fstore<Q>(y + (size_t)k * S, c1);
+  fstore<Q>(y + (size_t)(k + h) * S, c2);
+}
+
+// Pieces of a large integer (16-bit limbs) as ring elements: element k holds piece j of
+// pw words (j = k, or j = (n - k) mod n for the reversed defining row), zero-extended.
+__global__ void k_fm_pack(const uint16_t* __restrict__ src, uint64_t nlimbs, uint32_t pw, uint32_t n, uint32_t W,
+                          uint32_t reverse, uint32_t* __restrict__ dst) {
+  const uint64_t idx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t S = (uint64_t)W + 1;
+  if (idx >= (uint64_t)n * S) return;
+  const uint32_t k = (uint32_t)(idx / S), w = (uint32_t)(idx % S);
+  const uint32_t j = reverse ? (n - k) & (n - 1u) : k;
+  uint32_t v = 0;
+  if (w < pw) {
+    const uint64_t l0 = 2 * ((uint64_t)j * pw + w);
+    const uint32_t lo = l0 < nlimbs ? src[l0] : 0u;
+    const uint32_t hi = l0 + 1 < nlimbs ? src[l0 + 1] : 0u;
+    v = lo | (hi << 16);
+  }
+  dst[idx] = v;
+}
+
+// coef[k] = sum over pieces j of limb k - j p16 of y_j (each y_j < 2^K, 2 W limbs).
+__global__ void k_fm_coef(const uint32_t* __restrict__ y, uint32_t n, uint32_t W, uint32_t p16, uint64_t nc,
+                          uint64_t* __restrict__ coef) {
+  const uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nc) return;
+  const uint64_t span = 2ull * W;  // limbs per element
+  const uint64_t jhi = std::min<uint64_t>(n - 1, k / p16);
+  const uint64_t jlo = k >= span ? (k - span) / p16 + 1 : 0;
+  uint64_t s = 0;
+  for (uint64_t j = jlo; j <= jhi; ++j) {
+    const uint64_t off = k - j * p16;  // < 2 W
+    const uint32_t word = y[j * ((uint64_t)W + 1) + (off >> 1)];
+    s += (off & 1) ? (word >> 16) : (word & 0xFFFFu);
+  }
+  coef[k] = s;
+}
+
+template <int Q>
+hipError_t fm_product_q(Ctx& c, const uint32_t* a, const uint32_t* x, uint32_t* y, int L, uint32_t f_shift, uint32_t* wa,
+                        uint32_t* wx, hipStream_t s) {
+  const uint32_t n = 1u << L;
+  const uint32_t gb = (n / 2 + FM_WAVES - 1) / FM_WAVES, gl = (n + FM_WAVES - 1) / FM_WAVES;
+  hipError_t e = hipSuccess;
+  const uint32_t* sa = a;
+  const uint32_t* sx = x;
+  for (int d = 0; d < L && e == hipSuccess; ++d) {
+    const uint32_t dd = (uint32_t)d;
+    e = launch(c, "fcirc_fermat_split", s, [&](hipEvent_t e0_, hipEvent_t e1_) {
+      FCIRC_LAUNCH(e0_, e1_, k_fm_split<Q>, dim3(gb), dim3(64 * FM_WAVES), 0, s, sa, sx, wa, wx, n, dd, f_shift);
+    });
+    sa = wa;
+    sx = wx;
+  }
+  if (e != hipSuccess) return e;
+  const uint32_t LL = (uint32_t)L;
+  e = launch(c, "fcirc_fermat_leaf", s, [&](hipEvent_t e0_, hipEvent_t e1_) {
+    FCIRC_LAUNCH(e0_, e1_, k_fm_leaf<Q>, dim3(gl), dim3(64 * FM_WAVES), 0, s, sa, sx, y, n, LL);
+  });
+  for (int d = L - 1; d >= 0 && e == hipSuccess; --d) {
+    const uint32_t dd = (uint32_t)d;
+    e = launch(c, "fcirc_fermat_merge", s, [&](hipEvent_t e0_, hipEvent_t e1_) {
+      FCIRC_LAUNCH(e0_, e1_, k_fm_merge<Q>, dim3(gb), dim3(64 * FM_WAVES), 0, s, y, n, dd, f_shift);
+    });
+  }
+  return e;
+}
+
+// Workspace: two arrays of n elements (the transformed row and vector).
+hipError_t fm_product(Ctx& c, const uint32_t* a, const uint32_t* x, uint32_t* y, int L, int q, uint32_t f_shift,
+                      uint32_t* wa, uint32_t* wx, hipStream_t s) {
+  switch (q) {
+    case 1: return fm_product_q<1>(c, a, x, y, L, f_shift, wa, wx, s);
+    case 2: return fm_product_q<2>(c, a, x, y, L, f_shift, wa, wx, s);
+    case 4: return fm_product_q<4>(c, a, x, y, L, f_shift, wa, wx, s);
+    case 8: return fm_product_q<8>(c, a, x, y, L, f_shift, wa, wx, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// Parameters of the large-integer product: words per lane q (K = 2048 q), log2 of the
+// number of pieces L, and piece size pw words. The coefficients of the product stay below
+// 2^K when 32 pw 2 + L <= K (at most 2^(L-1) nonzero products of pieces < 2^(32 pw)), the
+// pieces of both factors fit in 2^L, and 2^(L-1) | K. Among the feasible (q, L) the one
+// with the fewest estimated operations wins (3 L levels of W-word butterflies, and W^2
+// word products per leaf).
+struct FmPlan {
+  int q = 0, L = 0;
+  uint32_t pw = 0;
+};
+
+FmPlan fm_plan(uint64_t na, uint64_t nb) {
+  FmPlan best;
+  double best_cost = 0;
+  for (int q : {1, 2, 4, 8}) {
+    const uint32_t K = 2048u * q, W = 64u * q;
+    const int lmax = 12 + ilog2((uint64_t)q);
+    for (int L = 1; L <= lmax; ++L) {
+      const uint32_t pw = (K - (uint32_t)L) / 64u;  // 64 pw + L <= K
+      if (pw == 0) break;
+      const uint64_t pa = (na + 2ull * pw - 1) / (2ull * pw), pb = (nb + 2ull * pw - 1) / (2ull * pw);
+      if (pa + pb - 1 > (1ull << L)) continue;
+      const double cost = (double)(1ull << L) * W * (3.0 * L * 40.0 + 6.0 * W);
+      if (best.q == 0 || cost < best_cost) {
+        best = FmPlan{q, L, pw};
+        best_cost = cost;
+      }
+      break;  // larger L with the same q only costs more
+    }
+  }
+  return best;
+}
+
+}  // namespace
+
+fcirc_status fermat_matvec(Ctx& c, const uint32_t* a, const uint32_t* x, uint32_t* y, int L, int q, uint32_t f_shift,
+                           hipStream_t s) {
+  const uint64_t elems = ((uint64_t)1 << L) * (64ull * q + 1);
+  fcirc_status st = ws_reserve(c, 2 * elems * sizeof(uint32_t));
+  if (st != FCIRC_OK) return st;
+  uint32_t* wa = (uint32_t*)c.ws;
+  return hip_status(fm_product(c, a, x, y, L, q, f_shift, wa, wa + elems, s));
+}
+
+fcirc_status fermat_bigint_mul(Ctx& c, const uint16_t* a, uint64_t na, const uint16_t* b, uint64_t nb, uint16_t* out,
+                               hipStream_t s) {
+  const FmPlan P = fm_plan(na, nb);
+  if (P.q == 0) return FCIRC_ESIZE;
+  const uint32_t n = 1u << P.L, W = 64u * P.q;
+  const uint64_t elems = (uint64_t)n * (W + 1);
+  // every limb position of the product (a coefficient y_j spans 2 W limbs from position
+  // j p16 on, so its upper limbs land above position na + nb - 2)
+  const uint64_t nl = na + nb, nc = nl, nblk = carry_blocks(nl);
+  // layout (uint32 units): row | vector | y | transformed row | transformed vector | coef u64[nc] | u[nl] | summaries
+  const uint64_t off_c = 5 * elems, off_u = off_c + 2 * nc, off_s = off_u + nl, total = off_s + 2 * nblk;
+  fcirc_status st = ws_reserve(c, total * sizeof(uint32_t));
+  if (st != FCIRC_OK) return st;
+  uint32_t* base = (uint32_t*)c.ws;
+  uint32_t *row = base, *vec = base + elems, *y = base + 2 * elems, *wa = base + 3 * elems, *wx = base + 4 * elems;
+  uint64_t* coef = (uint64_t*)(base + off_c);
+  const uint32_t grid_p = (uint32_t)((elems + 255) / 256);
+  const uint32_t pw = P.pw;
+  hipError_t e = launch(c, "fcirc_fermat_pack", s, [&](hipEvent_t e0_, hipEvent_t e1_) {
+    FCIRC_LAUNCH(e0_, e1_, k_fm_pack, dim3(grid_p), dim3(256), 0, s, a, na, pw, n, W, 1u, row);
+  });
+  if (e == hipSuccess)
+    e = launch(c, "fcirc_fermat_pack", s, [&](hipEvent_t e0_, hipEvent_t e1_) {
+      FCIRC_LAUNCH(e0_, e1_, k_fm_pack, dim3(grid_p), dim3(256), 0, s, b, nb, pw, n, W, 0u, vec);
+    });
+  if (e == hipSuccess) e = fm_product(c, row, vec, y, P.L, P.q, 0u, wa, wx, s);
+  if (e == hipSuccess)
+    e = launch(c, "fcirc_fermat_coef", s, [&](hipEvent_t e0_, hipEvent_t e1_) {
+      FCIRC_LAUNCH(e0_, e1_, k_fm_coef, dim3((uint32_t)((nc + 255) / 256)), dim3(256), 0, s, y, n, W, 2u * pw, nc, coef);
+    });
+  if (e != hipSuccess) return hip_status(e);
+  return carry_to_limbs(c, coef, nc, nl, base + off_u, base + off_s, out, s);
+}
+
+}  // namespace fcirc

@@ -528,6 +528,15 @@ fcirc_status embed_product(Ctx& c, fcirc_ring ring, const void* r, const void* c
 fcirc_status polymul_i64(Ctx& c, const int32_t* a, uint64_t na, const int32_t* b, uint64_t nb, int64_t* out, hipStream_t s);
 fcirc_status bigint_mul(Ctx& c, const uint16_t* a, uint64_t na, const uint16_t* b, uint64_t nb, uint16_t* out, hipStream_t s);
 void release_graphs(Ctx& c);
+// Limbs of sum_k coef[k] 2^(16 k) (coef[k] < 2^64, k < nc) into out[0, nl); u holds nl and
+// summ 2 carry_blocks(nl) words of scratch.
+uint64_t carry_blocks(uint64_t nl);
+fcirc_status carry_to_limbs(Ctx& c, const uint64_t* coef, uint64_t nc, uint64_t nl, uint32_t* u, uint32_t* summ,
+                            uint16_t* out, hipStream_t s);
+fcirc_status fermat_matvec(Ctx& c, const uint32_t* a, const uint32_t* x, uint32_t* y, int L, int q, uint32_t f_exp,
+                           hipStream_t s);
+fcirc_status fermat_bigint_mul(Ctx& c, const uint16_t* a, uint64_t na, const uint16_t* b, uint64_t nb, uint16_t* out,
+                               hipStream_t s);
 
 // The input range check of FCIRC_CHECK_INPUTS: one launch per span of 32-bit words,
 // then one synchronisation in finish(), which returns FCIRC_EINVAL if a word was >= bound.

@@ -185,6 +185,38 @@ def bigint_mul(a: torch.Tensor, b: torch.Tensor, out: torch.Tensor | None = None
     return c
 
 
+def fermat_matvec(a: torch.Tensor, x: torch.Tensor, K: int, f_shift: int = 0, out: torch.Tensor | None = None):
+    """y = A(a, 2^f_shift) x over Z/(2^K + 1) (section 3.2's ring; roots are shifts).
+
+    a, x: int32/uint32 tensors of shape (n, K/32 + 1), one element per row: K/32 words of
+    the value (least significant first), then the top word (1 only for the value 2^K)."""
+    _need(a, "a")
+    _need(x, "x")
+    if a.dtype not in (torch.int32, torch.uint32) or a.dim() != 2 or a.shape != x.shape or a.dtype != x.dtype:
+        raise ValueError("a and x must be (n, K/32 + 1) int32 tensors of the same shape")
+    if a.shape[1] != K // 32 + 1:
+        raise ValueError(f"elements of Z/(2^{K} + 1) take {K // 32 + 1} words")
+    y = torch.empty_like(a) if out is None else out
+    _need(y, "out")
+    ctx = context(a.device)
+    L.check(L.lib().fcirc_fermat_matvec(ctx.handle, _ptr(a), _ptr(x), _ptr(y), a.shape[0], int(K), int(f_shift),
+                                        _stream(a)), "fcirc_fermat_matvec")
+    return y
+
+
+def bigint_mul_fermat(a: torch.Tensor, b: torch.Tensor, out: torch.Tensor | None = None):
+    """bigint_mul by section 3.2's route: one cyclic product over Z/(2^K + 1)."""
+    _need(a, "a")
+    _need(b, "b")
+    if a.dtype not in (torch.int16, torch.uint16) or b.dtype != a.dtype:
+        raise TypeError("bigint_mul_fermat takes uint16 (or int16-viewed) limb tensors")
+    c = torch.empty(a.numel() + b.numel(), dtype=a.dtype, device=a.device) if out is None else out
+    ctx = context(a.device)
+    L.check(L.lib().fcirc_bigint_mul_fermat(ctx.handle, _ptr(a), a.numel(), _ptr(b), b.numel(), _ptr(c), _stream(a)),
+            "fcirc_bigint_mul_fermat")
+    return c
+
+
 def check(device=None):
     """Synchronise the current stream and raise on a sticky device-side error (ERANGE)."""
     ctx = context(device)
