@@ -171,12 +171,30 @@ def secondary(torch, F, W, quick: bool):
     c = torch.empty(1 << 21, dtype=torch.int16, device="cuda")
     ms = time_steps(torch, lambda i: F.bigint_mul(ta, tb, out=c), 20 if quick else 100, 5)
     out["bigint_mul_2x2^24bit"] = {"ms": ms, "Glimb_per_s": (1 << 21) / ms / 1e6}
+    out["bigint_fermat_2x2^24bit"] = bigint_fermat(torch, F, ta, tb, ms, quick)
     out["c1_n1024_latency"] = c1_latency(torch, F, W)
     out["circulant_vs_fft_c64_2^21"] = circulant_vs_fft(torch, F, W, quick)
     out["gfp2_section3_ring_2^21"] = gfp2_product(torch, F, quick)
     out["batched_c64_4096"] = batched_vs_plain(torch, F, W, quick)
     out["layer_fwd_bwd_256x2^14"] = layer_vs_plain(torch, F, W, quick)
     return out
+
+
+def bigint_fermat(torch, F, ta, tb, ms_ntt, quick: bool):
+    """Section 3.2's route for the C3 integers (2 x 2^24 bits, seed 5): pieces as
+    coefficients over Z/(2^K + 1), one cyclic product with shift-only roots. Compared with
+    the three-prime route on the same inputs; both give the same limbs."""
+    c = torch.empty(1 << 21, dtype=torch.int16, device="cuda")
+    ms = time_steps(torch, lambda i: F.bigint_mul_fermat(ta, tb, out=c), 5 if quick else 30, 2)
+    F.set_timing(True)
+    F.bigint_mul_fermat(ta, tb, out=c)
+    st = F.stage_times()
+    F.set_timing(False)
+    ref = F.bigint_mul(ta, tb)
+    same = bool(torch.equal(ref, c))
+    kern = {k: round(v[1] * 1e3, 1) for k, v in st.items() if k.startswith("fcirc_fermat") and v[0]}
+    return {"ms": ms, "Glimb_per_s": (1 << 21) / ms / 1e6, "over_three_prime": ms / ms_ntt, "same_limbs": same,
+            "kernel_us": kern}
 
 
 def circulant_vs_fft(torch, F, W, quick: bool):

@@ -251,7 +251,8 @@ __device__ __forceinline__ void combine3(uint32_t (&r)[Q], const uint32_t* x0, c
 // convolution: a_i b_j lands in column (i + j) mod W, with a minus sign when i + j >= W
 // (2^(32 W) = 2^K = -1). Lane l owns columns l + 64 m (m < Q); every column has exactly W
 // terms, so the lanes stay balanced. Positive and negative parts are kept apart in 96-bit
-// accumulators, moved to LDS, and recombined as K-bit numbers. sm: 8 W words of LDS.
+// accumulators, moved to LDS, and recombined as K-bit numbers. sm: 8 W words of LDS (a,
+// then b twice while the columns are summed; the six column arrays afterwards).
 template <int Q>
 __device__ __forceinline__ FE<Q> fmul(const FE<Q>& a, const FE<Q>& b, uint32_t* sm) {
   constexpr uint32_t W = 64u * Q;
@@ -267,11 +268,12 @@ __device__ __forceinline__ FE<Q> fmul(const FE<Q>& a, const FE<Q>& b, uint32_t* 
     return fneg<Q>(a.hi ? b : a);
   }
   uint32_t* sa = sm;
-  uint32_t* sb = sm + W;
+  uint32_t* sb = sm + W;  // b twice: sb[j] = sb[j + W] = b_j, so (c - i) mod W needs no wrap
 #pragma unroll
   for (int s = 0; s < Q; ++s) {
     sa[l * Q + s] = a.w[s];
     sb[l * Q + s] = b.w[s];
+    sb[W + l * Q + s] = b.w[s];
   }
   wave_lds_sync();
   uint32_t p0[Q], p1[Q], p2[Q], n0[Q], n1[Q], n2[Q];
@@ -281,13 +283,14 @@ __device__ __forceinline__ FE<Q> fmul(const FE<Q>& a, const FE<Q>& b, uint32_t* 
   // i <= c_m: for t < m always, for t > m never, for t == m when u <= l.
 #pragma unroll
   for (int t = 0; t < Q; ++t) {
+#pragma unroll(Q <= 4 ? 4 : 1)
     for (uint32_t u = 0; u < 64u; ++u) {
       const uint32_t i = 64u * t + u;
       const uint32_t ai = sa[i];
+      const uint32_t* sbi = sb + (l + W - i);  // column c_m reads sbi[64 m], index in [1, 2W)
 #pragma unroll
       for (int m = 0; m < Q; ++m) {
-        const uint32_t j = (l + 64u * m + W - i) & (W - 1u);
-        const uint64_t pr = (uint64_t)ai * sb[j];
+        const uint64_t pr = (uint64_t)ai * sbi[64 * m];
         if (m > t) {
           add96(p0[m], p1[m], p2[m], pr);
         } else if (m < t) {
@@ -384,6 +387,51 @@ __global__ void __launch_bounds__(64 * FM_WAVES) k_fm_split(const uint32_t* a_in
   }
 }
 
+// Two split levels d, d + 1 in one pass: a wave takes elements k, k + m/4, k + m/2,
+// k + 3m/4 of a depth-d block of m elements, splits them with node (d, b)'s root, then each
+// half with the root of its child node (d + 1, 2b) or (d + 1, 2b + 1).
+template <int Q>
+__global__ void __launch_bounds__(64 * FM_WAVES) k_fm_split2(const uint32_t* a_in, const uint32_t* x_in, uint32_t* wa,
+                                                             uint32_t* wx, uint32_t n, uint32_t d, uint32_t f_shift) {
+  constexpr uint32_t W = 64u * Q, K = 32u * W, S = W + 1;
+  const uint32_t t = blockIdx.x * FM_WAVES + (threadIdx.x >> 6);
+  if (t >= n / 4) return;
+  const uint32_t q4 = n >> (d + 2), b = t / q4, k = b * 4 * q4 + (t - b * q4);
+  const uint32_t e0 = root_shift(f_shift, K, d, b);
+  const uint32_t e1 = root_shift(f_shift, K, d + 1, 2 * b), e2 = root_shift(f_shift, K, d + 1, 2 * b + 1);
+  const size_t o0 = (size_t)k * S, o1 = (size_t)(k + q4) * S, o2 = (size_t)(k + 2 * q4) * S, o3 = (size_t)(k + 3 * q4) * S;
+  {  // row: (u, v) -> (u + g v, u - g v)
+    FE<Q> v0 = fload<Q>(a_in + o0), v1 = fload<Q>(a_in + o1), v2 = fload<Q>(a_in + o2), v3 = fload<Q>(a_in + o3);
+    FE<Q> g = fshl<Q>(v2, e0);
+    v2 = fsub<Q>(v0, g);
+    v0 = fadd<Q>(v0, g);
+    g = fshl<Q>(v3, e0);
+    v3 = fsub<Q>(v1, g);
+    v1 = fadd<Q>(v1, g);
+    g = fshl<Q>(v1, e1);
+    fstore<Q>(wa + o1, fsub<Q>(v0, g));
+    fstore<Q>(wa + o0, fadd<Q>(v0, g));
+    g = fshl<Q>(v3, e2);
+    fstore<Q>(wa + o3, fsub<Q>(v2, g));
+    fstore<Q>(wa + o2, fadd<Q>(v2, g));
+  }
+  {  // vector: (u, v) -> (g u + v, g u - v)
+    FE<Q> v0 = fload<Q>(x_in + o0), v1 = fload<Q>(x_in + o1), v2 = fload<Q>(x_in + o2), v3 = fload<Q>(x_in + o3);
+    FE<Q> g = fshl<Q>(v0, e0);
+    v0 = fadd<Q>(g, v2);
+    v2 = fsub<Q>(g, v2);
+    g = fshl<Q>(v1, e0);
+    v1 = fadd<Q>(g, v3);
+    v3 = fsub<Q>(g, v3);
+    g = fshl<Q>(v0, e1);
+    fstore<Q>(wx + o0, fadd<Q>(g, v1));
+    fstore<Q>(wx + o1, fsub<Q>(g, v1));
+    g = fshl<Q>(v2, e2);
+    fstore<Q>(wx + o2, fadd<Q>(g, v3));
+    fstore<Q>(wx + o3, fsub<Q>(g, v3));
+  }
+}
+
 // Leaves: y_k = a_k x_k / n (1/n = 2^(2K - L)), one wave per element.
 template <int Q>
 __global__ void __launch_bounds__(64 * FM_WAVES) k_fm_leaf(const uint32_t* a, const uint32_t* x, uint32_t* y, uint32_t n,
@@ -411,6 +459,33 @@ __global__ void __launch_bounds__(64 * FM_WAVES) k_fm_merge(uint32_t* y, uint32_
   const FE<Q> c2 = fsub<Q>(m1, m2);
   fstore<Q>(y + (size_t)k * S, c1);
   fstore<Q>(y + (size_t)(k + h) * S, c2);
+}
+
+// Two merge levels d + 1, d in one pass (the inverse order of k_fm_split2).
+template <int Q>
+__global__ void __launch_bounds__(64 * FM_WAVES) k_fm_merge2(uint32_t* y, uint32_t n, uint32_t d, uint32_t f_shift) {
+  constexpr uint32_t W = 64u * Q, K = 32u * W, S = W + 1;
+  const uint32_t t = blockIdx.x * FM_WAVES + (threadIdx.x >> 6);
+  if (t >= n / 4) return;
+  const uint32_t q4 = n >> (d + 2), b = t / q4, k = b * 4 * q4 + (t - b * q4);
+  const uint32_t e0 = root_shift(f_shift, K, d, b);
+  const uint32_t e1 = root_shift(f_shift, K, d + 1, 2 * b), e2 = root_shift(f_shift, K, d + 1, 2 * b + 1);
+  const size_t o0 = (size_t)k * S, o1 = (size_t)(k + q4) * S, o2 = (size_t)(k + 2 * q4) * S, o3 = (size_t)(k + 3 * q4) * S;
+  FE<Q> v0 = fload<Q>(y + o0), v1 = fload<Q>(y + o1), v2 = fload<Q>(y + o2), v3 = fload<Q>(y + o3);
+  // level d + 1: (M1, M2) -> ((M1 + M2) / g, M1 - M2) in both children
+  FE<Q> sum = fadd<Q>(v0, v1);
+  v1 = fsub<Q>(v0, v1);
+  v0 = fshl<Q>(sum, (2u * K - e1) % (2u * K));
+  sum = fadd<Q>(v2, v3);
+  v3 = fsub<Q>(v2, v3);
+  v2 = fshl<Q>(sum, (2u * K - e2) % (2u * K));
+  // level d
+  sum = fadd<Q>(v0, v2);
+  fstore<Q>(y + o2, fsub<Q>(v0, v2));
+  fstore<Q>(y + o0, fshl<Q>(sum, (2u * K - e0) % (2u * K)));
+  sum = fadd<Q>(v1, v3);
+  fstore<Q>(y + o3, fsub<Q>(v1, v3));
+  fstore<Q>(y + o1, fshl<Q>(sum, (2u * K - e0) % (2u * K)));
 }
 
 // Pieces of a large integer (16-bit limbs) as ring elements: element k holds piece j of
@@ -454,14 +529,21 @@ hipError_t fm_product_q(Ctx& c, const uint32_t* a, const uint32_t* x, uint32_t* 
                         uint32_t* wx, hipStream_t s) {
   const uint32_t n = 1u << L;
   const uint32_t gb = (n / 2 + FM_WAVES - 1) / FM_WAVES, gl = (n + FM_WAVES - 1) / FM_WAVES;
+  const uint32_t g4 = (n / 4 + FM_WAVES - 1) / FM_WAVES;
   hipError_t e = hipSuccess;
   const uint32_t* sa = a;
   const uint32_t* sx = x;
-  for (int d = 0; d < L && e == hipSuccess; ++d) {
+  // levels in pairs (radix 4); an odd last level alone
+  for (int d = 0; d < L && e == hipSuccess; d += 2) {
     const uint32_t dd = (uint32_t)d;
-    e = launch(c, "fcirc_fermat_split", s, [&](hipEvent_t e0_, hipEvent_t e1_) {
-      FCIRC_LAUNCH(e0_, e1_, k_fm_split<Q>, dim3(gb), dim3(64 * FM_WAVES), 0, s, sa, sx, wa, wx, n, dd, f_shift);
-    });
+    if (d + 1 < L)
+      e = launch(c, "fcirc_fermat_split", s, [&](hipEvent_t e0_, hipEvent_t e1_) {
+        FCIRC_LAUNCH(e0_, e1_, k_fm_split2<Q>, dim3(g4), dim3(64 * FM_WAVES), 0, s, sa, sx, wa, wx, n, dd, f_shift);
+      });
+    else
+      e = launch(c, "fcirc_fermat_split", s, [&](hipEvent_t e0_, hipEvent_t e1_) {
+        FCIRC_LAUNCH(e0_, e1_, k_fm_split<Q>, dim3(gb), dim3(64 * FM_WAVES), 0, s, sa, sx, wa, wx, n, dd, f_shift);
+      });
     sa = wa;
     sx = wx;
   }
@@ -470,11 +552,17 @@ hipError_t fm_product_q(Ctx& c, const uint32_t* a, const uint32_t* x, uint32_t* 
   e = launch(c, "fcirc_fermat_leaf", s, [&](hipEvent_t e0_, hipEvent_t e1_) {
     FCIRC_LAUNCH(e0_, e1_, k_fm_leaf<Q>, dim3(gl), dim3(64 * FM_WAVES), 0, s, sa, sx, y, n, LL);
   });
-  for (int d = L - 1; d >= 0 && e == hipSuccess; --d) {
+  // the same pairs in reverse: the odd last level first, alone
+  for (int d = (L - 1) & ~1; d >= 0 && e == hipSuccess; d -= 2) {
     const uint32_t dd = (uint32_t)d;
-    e = launch(c, "fcirc_fermat_merge", s, [&](hipEvent_t e0_, hipEvent_t e1_) {
-      FCIRC_LAUNCH(e0_, e1_, k_fm_merge<Q>, dim3(gb), dim3(64 * FM_WAVES), 0, s, y, n, dd, f_shift);
-    });
+    if (d + 1 < L)
+      e = launch(c, "fcirc_fermat_merge", s, [&](hipEvent_t e0_, hipEvent_t e1_) {
+        FCIRC_LAUNCH(e0_, e1_, k_fm_merge2<Q>, dim3(g4), dim3(64 * FM_WAVES), 0, s, y, n, dd, f_shift);
+      });
+    else
+      e = launch(c, "fcirc_fermat_merge", s, [&](hipEvent_t e0_, hipEvent_t e1_) {
+        FCIRC_LAUNCH(e0_, e1_, k_fm_merge<Q>, dim3(gb), dim3(64 * FM_WAVES), 0, s, y, n, dd, f_shift);
+      });
   }
   return e;
 }
