@@ -300,6 +300,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip timing the CPU oracle")
     ap.add_argument("--no-secondary", action="store_true", help="skip the secondary workloads")
+    ap.add_argument("--quick-secondary", action="store_true", help="time the secondary workloads with fewer steps")
     ap.add_argument("--calib-copy", action="store_true",
                     help="first run 3 plain 64 MiB device copies (torch), the reference for HBM byte counters")
     args = ap.parse_args()
@@ -357,7 +358,7 @@ def main():
                        "split": {"top_levels": T, "block_levels": B}},
             "roofline": roofline}
     if not args.no_secondary:
-        line["secondary"] = secondary(torch, F, W, quick=False)
+        line["secondary"] = secondary(torch, F, W, quick=args.quick_secondary)
     if not args.no_cpu_baseline:
         cb = cpu_baseline(W)
         line["cpu_baseline"] = cb
