@@ -115,3 +115,18 @@ def fcirc_any_matvec_modp(a, x, f, p: int):
 def fcirc_any_matvec_c128(a, x, f=1.0):
     a = np.asarray(a, dtype=np.complex128)
     return toeplitz_matvec_c128(a, fcirc_col(list(a), complex(f)), x)
+
+
+def toeplitz_entry_modp(row, col, x, p: int, i: int) -> int:
+    """One output y_i = sum_j t_(j-i) x_j of the Toeplitz definition (t_k = row[k] for
+    k >= 0, col[-k] for k < 0), O(n), for sampled checks at large n."""
+    r = np.asarray(row).astype(np.int64) % p
+    c = np.asarray(col).astype(np.int64) % p
+    xv = np.asarray(x).astype(np.int64) % p
+    n = r.shape[0]
+    j = np.arange(n)
+    k = j - i
+    t = np.where(k >= 0, r[np.clip(k, 0, n - 1)], c[np.clip(-k, 0, n - 1)])
+    lo = int(((t * (xv & 0x7FFF)) % p).sum() % p)
+    hi = int(((t * (xv >> 15)) % p).sum() % p)
+    return (lo + hi * (1 << 15)) % p

@@ -159,3 +159,14 @@ def bigint_mul_ssa(u: int, v: int, P: int, N: int, K: int) -> int:
     r = [a[(-k) % N] for k in range(N)]
     c = levels_matvec(r, b, 0, K)
     return bigint_recompose(c, P)
+
+
+def matvec_entry(a, x, f, K: int, i: int) -> int:
+    """One output y_i of Definition 2 over Z/(2^K + 1), O(n) big-integer products."""
+    M = modulus(K)
+    n = len(a)
+    s = 0
+    for j in range(n):
+        e = a[j - i] if j >= i else f * a[n + j - i]
+        s += e * x[j]
+    return s % M

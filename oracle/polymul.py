@@ -123,3 +123,17 @@ def crt_textbook(residues, primes):
 def poly_via_circulant(a, b, primes):
     """Exact product: one circulant product per prime, then the CRT."""
     return crt_textbook([poly_residues(a, b, q) for q in primes], primes)
+
+
+def poly_coef(a, b, k: int) -> int:
+    """c_k = sum_i a_i b_(k-i) of the polynomial product, O(n) in int64; refuses inputs
+    whose partial sums could leave int64."""
+    av = np.asarray(a).astype(np.int64)
+    bv = np.asarray(b).astype(np.int64)
+    bound = int(np.abs(av).max(initial=0)) * int(np.abs(bv).max(initial=0)) * min(len(av), len(bv))
+    if bound >= 1 << 62:
+        raise ValueError("inputs too large for an int64 coefficient")
+    lo, hi = max(0, k - (len(bv) - 1)), min(k, len(av) - 1)
+    if lo > hi:
+        return 0
+    return int((av[lo:hi + 1] * bv[k - hi:k - lo + 1][::-1]).sum())

@@ -104,3 +104,34 @@ def test_bigint_full_config(F):
     got = F.bigint_mul(d(a), d(b)).cpu().numpy().view(np.uint16)
     F.check()
     np.testing.assert_array_equal(got, OB.bigint_mul_pyint(a, b))
+
+
+def test_polymul_max_size_sampled(F):
+    """na = nb = 2^22: 2^23 - 1 coefficients, the largest cyclic length of the first prime;
+    sampled coefficients from the O(n) definition."""
+    import torch
+    from oracle import polymul as OP
+    na = nb = 1 << 22
+    rng = np.random.default_rng(41)
+    a = rng.integers(-(1 << 15), 1 << 15, na, dtype=np.int32)
+    b = rng.integers(-(1 << 15), 1 << 15, nb, dtype=np.int32)
+    c = F.polymul_i64(torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda()).cpu().numpy()
+    F.check()
+    nc = na + nb - 1
+    for k in [0, 1, nc // 2, nc - 2, nc - 1] + [int(v) for v in rng.integers(0, nc, 5)]:
+        assert int(c[k]) == OP.poly_coef(a, b, k), k
+
+
+def test_bigint_max_size_both_routes(F):
+    """na + nb - 1 = 2^23 - 1 limbs with min(na, nb) = 2^20: the three-prime route at its
+    limit, and section 3.2's route on the same factors, against Python's product."""
+    import torch
+    na, nb = 1 << 20, (1 << 23) - (1 << 20)
+    rng = np.random.default_rng(42)
+    ua = rng.integers(0, 1 << 16, na, dtype=np.uint16)
+    vb = rng.integers(0, 1 << 16, nb, dtype=np.uint16)
+    want = int.from_bytes(ua.tobytes(), "little") * int.from_bytes(vb.tobytes(), "little")
+    ta, tb = torch.from_numpy(ua.view(np.int16)).cuda(), torch.from_numpy(vb.view(np.int16)).cuda()
+    for fn in (F.bigint_mul, F.bigint_mul_fermat):
+        got = fn(ta, tb).cpu().numpy().view(np.uint16)
+        assert int.from_bytes(got.tobytes(), "little") == want, fn.__name__

@@ -124,3 +124,22 @@ def test_embed_errors(F):
     big = torch.zeros((1 << 22) + 1, dtype=torch.int32, device="cuda")  # N = 2^24 > 2^23
     with pytest.raises(FcircError, match="ESIZE"):
         F.matvec_any(big, big, f=1, p=p)
+
+
+def test_largest_embedding_sampled(F):
+    """n = 2^22 - 1 over Z/998244353: the embedded cyclic length is 2^23, the prime's limit.
+    Sampled entries of the f-circulant (f = 3, no 2^22-th root needed) and Toeplitz
+    definitions; one more element (N = 2^24) is refused."""
+    from paper_2103_02605_amd._lib import FcircError
+    p = W.P1
+    n = (1 << 22) - 1
+    rng = np.random.default_rng(23)
+    a, x, col = (rng.integers(0, p, n, dtype=np.uint32) for _ in range(3))
+    y = host_u32(F.matvec_any(dev(a), dev(x), f=3, p=p))
+    t = host_u32(F.toeplitz_matvec(dev(a), dev(col), dev(x), p=p))
+    for i in (0, 1, n // 2, n - 1, 3141592):
+        assert y[i] == O.matvec_entry_modp(a, x, 3, p, i), i
+        assert t[i] == OE.toeplitz_entry_modp(a, col, x, p, i), i
+    big = dev(np.zeros((1 << 22) + 1, dtype=np.uint32))
+    with pytest.raises(FcircError, match="ESIZE"):
+        F.matvec_any(big, big.clone(), f=3, p=p)

@@ -154,3 +154,13 @@ def test_bigint_fermat_all_ones_and_c3_size(F):
     assert int_of(got) == int_of(ua) * int_of(vb)
     ntt = F.bigint_mul(torch.from_numpy(ua.view(np.int16)).cuda(), torch.from_numpy(vb.view(np.int16)).cuda())
     np.testing.assert_array_equal(ntt.cpu().numpy().view(np.uint16), got)
+
+
+def test_fermat_max_size_sampled(F):
+    """K = 16384 at its largest n = 2^15 (2^(L-1) | K): sampled entries of the definition."""
+    K, n = 16384, 1 << 15
+    rng = random.Random(99)
+    a, x = rand_elems(n, K, rng), rand_elems(n, K, rng)
+    y = run(F, a, x, K, 0)
+    for i in (0, n - 1, 12345):
+        assert y[i] == OF.matvec_entry(a, x, 1, K, i), i

@@ -81,3 +81,15 @@ def test_gfp2_errors(F):
     bad[0, 0] = P  # the ABI checks f, not the data; data must be canonical
     with pytest.raises(FcircError, match="EINVAL"):
         F.matvec(a, a, f=1, p=P, out=a)
+
+
+def test_gfp2_max_size_sampled(F):
+    """n = 2^26, the largest size the ring's tables serve: sampled entries from the O(n)
+    definition, f = 1 and f = -1."""
+    n = 1 << 26
+    a, x = rand(n, 61), rand(n, 62)
+    da, dx = dev(a), dev(x)
+    for fs, fe in FS.items():
+        got = F.matvec(da, dx, f=fs, p=P).cpu().numpy()
+        for i in (0, n - 1, 12345677):
+            assert tuple(int(c) for c in got[i]) == G.matvec_entry(a, x, fe, i), (fs, i)

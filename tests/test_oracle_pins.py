@@ -585,3 +585,26 @@ def test_p16_bigint_through_one_cyclic_product(P, N, K):
     top = (1 << (P * (N // 2))) - 1
     assert OF.bigint_mul_ssa(top, top, P, N, K) == top * top
     assert OF.bigint_mul_ssa(0, top, P, N, K) == 0
+
+
+def test_sampled_entry_helpers_match_full_definitions():
+    """The O(n) one-entry forms used for sampled checks at large n agree with the full
+    definitions on small inputs (Toeplitz, polynomial product, Z/(2^K + 1))."""
+    rng = np.random.default_rng(77)
+    p = 998244353
+    for n in (1, 2, 7, 33):
+        row, col, x = (rng.integers(0, p, n) for _ in range(3))
+        full = OE.toeplitz_matvec_dense(row.tolist(), col.tolist(), x.tolist(), p)
+        assert [OE.toeplitz_entry_modp(row, col, x, p, i) for i in range(n)] == [int(v) for v in full]
+    for na, nb in ((1, 1), (5, 3), (40, 17)):
+        a = rng.integers(-(1 << 15), 1 << 15, na)
+        b = rng.integers(-(1 << 15), 1 << 15, nb)
+        full = OP.poly_schoolbook(a.tolist(), b.tolist())
+        assert [OP.poly_coef(a, b, k) for k in range(na + nb - 1)] == [int(v) for v in full]
+    K, n = 64, 8
+    M = OF.modulus(K)
+    r = random.Random(78)
+    a = [r.randrange(M) for _ in range(n)]
+    x = [r.randrange(M) for _ in range(n)]
+    full = OF.dense_matvec(a, x, 5, K)
+    assert [OF.matvec_entry(a, x, 5, K, i) for i in range(n)] == full
