@@ -90,15 +90,18 @@ struct LeafSchedule {
   int d0[4], r[4], c[4];
 };
 
-LeafSchedule leaf_schedule(int L) {
+LeafSchedule leaf_schedule(int L, uint32_t count) {
   LeafSchedule S;
-  const int last = L < 12 ? L : 12;
+  // tiles of 2^12 elements, or of 2^10 when 2^12 would give fewer than 64 workgroups (the
+  // shared row: one instance)
+  const int tl = (L > 12 && ((uint64_t)count << (L - 12)) >= 64) ? 12 : 10;
+  const int last = L < tl ? L : tl;
   const int T = L - last;
   const int ntop = T == 0 ? 0 : (T + 9) / 10;
   int d0 = 0;
   for (int i = 0; i < ntop; ++i) {
     const int r = (T - d0) / (ntop - i);
-    int c = 12 - r;
+    int c = tl - r;
     if (c > L - d0 - r) c = L - d0 - r;
     S.d0[S.n] = d0;
     S.r[S.n] = r;
@@ -167,7 +170,7 @@ template <class Src>
 hipError_t transform(Ctx& c, const C32Tables* T, int L, uint32_t count, int arr, Src src, float2* out, hipStream_t s) {
   const uint64_t n = 1ull << L;
   const C32Params rp[3] = {{1.f}, {1.f}, {1.f}};
-  const LeafSchedule S = leaf_schedule(L);
+  const LeafSchedule S = leaf_schedule(L, count);
   PassArgs<C32> A = layer_args(T, L, count);
   A.arr0 = arr;
   A.final_store = 0;
@@ -192,7 +195,7 @@ template <class Dst>
 hipError_t merge_leaves(Ctx& c, const C32Tables* T, int L, uint32_t count, float2* leaves, Dst dst, hipStream_t s) {
   const uint64_t n = 1ull << L;
   const C32Params rp[3] = {{1.f}, {1.f}, {1.f}};
-  const LeafSchedule S = leaf_schedule(L);
+  const LeafSchedule S = leaf_schedule(L, count);
   PassArgs<C32> A = layer_args(T, L, count);
   const LdPlain<float2> lo{leaves, n};
   const StPlain<float2> so{leaves, n};
@@ -314,7 +317,7 @@ hipError_t lf_block(Ctx& c, const C32Tables* T, int L, int top, uint32_t count, 
                 : lf_block_b<b, false>(c, A, scale, src, ahat, dst, s);
   switch (L - top) {
     FCIRC_LF(1) FCIRC_LF(2) FCIRC_LF(3) FCIRC_LF(4) FCIRC_LF(5) FCIRC_LF(6) FCIRC_LF(7)
-    FCIRC_LF(8) FCIRC_LF(9) FCIRC_LF(10) FCIRC_LF(11) FCIRC_LF(12) FCIRC_LF(13)
+    FCIRC_LF(8) FCIRC_LF(9) FCIRC_LF(10) FCIRC_LF(11) FCIRC_LF(12) FCIRC_LF(13) FCIRC_LF(14)
     default: return hipErrorInvalidValue;
   }
 #undef FCIRC_LF
@@ -328,12 +331,21 @@ int lf_top(int L, uint32_t count) {
   return L - b;
 }
 
+// Top levels of the forward and grad_x products: none (one workgroup per instance runs
+// every level in LDS, 1024 threads for 2^14 complex elements) when the instance fits,
+// unless there are too few instances to fill the chip. Measured on MI355X for 2^11..2^14
+// and 32..512 instances: one pass is faster except at 2^14 with fewer than 64 instances.
+int lf_product_top(int L, uint32_t count) {
+  if (L <= 13 || (L == 14 && count >= 64)) return 0;
+  return lf_top(L, count);
+}
+
 // y_b = M(ahat (or its conjugate) * Fx(x_b)) for every instance: top split of the vectors,
 // one leaf-domain block launch, top merge.
 template <class Src, class Dst>
 hipError_t lf_product(Ctx& c, const C32Tables* T, int L, uint32_t count, bool conj, Src src, const float2* ahat,
                       float2* ws, Dst dst, hipStream_t s) {
-  const int top = lf_top(L, count);
+  const int top = lf_product_top(L, count);
   if (top == 0) return lf_block(c, T, L, 0, count, conj, src, ahat, dst, s);
   const uint64_t n = 1ull << L;
   hipError_t e = split_top(c, T, L, top, count, 1, src, ws, s);

@@ -43,7 +43,7 @@ def test_real_n64_against_dense_autograd_and_finite_differences(F):
     assert rel(tx.grad.cpu().numpy(), fx) <= TOL
 
 
-@pytest.mark.parametrize("n,batch", [(16, 1), (64, 3), (1024, 7), (1 << 13, 4), (1 << 14, 33), (1 << 16, 2), (1 << 21, 1)])
+@pytest.mark.parametrize("n,batch", [(16, 1), (64, 3), (1024, 7), (1 << 13, 4), (1 << 14, 33), (1 << 14, 64), (1 << 16, 2), (1 << 21, 1)])
 def test_complex_layer(F, n, batch):
     import torch
     rng = np.random.default_rng(n + batch)
