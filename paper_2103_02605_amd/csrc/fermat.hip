@@ -32,7 +32,9 @@ struct FE {
   uint32_t hi;  // uniform: 1 only for the value 2^K
 };
 
-__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+// The physical lane (workgroups are whole waves). Not a count of active lanes, so it stays
+// right inside branches.
+__device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & 63u; }
 
 __device__ __forceinline__ void wave_lds_sync() {
   asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
@@ -45,16 +47,18 @@ __device__ __forceinline__ void wave_lds_sync() {
 // carries of the 64-bit sum A + B + cin (bit l of (A + B + cin) ^ A ^ B).
 template <int Q>
 __device__ __forceinline__ uint32_t wadd(uint32_t (&r)[Q], const uint32_t (&a)[Q], const uint32_t (&b)[Q], uint32_t cin) {
-  uint32_t c = 0, ones = 1;
+  // (64-bit sums: the same chain written with 32-bit carry compares, which the compiler
+  // turns into add-with-carry instructions, gave wrong results for a constant operand)
+  uint32_t c = 0, all = 0xffffffffu;
 #pragma unroll
   for (int s = 0; s < Q; ++s) {
     const uint64_t t = (uint64_t)a[s] + b[s] + c;
     r[s] = (uint32_t)t;
     c = (uint32_t)(t >> 32);
-    ones &= r[s] == 0xffffffffu ? 1u : 0u;
+    all &= r[s];
   }
   const uint64_t G = __ballot(c != 0);
-  const uint64_t A = G | __ballot(ones != 0 && c == 0);
+  const uint64_t A = G | __ballot(all == 0xffffffffu && c == 0);
   const uint64_t S = A + G;
   const uint64_t S2 = S + (uint64_t)cin;
   const uint32_t cout = (S < A ? 1u : 0u) | (S2 < S ? 1u : 0u);
@@ -73,12 +77,18 @@ template <int Q>
 __device__ __forceinline__ uint32_t wadd_s96(uint32_t (&r)[Q], const uint32_t (&a)[Q], uint32_t t0, uint32_t t1,
                                              uint32_t t2) {
   const uint32_t ext = (int32_t)t2 < 0 ? 0xffffffffu : 0u;
-  const uint32_t base = lane_id() * Q;
   uint32_t b[Q];
+  if constexpr (Q >= 4) {  // words 0..2 all sit in lane 0
+    const bool l0 = lane_id() == 0;
 #pragma unroll
-  for (int s = 0; s < Q; ++s) {
-    const uint32_t j = base + s;
-    b[s] = j == 0 ? t0 : (j == 1 ? t1 : (j == 2 ? t2 : ext));
+    for (int s = 0; s < Q; ++s) b[s] = (l0 && s < 3) ? (s == 0 ? t0 : (s == 1 ? t1 : t2)) : ext;
+  } else {
+    const uint32_t base = lane_id() * Q;
+#pragma unroll
+    for (int s = 0; s < Q; ++s) {
+      const uint32_t j = base + s;
+      b[s] = j == 0 ? t0 : (j == 1 ? t1 : (j == 2 ? t2 : ext));
+    }
   }
   return wadd<Q>(r, a, b, 0);
 }
@@ -214,12 +224,12 @@ __device__ __forceinline__ FE<Q> fshl(const FE<Q>& x, uint32_t e) {
   return reduce_hi<Q>(r, (int32_t)c - 1);
 }
 
-__device__ __forceinline__ void add96(uint32_t& a0, uint32_t& a1, uint32_t& a2, uint64_t p) {
-  const uint64_t t0 = (uint64_t)a0 + (uint32_t)p;
-  a0 = (uint32_t)t0;
-  const uint64_t t1 = (uint64_t)a1 + (uint32_t)(p >> 32) + (t0 >> 32);
-  a1 = (uint32_t)t1;
-  a2 += (uint32_t)(t1 >> 32);
+// acc (96 bits: lo64, hi32) += a b. The product and the low 64 bits come from one 64-bit
+// multiply-add; it wrapped exactly when the new low part is below the old one.
+__device__ __forceinline__ void mac96(uint64_t& lo, uint32_t& hi, uint32_t a, uint32_t b) {
+  const uint64_t t = (uint64_t)a * b + lo;
+  hi += t < lo ? 1u : 0u;
+  lo = t;
 }
 
 // Sum of the three shifted word arrays X0 + X1 2^32 + X2 2^64 (each W words in LDS) as a
@@ -276,29 +286,31 @@ __device__ __forceinline__ FE<Q> fmul(const FE<Q>& a, const FE<Q>& b, uint32_t* 
     sb[W + l * Q + s] = b.w[s];
   }
   wave_lds_sync();
-  uint32_t p0[Q], p1[Q], p2[Q], n0[Q], n1[Q], n2[Q];
+  uint64_t pl[Q], nl[Q];  // low 64 bits of the positive and negative column sums
+  uint32_t ph[Q], nh[Q];  // their bits 64..95
 #pragma unroll
-  for (int m = 0; m < Q; ++m) p0[m] = p1[m] = p2[m] = n0[m] = n1[m] = n2[m] = 0;
+  for (int m = 0; m < Q; ++m) pl[m] = nl[m] = 0, ph[m] = nh[m] = 0;
   // i = 64 t + u; column c_m = l + 64 m receives a_i b_((c_m - i) mod W), positive when
   // i <= c_m: for t < m always, for t > m never, for t == m when u <= l.
+  constexpr int UNROLL_U = Q <= 4 ? 4 : 1;  // beyond Q = 4 the unrolled body only adds registers
 #pragma unroll
   for (int t = 0; t < Q; ++t) {
-#pragma unroll(Q <= 4 ? 4 : 1)
+#pragma unroll UNROLL_U
     for (uint32_t u = 0; u < 64u; ++u) {
       const uint32_t i = 64u * t + u;
       const uint32_t ai = sa[i];
       const uint32_t* sbi = sb + (l + W - i);  // column c_m reads sbi[64 m], index in [1, 2W)
 #pragma unroll
       for (int m = 0; m < Q; ++m) {
-        const uint64_t pr = (uint64_t)ai * sbi[64 * m];
+        const uint32_t bj = sbi[64 * m];
         if (m > t) {
-          add96(p0[m], p1[m], p2[m], pr);
+          mac96(pl[m], ph[m], ai, bj);
         } else if (m < t) {
-          add96(n0[m], n1[m], n2[m], pr);
+          mac96(nl[m], nh[m], ai, bj);
         } else {
-          const uint64_t pp = u <= l ? pr : 0ull;
-          add96(p0[m], p1[m], p2[m], pp);
-          add96(n0[m], n1[m], n2[m], pr - pp);
+          const uint32_t bp = u <= l ? bj : 0u;
+          mac96(pl[m], ph[m], ai, bp);
+          mac96(nl[m], nh[m], ai, bj - bp);
         }
       }
     }
@@ -308,12 +320,12 @@ __device__ __forceinline__ FE<Q> fmul(const FE<Q>& a, const FE<Q>& b, uint32_t* 
 #pragma unroll
   for (int m = 0; m < Q; ++m) {
     const uint32_t col = l + 64u * m;
-    c0[col] = p0[m];
-    c0[W + col] = p1[m];
-    c0[2 * W + col] = p2[m];
-    c0[3 * W + col] = n0[m];
-    c0[4 * W + col] = n1[m];
-    c0[5 * W + col] = n2[m];
+    c0[col] = (uint32_t)pl[m];
+    c0[W + col] = (uint32_t)(pl[m] >> 32);
+    c0[2 * W + col] = ph[m];
+    c0[3 * W + col] = (uint32_t)nl[m];
+    c0[4 * W + col] = (uint32_t)(nl[m] >> 32);
+    c0[5 * W + col] = nh[m];
   }
   wave_lds_sync();
   uint32_t rp[Q], rn[Q];
@@ -367,7 +379,7 @@ template <int Q>
 __global__ void __launch_bounds__(64 * FM_WAVES) k_fm_split(const uint32_t* a_in, const uint32_t* x_in, uint32_t* wa,
                                                             uint32_t* wx, uint32_t n, uint32_t d, uint32_t f_shift) {
   constexpr uint32_t W = 64u * Q, K = 32u * W, S = W + 1;
-  const uint32_t t = blockIdx.x * FM_WAVES + (threadIdx.x >> 6);
+  const uint32_t t = __builtin_amdgcn_readfirstlane(blockIdx.x * FM_WAVES + (threadIdx.x >> 6));  // one per wave
   if (t >= n / 2) return;
   const uint32_t h = n >> (d + 1), b = t / h, k = b * 2 * h + (t - b * h);
   const uint32_t e = root_shift(f_shift, K, d, b);
@@ -394,7 +406,7 @@ template <int Q>
 __global__ void __launch_bounds__(64 * FM_WAVES) k_fm_split2(const uint32_t* a_in, const uint32_t* x_in, uint32_t* wa,
                                                              uint32_t* wx, uint32_t n, uint32_t d, uint32_t f_shift) {
   constexpr uint32_t W = 64u * Q, K = 32u * W, S = W + 1;
-  const uint32_t t = blockIdx.x * FM_WAVES + (threadIdx.x >> 6);
+  const uint32_t t = __builtin_amdgcn_readfirstlane(blockIdx.x * FM_WAVES + (threadIdx.x >> 6));  // one per wave
   if (t >= n / 4) return;
   const uint32_t q4 = n >> (d + 2), b = t / q4, k = b * 4 * q4 + (t - b * q4);
   const uint32_t e0 = root_shift(f_shift, K, d, b);
@@ -438,7 +450,7 @@ __global__ void __launch_bounds__(64 * FM_WAVES) k_fm_leaf(const uint32_t* a, co
                                                            uint32_t L) {
   constexpr uint32_t W = 64u * Q, K = 32u * W, S = W + 1;
   __shared__ uint32_t sm[FM_WAVES * 8 * W];
-  const uint32_t wv = threadIdx.x >> 6;
+  const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const uint32_t k = blockIdx.x * FM_WAVES + wv;
   if (k >= n) return;
   const FE<Q> p = fmul<Q>(fload<Q>(a + (size_t)k * S), fload<Q>(x + (size_t)k * S), sm + wv * 8 * W);
@@ -450,7 +462,7 @@ __global__ void __launch_bounds__(64 * FM_WAVES) k_fm_leaf(const uint32_t* a, co
 template <int Q>
 __global__ void __launch_bounds__(64 * FM_WAVES) k_fm_merge(uint32_t* y, uint32_t n, uint32_t d, uint32_t f_shift) {
   constexpr uint32_t W = 64u * Q, K = 32u * W, S = W + 1;
-  const uint32_t t = blockIdx.x * FM_WAVES + (threadIdx.x >> 6);
+  const uint32_t t = __builtin_amdgcn_readfirstlane(blockIdx.x * FM_WAVES + (threadIdx.x >> 6));  // one per wave
   if (t >= n / 2) return;
   const uint32_t h = n >> (d + 1), b = t / h, k = b * 2 * h + (t - b * h);
   const uint32_t e = root_shift(f_shift, K, d, b);
@@ -465,7 +477,7 @@ __global__ void __launch_bounds__(64 * FM_WAVES) k_fm_merge(uint32_t* y, uint32_
 template <int Q>
 __global__ void __launch_bounds__(64 * FM_WAVES) k_fm_merge2(uint32_t* y, uint32_t n, uint32_t d, uint32_t f_shift) {
   constexpr uint32_t W = 64u * Q, K = 32u * W, S = W + 1;
-  const uint32_t t = blockIdx.x * FM_WAVES + (threadIdx.x >> 6);
+  const uint32_t t = __builtin_amdgcn_readfirstlane(blockIdx.x * FM_WAVES + (threadIdx.x >> 6));  // one per wave
   if (t >= n / 4) return;
   const uint32_t q4 = n >> (d + 2), b = t / q4, k = b * 4 * q4 + (t - b * q4);
   const uint32_t e0 = root_shift(f_shift, K, d, b);
