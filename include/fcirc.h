@@ -209,9 +209,10 @@ fcirc_status fcirc_check(fcirc_ctx *ctx, void *stream);
  * FCIRC_CHECK_INPUTS, FCIRC_DEBUG_SYNC=1 sets FCIRC_CHECK_SYNC.
  *   FCIRC_CHECK_INPUTS: the Z/p and GF(p^2) products (fcirc_matvec, fcirc_matvec_many,
  *     fcirc_matvec_any, fcirc_toeplitz_matvec, fcirc_matvec_batched) take canonical inputs,
- *     every word in [0,p), and give unspecified results otherwise. With this bit, a kernel
- *     first checks every input word of the call; the call then synchronises the stream and
- *     returns FCIRC_EINVAL, having written no output, when a word is out of range. Because
+ *     every word in [0,p), and fcirc_fermat_matvec canonical elements (top word 0 or 1, and
+ *     1 only with all other words 0); results are unspecified otherwise. With this bit, a
+ *     kernel first checks every input of the call; the call then synchronises the stream
+ *     and returns FCIRC_EINVAL, having written no output, when one is not canonical. Because
  *     it synchronises, it cannot be used while the stream is being captured into a graph.
  *   FCIRC_CHECK_SYNC: synchronise the stream after every kernel the library launches and
  *     return FCIRC_EDEVICE at the first failed one.

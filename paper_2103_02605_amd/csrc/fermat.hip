@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <initializer_list>
 
 #include "host.hpp"
 
@@ -500,6 +501,23 @@ __global__ void __launch_bounds__(64 * FM_WAVES) k_fm_merge2(uint32_t* y, uint32
   fstore<Q>(y + o1, fshl<Q>(sum, (2u * K - e0) % (2u * K)));
 }
 
+// Canonical form of n elements (the input check): the top word is 0 or 1, and 1 only
+// with every other word 0. One thread per element; the words are read only when the top
+// word is 1.
+__global__ void k_fm_check(const uint32_t* __restrict__ v, uint32_t n, uint32_t W, uint32_t* flag) {
+  const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const uint32_t* e = v + (size_t)k * (W + 1);
+  const uint32_t hi = e[W];
+  bool bad = hi > 1;
+  if (hi == 1) {
+    uint32_t acc = 0;
+    for (uint32_t w = 0; w < W; ++w) acc |= e[w];
+    bad = acc != 0;
+  }
+  if (bad) atomicOr(flag, 1u);
+}
+
 // Pieces of a large integer (16-bit limbs) as ring elements: element k holds piece j of
 // pw words (j = k, or j = (n - k) mod n for the reversed defining row), zero-extended.
 __global__ void k_fm_pack(const uint16_t* __restrict__ src, uint64_t nlimbs, uint32_t pw, uint32_t n, uint32_t W,
@@ -628,6 +646,22 @@ FmPlan fm_plan(uint64_t na, uint64_t nb) {
 
 fcirc_status fermat_matvec(Ctx& c, const uint32_t* a, const uint32_t* x, uint32_t* y, int L, int q, uint32_t f_shift,
                            hipStream_t s) {
+  const uint32_t n = 1u << L, W = 64u * q;
+  if (c.check_inputs) {  // canonical inputs, checked before anything is written
+    uint32_t* flag = c.d_status + 1;
+    hipError_t e = hipMemsetAsync(flag, 0, sizeof(uint32_t), s);
+    for (const uint32_t* v : {a, x}) {
+      if (e != hipSuccess) break;
+      e = launch(c, "fcirc_input_check", s, [&](hipEvent_t e0_, hipEvent_t e1_) {
+        FCIRC_LAUNCH(e0_, e1_, k_fm_check, dim3((n + 255) / 256), dim3(256), 0, s, v, n, W, flag);
+      });
+    }
+    uint32_t bad = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&bad, flag, sizeof bad, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_status(e);
+    if (bad) return FCIRC_EINVAL;
+  }
   const uint64_t elems = ((uint64_t)1 << L) * (64ull * q + 1);
   fcirc_status st = ws_reserve(c, 2 * elems * sizeof(uint32_t));
   if (st != FCIRC_OK) return st;

@@ -164,3 +164,29 @@ def test_fermat_max_size_sampled(F):
     y = run(F, a, x, K, 0)
     for i in (0, n - 1, 12345):
         assert y[i] == OF.matvec_entry(a, x, 1, K, i), i
+
+
+def test_fermat_input_check(F):
+    """With the input check on, a non-canonical element (top word 2, or top word 1 with a
+    nonzero word) is refused with EINVAL and nothing is written; canonical ones pass."""
+    import torch
+    from paper_2103_02605_amd._lib import FcircError
+    K, n = 4096, 16
+    rng = random.Random(5)
+    a, x = rand_elems(n, K, rng), rand_elems(n, K, rng)
+    good_a, good_x = to_words(a, K), to_words(x, K)
+    want = OF.levels_matvec(a, x, 0, K)
+    F.set_checks(F.CHECK_INPUTS)
+    try:
+        assert from_words(F.fermat_matvec(dev(good_a), dev(good_x), K, 0).cpu().numpy().view(np.uint32), K) == want
+        for bad_k, top, word in ((3, 2, None), (9, 1, 17)):
+            bad = good_x.copy()
+            bad[bad_k, K // 32] = top
+            if word is not None:
+                bad[bad_k, word] = 5
+            y = torch.full((n, K // 32 + 1), 7, dtype=torch.int32, device="cuda")
+            with pytest.raises(FcircError, match="EINVAL"):
+                F.fermat_matvec(dev(good_a), dev(bad), K, 0, out=y)
+            assert (y.cpu().numpy() == 7).all()
+    finally:
+        F.set_checks(0)
