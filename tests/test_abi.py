@@ -60,3 +60,32 @@ def test_create_without_gpu_reports_edevice(lib):
         pytest.skip("a GPU is present")
     h = C.c_void_p()
     assert lib.fcirc_create(C.byref(h), 0) == 6
+
+
+def test_header_is_plain_c_and_links():
+    """include/fcirc.h is a C header (no C++ or HIP types): a C99 translation unit that
+    includes it and takes the address of every declared entry point compiles, and links
+    against libfcirc.so (no GPU needed: nothing is called)."""
+    import shutil
+    import subprocess
+    import tempfile
+    from paper_2103_02605_amd import _lib
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no C compiler")
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_2103_02605_amd.build import build
+        build()
+    names = declared_functions()
+    src = "#include <stdio.h>\n#include \"fcirc.h\"\ntypedef void (*fn)(void);\nint main(void) {\n  fn p[] = {\n"
+    src += ",\n".join(f"    (fn)&{n}" for n in names)
+    src += "\n  };\n  printf(\"%d\\n\", (int)(sizeof p / sizeof p[0]));\n  return 0;\n}\n"
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "abi.c")
+        open(c, "w").write(src)
+        exe = os.path.join(d, "abi")
+        libdir = os.path.dirname(_lib.LIB_PATH)
+        r = subprocess.run([gcc, "-std=c99", "-Wall", "-Werror", "-pedantic", "-I", os.path.join(ROOT, "include"), c,
+                            "-o", exe, "-L", libdir, "-lfcirc", f"-Wl,-rpath,{libdir}", "-Wl,--unresolved-symbols=ignore-in-shared-libs"],
+                           capture_output=True, text=True)
+        assert r.returncode == 0, r.stderr
