@@ -257,6 +257,20 @@ int fcirc_get_split(fcirc_ctx *ctx, uint64_t n, fcirc_ring ring);
 fcirc_status fcirc_set_schedule(fcirc_ctx *ctx, fcirc_ring ring, uint64_t n, int top_levels, int tile_log, int flags);
 int fcirc_get_schedule(fcirc_ctx *ctx, fcirc_ring ring, uint64_t n, int *top_levels, int *tile_log, int *flags);
 
+/*
+ * Schedules chosen by fcirc_tune or fcirc_set_schedule kept in a text file, one line per
+ * (ring, n): "<arch> <compute units> <ring> <log2 n> <top_levels> <tile_log> <flags>".
+ * fcirc_save_schedules writes every schedule the context holds (replacing the file).
+ * fcirc_load_schedules reads such a file and takes the lines written for this device's
+ * architecture and compute-unit count (other lines are skipped). A file that cannot be
+ * read, or holds a malformed or out-of-range line, returns FCIRC_EINVAL and changes
+ * nothing: the context keeps its schedules and defaults. fcirc_create loads the file named
+ * by the environment variable FCIRC_TUNE_FILE, if set; when that fails it prints one
+ * warning to stderr and keeps the defaults.
+ */
+fcirc_status fcirc_save_schedules(fcirc_ctx *ctx, const char *path);
+fcirc_status fcirc_load_schedules(fcirc_ctx *ctx, const char *path);
+
 #ifdef __cplusplus
 }
 #endif

@@ -54,6 +54,8 @@ SIGNATURES = {
     "fcirc_check": (C.c_int, [C.c_void_p, C.c_void_p]),
     "fcirc_set_timing": (C.c_int, [C.c_void_p, C.c_int]),
     "fcirc_set_checks": (C.c_int, [C.c_void_p, C.c_int]),
+    "fcirc_save_schedules": (C.c_int, [C.c_void_p, C.c_char_p]),
+    "fcirc_load_schedules": (C.c_int, [C.c_void_p, C.c_char_p]),
     "fcirc_stage_times": (C.c_int, [C.c_void_p, C.POINTER(C.c_char_p), C.POINTER(C.c_uint64),
                                     C.POINTER(C.c_double), C.c_int]),
     "fcirc_tune": (C.c_int, [C.c_void_p, C.c_uint64, C.c_int, C.c_void_p]),

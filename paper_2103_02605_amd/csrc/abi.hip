@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <initializer_list>
@@ -167,6 +168,10 @@ fcirc_status fcirc_create(fcirc_ctx** out, int dev) {
       hipMemset(ctx->c.d_status, 0, 2 * sizeof(uint32_t)) != hipSuccess) {
     delete ctx;
     return FCIRC_EDEVICE;
+  }
+  if (const char* tf = std::getenv("FCIRC_TUNE_FILE")) {
+    if (load_schedules(ctx->c, tf) != FCIRC_OK)
+      std::fprintf(stderr, "libfcirc: FCIRC_TUNE_FILE=%s could not be read; default schedules kept\n", tf);
   }
   *out = ctx;
   return FCIRC_OK;

@@ -5,6 +5,9 @@
 // events on the caller's stream over scratch buffers; the fastest is kept in the context.
 #include <hip/hip_runtime.h>
 
+#include <cstdio>
+#include <cstring>
+#include <map>
 #include <vector>
 
 #include "host.hpp"
@@ -21,9 +24,78 @@ fcirc_status run_once(Ctx& c, fcirc_ring ring, int L, void* a, void* x, void* y,
   return c32_matvec(c, a, x, y, L, 1, 1.0, 0.0, ring == FCIRC_R32, s);
 }
 
+// The device's architecture name (up to the first ':' feature suffix) and CU count.
+void device_id(const Ctx& c, char* arch, size_t len, int* cus) {
+  std::snprintf(arch, len, "%s", c.prop.gcnArchName);
+  if (char* colon = std::strchr(arch, ':')) *colon = 0;
+  *cus = c.prop.multiProcessorCount;
+}
+
 }  // namespace
 
+namespace fcirc {
+
+fcirc_status load_schedules(Ctx& c, const char* path) {
+  std::FILE* f = std::fopen(path, "r");
+  if (!f) return FCIRC_EINVAL;
+  char arch[64];
+  int cus = 0;
+  device_id(c, arch, sizeof arch, &cus);
+  std::map<TuneKey, TuneVal> got;
+  char line[256];
+  bool ok = true;
+  while (ok && std::fgets(line, sizeof line, f)) {
+    if (line[0] == '\n' || line[0] == '#') continue;
+    char a[64];
+    int u, ring, L, top, tile, flags;
+    char tail;
+    if (std::sscanf(line, "%63s %d %d %d %d %d %d %c", a, &u, &ring, &L, &top, &tile, &flags, &tail) != 7) {
+      ok = false;
+      break;
+    }
+    const bool zp = ring >= FCIRC_ZP_998244353 && ring <= FCIRC_ZP_167772161;
+    if (ring < FCIRC_ZP_998244353 || ring > FCIRC_GFP2 || L < 0 || L > 26 || top < -1 || top > 26 || tile < -1 ||
+        tile > (zp ? 14 : 13) || flags < 0 || flags > 3) {
+      ok = false;
+      break;
+    }
+    if (std::strcmp(a, arch) != 0 || u != cus) continue;  // tuned on another device
+    TuneVal v;
+    v.top = top;
+    v.tile_log = tile;
+    v.flags = flags;
+    got[TuneKey{ring, L}] = v;
+  }
+  if (std::ferror(f)) ok = false;
+  std::fclose(f);
+  if (!ok) return FCIRC_EINVAL;
+  for (const auto& kv : got) c.tuned[kv.first] = kv.second;
+  return FCIRC_OK;
+}
+
+}  // namespace fcirc
+
 extern "C" {
+
+fcirc_status fcirc_save_schedules(fcirc_ctx* ctx, const char* path) {
+  if (!ctx || !path) return FCIRC_EINVAL;
+  std::FILE* f = std::fopen(path, "w");
+  if (!f) return FCIRC_EINVAL;
+  char arch[64];
+  int cus = 0;
+  device_id(ctx->c, arch, sizeof arch, &cus);
+  std::fprintf(f, "# arch cus ring log2n top_levels tile_log flags\n");
+  for (const auto& kv : ctx->c.tuned)
+    std::fprintf(f, "%s %d %d %d %d %d %d\n", arch, cus, kv.first.ring, kv.first.L, kv.second.top, kv.second.tile_log,
+                 kv.second.flags);
+  const bool bad = std::ferror(f) != 0;
+  return (std::fclose(f) != 0 || bad) ? FCIRC_EINVAL : FCIRC_OK;
+}
+
+fcirc_status fcirc_load_schedules(fcirc_ctx* ctx, const char* path) {
+  if (!ctx || !path) return FCIRC_EINVAL;
+  return load_schedules(ctx->c, path);
+}
 
 fcirc_status fcirc_set_schedule(fcirc_ctx* ctx, fcirc_ring ring, uint64_t n, int top_levels, int tile_log, int flags) {
   if (!ctx || n == 0 || (n & (n - 1)) || ring < FCIRC_ZP_998244353 || ring > FCIRC_GFP2) return FCIRC_EINVAL;

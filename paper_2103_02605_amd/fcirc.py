@@ -269,6 +269,16 @@ def set_schedule(n: int, ring: int, top_levels: int = -1, tile_log: int = -1, fl
     L.check(L.lib().fcirc_set_schedule(context(device).handle, ring, n, top_levels, tile_log, flags), "fcirc_set_schedule")
 
 
+def save_schedules(path: str, device=None):
+    """Write the device context's tuned/set schedules to a text file."""
+    L.check(L.lib().fcirc_save_schedules(context(device).handle, str(path).encode()), "fcirc_save_schedules")
+
+
+def load_schedules(path: str, device=None):
+    """Take the schedules a file holds for this device (EINVAL and no change if malformed)."""
+    L.check(L.lib().fcirc_load_schedules(context(device).handle, str(path).encode()), "fcirc_load_schedules")
+
+
 def get_schedule(n: int, ring: int, device=None) -> dict:
     top, tile, flags = C.c_int(), C.c_int(), C.c_int()
     ntop = L.lib().fcirc_get_schedule(context(device).handle, ring, n, C.byref(top), C.byref(tile), C.byref(flags))
