@@ -13,6 +13,12 @@
 
 using namespace fcirc;
 
+namespace fcirc {
+// Schedules from a file written by fcirc_save_schedules (tune.hip; FCIRC_EINVAL, nothing
+// changed, if the file is unreadable or malformed).
+fcirc_status load_schedules(Ctx& c, const char* path);
+}  // namespace fcirc
+
 
 namespace {
 

@@ -528,9 +528,6 @@ fcirc_status embed_product(Ctx& c, fcirc_ring ring, const void* r, const void* c
 fcirc_status polymul_i64(Ctx& c, const int32_t* a, uint64_t na, const int32_t* b, uint64_t nb, int64_t* out, hipStream_t s);
 fcirc_status bigint_mul(Ctx& c, const uint16_t* a, uint64_t na, const uint16_t* b, uint64_t nb, uint16_t* out, hipStream_t s);
 void release_graphs(Ctx& c);
-// Schedules from a file written by fcirc_save_schedules (FCIRC_EINVAL, nothing changed, if
-// the file is unreadable or malformed).
-fcirc_status load_schedules(Ctx& c, const char* path);
 // Limbs of sum_k coef[k] 2^(16 k) (coef[k] < 2^64, k < nc) into out[0, nl); u holds nl and
 // summ 2 carry_blocks(nl) words of scratch.
 uint64_t carry_blocks(uint64_t nl);
