@@ -43,7 +43,10 @@ def test_real_n64_against_dense_autograd_and_finite_differences(F):
     assert rel(tx.grad.cpu().numpy(), fx) <= TOL
 
 
-@pytest.mark.parametrize("n,batch", [(16, 1), (64, 3), (1024, 7), (1 << 13, 4), (1 << 14, 33), (1 << 14, 64), (1 << 16, 2), (1 << 21, 1)])
+@pytest.mark.parametrize("n,batch", [(16, 1), (64, 3), (1024, 7), (1 << 13, 4), (1 << 14, 33), (1 << 14, 64), (1 << 16, 2), (1 << 21, 1),
+                                     # grad_a by 13-level accumulating blocks: no top split at 2^13
+                                     # (512 instances), one top level at 2^14 (256 instances)
+                                     (1 << 13, 512), (1 << 14, 256)])
 def test_complex_layer(F, n, batch):
     import torch
     rng = np.random.default_rng(n + batch)
@@ -74,6 +77,21 @@ def test_real_odd_batches(F, batch):
     ga, gx = F.layer_backward(torch.from_numpy(a).cuda(), torch.from_numpy(x).cuda(), torch.from_numpy(g).cuda())
     y_ref, ga_ref, gx_ref = OG.grads_fft(a.astype(np.float64), x.astype(np.float64), g.astype(np.float64))
     assert rel(y, y_ref) <= TOL
+    assert rel(ga.cpu().numpy(), ga_ref) <= TOL
+    assert rel(gx.cpu().numpy(), gx_ref) <= TOL
+
+
+def test_real_13_level_accumulation(F):
+    """Real batch of 1024 at n = 2^13: 512 packed pairs, so grad_a's accumulating blocks take
+    all 13 levels straight from the real rows (no top split)."""
+    import torch
+    rng = np.random.default_rng(13)
+    n, batch = 1 << 13, 1024
+    a = rng.standard_normal(n).astype(np.float32)
+    x = rng.standard_normal((batch, n)).astype(np.float32)
+    g = rng.standard_normal((batch, n)).astype(np.float32)
+    ga, gx = F.layer_backward(torch.from_numpy(a).cuda(), torch.from_numpy(x).cuda(), torch.from_numpy(g).cuda())
+    _, ga_ref, gx_ref = OG.grads_fft(a.astype(np.float64), x.astype(np.float64), g.astype(np.float64))
     assert rel(ga.cpu().numpy(), ga_ref) <= TOL
     assert rel(gx.cpu().numpy(), gx_ref) <= TOL
 
