@@ -57,18 +57,6 @@ struct LdConj {
   }
 };
 
-// Y[j][i] = leaf(A[i] or conj(A[i]), X[j][i]) for every instance j.
-__global__ void k_leaf_mul(const float2* __restrict__ A, float2* __restrict__ X, uint32_t n, uint32_t count, int conj_a,
-                           float scale) {
-  const uint64_t total = (uint64_t)n * count;
-  for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < total; k += (uint64_t)gridDim.x * blockDim.x) {
-    float2 a = A[k % n];
-    if (conj_a) a.y = -a.y;
-    const float2 x = X[k];
-    X[k] = make_float2((a.x * x.x - a.y * x.y) * scale, (a.x * x.y + a.y * x.x) * scale);
-  }
-}
-
 // S[i] = sum_j leaf(G[j][i], X[j][i]) (fixed summation order: deterministic).
 __global__ void k_leaf_sum(const float2* __restrict__ G, const float2* __restrict__ X, float2* __restrict__ S, uint32_t n,
                            uint32_t count, float scale) {
@@ -118,36 +106,32 @@ LeafSchedule leaf_schedule(int L, uint32_t count) {
   return S;
 }
 
-#define FCIRC_R12_SWITCH(R_, CALL)        \
-  switch (R_) {                           \
-    case 1: return CALL(1);               \
-    case 2: return CALL(2);               \
-    case 3: return CALL(3);               \
-    case 4: return CALL(4);               \
-    case 5: return CALL(5);               \
-    case 6: return CALL(6);               \
-    case 7: return CALL(7);               \
-    case 8: return CALL(8);               \
-    case 9: return CALL(9);               \
-    case 10: return CALL(10);             \
-    case 11: return CALL(11);             \
-    case 12: return CALL(12);             \
-    default: return hipErrorInvalidValue; \
+// Calls f(std::integral_constant<int, r>) for a pass of r levels, LO <= r <= HI (a kernel is
+// compiled per level count; each call site names the counts its schedule can produce).
+template <int LO, int HI, class F>
+hipError_t with_levels(int r, F&& f) {
+  if constexpr (LO > HI) {
+    return hipErrorInvalidValue;
+  } else {
+    if (r == LO) return f(std::integral_constant<int, LO>{});
+    return with_levels<LO + 1, HI>(r, f);
   }
+}
 
-template <class Src, class Dst>
+// Top passes take at most 10 levels; the last pass of a leaf schedule (logc = 0) up to 12.
+template <int HI, class Src, class Dst>
 hipError_t split_pass_any(Ctx& c, const PassArgs<C32>& A, const C32Params* rp, Src src, Dst dst, uint32_t grid, uint32_t nt,
                           size_t lds, hipStream_t s) {
-#define FCIRC_CALL(r) launch_split_r<C32, r>(c, A, rp, src, src, dst, dst, grid, nt, lds, s)
-  FCIRC_R12_SWITCH(A.logr, FCIRC_CALL)
-#undef FCIRC_CALL
+  return with_levels<1, HI>(A.logr, [&](auto r) {
+    return launch_split_r<C32, decltype(r)::value>(c, A, rp, src, src, dst, dst, grid, nt, lds, s);
+  });
 }
-template <class Src, class Dst>
+template <int HI, class Src, class Dst>
 hipError_t merge_pass_any(Ctx& c, const PassArgs<C32>& A, const C32Params* rp, Src src, Dst dst, uint32_t grid, uint32_t nt,
                           size_t lds, hipStream_t s) {
-#define FCIRC_CALL(r) launch_merge_r<C32, r>(c, A, rp, src, dst, grid, nt, lds, s)
-  FCIRC_R12_SWITCH(A.logr, FCIRC_CALL)
-#undef FCIRC_CALL
+  return with_levels<1, HI>(A.logr, [&](auto r) {
+    return launch_merge_r<C32, decltype(r)::value>(c, A, rp, src, dst, grid, nt, lds, s);
+  });
 }
 
 PassArgs<C32> layer_args(const C32Tables* T, int L, uint32_t count) {
@@ -183,8 +167,8 @@ hipError_t transform(Ctx& c, const C32Tables* T, int L, uint32_t count, int arr,
     A.tiles = (uint32_t)(n >> (A.logr + A.logc));
     const size_t tile = (size_t)1 << (A.logr + A.logc);
     const uint32_t grid = A.tiles * count, nt = (uint32_t)(tile >> EPT_LOG);
-    const hipError_t e = i == 0 ? split_pass_any(c, A, rp, src, so, grid, nt, tile * sizeof(float2), s)
-                                : split_pass_any(c, A, rp, lo, so, grid, nt, tile * sizeof(float2), s);
+    const hipError_t e = i == 0 ? split_pass_any<10>(c, A, rp, src, so, grid, nt, tile * sizeof(float2), s)
+                                : split_pass_any<12>(c, A, rp, lo, so, grid, nt, tile * sizeof(float2), s);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -207,8 +191,8 @@ hipError_t merge_leaves(Ctx& c, const C32Tables* T, int L, uint32_t count, float
     A.final_store = i == 0;
     const size_t tile = (size_t)1 << (A.logr + A.logc);
     const uint32_t grid = A.tiles * count, nt = (uint32_t)(tile >> EPT_LOG);
-    const hipError_t e = i == 0 ? merge_pass_any(c, A, rp, lo, dst, grid, nt, tile * sizeof(float2), s)
-                                : merge_pass_any(c, A, rp, lo, so, grid, nt, tile * sizeof(float2), s);
+    const hipError_t e = i == 0 ? merge_pass_any<10>(c, A, rp, lo, dst, grid, nt, tile * sizeof(float2), s)
+                                : merge_pass_any<12>(c, A, rp, lo, so, grid, nt, tile * sizeof(float2), s);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -246,8 +230,8 @@ hipError_t split_top(Ctx& c, const C32Tables* T, int L, int top, uint32_t count,
     A.tiles = (uint32_t)(n >> (A.logr + A.logc));
     const size_t tile = (size_t)1 << (A.logr + A.logc);
     const uint32_t grid = A.tiles * count, nt = (uint32_t)(tile >> EPT_LOG);
-    const hipError_t e = i == 0 ? split_pass_any(c, A, rp, src, so, grid, nt, tile * sizeof(float2), s)
-                                : split_pass_any(c, A, rp, lo, so, grid, nt, tile * sizeof(float2), s);
+    const hipError_t e = i == 0 ? split_pass_any<10>(c, A, rp, src, so, grid, nt, tile * sizeof(float2), s)
+                                : split_pass_any<10>(c, A, rp, lo, so, grid, nt, tile * sizeof(float2), s);
     if (e != hipSuccess) return e;
     d0 += r;
   }
@@ -278,8 +262,8 @@ hipError_t merge_top(Ctx& c, const C32Tables* T, int L, int top, uint32_t count,
     A.final_store = i == 0;
     const size_t tile = (size_t)1 << (A.logr + A.logc);
     const uint32_t grid = A.tiles * count, nt = (uint32_t)(tile >> EPT_LOG);
-    const hipError_t e = i == 0 ? merge_pass_any(c, A, rp, lo, dst, grid, nt, tile * sizeof(float2), s)
-                                : merge_pass_any(c, A, rp, lo, so, grid, nt, tile * sizeof(float2), s);
+    const hipError_t e = i == 0 ? merge_pass_any<10>(c, A, rp, lo, dst, grid, nt, tile * sizeof(float2), s)
+                                : merge_pass_any<10>(c, A, rp, lo, so, grid, nt, tile * sizeof(float2), s);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -315,8 +299,8 @@ hipError_t lf_block(Ctx& c, const C32Tables* T, int L, int top, uint32_t count, 
   case b:                                                                                     \
     return conj ? lf_block_b<b, true>(c, A, scale, src, ahat, dst, s)                         \
                 : lf_block_b<b, false>(c, A, scale, src, ahat, dst, s);
-  switch (L - top) {
-    FCIRC_LF(1) FCIRC_LF(2) FCIRC_LF(3) FCIRC_LF(4) FCIRC_LF(5) FCIRC_LF(6) FCIRC_LF(7)
+  switch (L - top) {  // the layer takes n >= 16; with top levels, at least 10 remain
+    FCIRC_LF(4) FCIRC_LF(5) FCIRC_LF(6) FCIRC_LF(7)
     FCIRC_LF(8) FCIRC_LF(9) FCIRC_LF(10) FCIRC_LF(11) FCIRC_LF(12) FCIRC_LF(13) FCIRC_LF(14)
     default: return hipErrorInvalidValue;
   }
@@ -353,12 +337,6 @@ hipError_t lf_product(Ctx& c, const C32Tables* T, int L, uint32_t count, bool co
     e = lf_block(c, T, L, top, count, conj, LdPlain<float2>{ws, n}, ahat, StPlain<float2>{ws, n}, s);
   if (e == hipSuccess) e = merge_top(c, T, L, top, count, ws, dst, s);
   return e;
-}
-
-hipError_t leaf_mul(Ctx& c, const float2* A, float2* X, uint32_t n, uint32_t count, bool conj_a, float scale, hipStream_t s) {
-  const uint64_t total = (uint64_t)n * count;
-  const uint32_t grid = (uint32_t)std::min<uint64_t>((total + 255) / 256, 8192);
-  return launch(c, "fcirc_leaf_mul", s, [&](hipEvent_t e0_, hipEvent_t e1_) { FCIRC_LAUNCH(e0_, e1_, k_leaf_mul, dim3(grid), dim3(256), 0, s, A, X, n, count, conj_a ? 1 : 0, scale); });
 }
 
 struct LayerWs {
@@ -436,15 +414,15 @@ hipError_t split_top_ax(Ctx& c, const C32Tables* T, int L, int top, uint32_t cou
     const size_t tile = (size_t)1 << (A.logr + A.logc);
     const uint32_t grid = A.tiles * count, nt = (uint32_t)(tile >> EPT_LOG);
     hipError_t e;
-#define FCIRC_CALL(rr) launch_split_ax_r<C32, rr>(c, A, rp, srca, srcx, sa, sx, grid, nt, 2 * tile * sizeof(float2), s)
-#define FCIRC_CALL2(rr) launch_split_ax_r<C32, rr>(c, A, rp, la, lx, sa, sx, grid, nt, 2 * tile * sizeof(float2), s)
     if (i == 0) {
-      e = [&]() -> hipError_t { FCIRC_R12_SWITCH(r, FCIRC_CALL) }();
+      e = with_levels<1, 10>(r, [&](auto rr) {
+        return launch_split_ax_r<C32, decltype(rr)::value>(c, A, rp, srca, srcx, sa, sx, grid, nt, 2 * tile * sizeof(float2), s);
+      });
     } else {
-      e = [&]() -> hipError_t { FCIRC_R12_SWITCH(r, FCIRC_CALL2) }();
+      e = with_levels<1, 10>(r, [&](auto rr) {
+        return launch_split_ax_r<C32, decltype(rr)::value>(c, A, rp, la, lx, sa, sx, grid, nt, 2 * tile * sizeof(float2), s);
+      });
     }
-#undef FCIRC_CALL
-#undef FCIRC_CALL2
     if (e != hipSuccess) return e;
     d0 += r;
   }
