@@ -67,11 +67,11 @@ class BatchPlan:
 
     def run(self, stream=None):
         ctx = context(self.a.device)
-        s = torch.cuda.current_stream(self.a.device) if stream is None else stream
-        L.check(L.lib().fcirc_matvec_batched(ctx.handle, C.c_void_p(self.a.data_ptr()), C.c_void_p(self.x.data_ptr()),
-                                             C.c_void_p(self.y.data_ptr()), self.items, len(self.sizes),
-                                             C.byref(self.f), self.ring, C.c_void_p(s.cuda_stream)),
-                "fcirc_matvec_batched")
+        with ctx.enqueue(self.a.device, stream) as s:
+            L.check(L.lib().fcirc_matvec_batched(ctx.handle, C.c_void_p(self.a.data_ptr()), C.c_void_p(self.x.data_ptr()),
+                                                 C.c_void_p(self.y.data_ptr()), self.items, len(self.sizes),
+                                                 C.byref(self.f), self.ring, s),
+                    "fcirc_matvec_batched")
         return self.y
 
     def outputs(self):

@@ -12,7 +12,9 @@ Conventions (Rosowski, arXiv 2103.02605):
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes as C
+import threading
 
 import torch
 
@@ -24,13 +26,33 @@ P_GF = (1 << 31) - 1  # GF(p^2) = Z/p[sqrt 3] of section 3.1: tensors (..., 2) i
 
 
 class Context:
-    """A libfcirc context on one HIP device (plans, workspaces, graphs)."""
+    """A libfcirc context on one HIP device (plans, workspaces, graphs).
+
+    The library requires calls that share a context to be serialised, and their device
+    work to be ordered (they share the context's workspace). enqueue() does both for the
+    calls of this module: it holds a lock for the call, and makes the current stream wait
+    for the stream of the context's previous call when the two differ."""
 
     def __init__(self, device: int = 0):
         self.device = device
+        self.lock = threading.RLock()
+        self._last_stream = None
         h = C.c_void_p()
         L.check(L.lib().fcirc_create(C.byref(h), device), "fcirc_create")
         self.handle = h
+
+    @contextlib.contextmanager
+    def enqueue(self, device=None, stream: torch.cuda.Stream | None = None):
+        """Hold the context for one call on `stream` (default: the current stream of
+        `device`); yields that stream as the library's stream argument."""
+        with self.lock:
+            s = stream if stream is not None else torch.cuda.current_stream(self.device if device is None else device)
+            if self._last_stream is not None and self._last_stream != s:
+                s.wait_stream(self._last_stream)
+            try:
+                yield C.c_void_p(s.cuda_stream)
+            finally:
+                self._last_stream = s
 
     def close(self):
         if self.handle:
@@ -45,21 +67,19 @@ class Context:
 
 
 _contexts: dict[int, Context] = {}
+_contexts_lock = threading.Lock()
 
 
 def context(device=None) -> Context:
     idx = torch.cuda.current_device() if device is None else torch.device(device).index or 0
-    if idx not in _contexts:
-        _contexts[idx] = Context(idx)
-    return _contexts[idx]
+    with _contexts_lock:
+        if idx not in _contexts:
+            _contexts[idx] = Context(idx)
+        return _contexts[idx]
 
 
 def _ptr(t: torch.Tensor) -> C.c_void_p:
     return C.c_void_p(t.data_ptr())
-
-
-def _stream(t: torch.Tensor) -> C.c_void_p:
-    return C.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
 
 
 def _need(t: torch.Tensor, name: str):
@@ -106,8 +126,9 @@ def matvec(a: torch.Tensor, x: torch.Tensor, f=None, p: int | None = None, out: 
     y = torch.empty_like(a) if out is None else out
     _need(y, "out")
     ctx = context(a.device)
-    L.check(L.lib().fcirc_matvec(ctx.handle, _ptr(a), _ptr(x), _ptr(y), a.shape[0], C.byref(fv), ring, _stream(a)),
-            "fcirc_matvec")
+    with ctx.enqueue(a.device) as s:
+        L.check(L.lib().fcirc_matvec(ctx.handle, _ptr(a), _ptr(x), _ptr(y), a.shape[0], C.byref(fv), ring, s),
+                "fcirc_matvec")
     return y
 
 
@@ -122,8 +143,9 @@ def matvec_any(a: torch.Tensor, x: torch.Tensor, f=None, p: int | None = None, o
     y = torch.empty_like(a) if out is None else out
     _need(y, "out")
     ctx = context(a.device)
-    L.check(L.lib().fcirc_matvec_any(ctx.handle, _ptr(a), _ptr(x), _ptr(y), a.numel(), C.byref(fv), ring, _stream(a)),
-            "fcirc_matvec_any")
+    with ctx.enqueue(a.device) as s:
+        L.check(L.lib().fcirc_matvec_any(ctx.handle, _ptr(a), _ptr(x), _ptr(y), a.numel(), C.byref(fv), ring, s),
+                "fcirc_matvec_any")
     return y
 
 
@@ -138,8 +160,9 @@ def toeplitz_matvec(row: torch.Tensor, col: torch.Tensor, x: torch.Tensor, p: in
     y = torch.empty_like(row) if out is None else out
     _need(y, "out")
     ctx = context(row.device)
-    L.check(L.lib().fcirc_toeplitz_matvec(ctx.handle, _ptr(row), _ptr(col), _ptr(x), _ptr(y), row.numel(), ring,
-                                          _stream(row)), "fcirc_toeplitz_matvec")
+    with ctx.enqueue(row.device) as s:
+        L.check(L.lib().fcirc_toeplitz_matvec(ctx.handle, _ptr(row), _ptr(col), _ptr(x), _ptr(y), row.numel(), ring,
+                                              s), "fcirc_toeplitz_matvec")
     return y
 
 
@@ -154,8 +177,9 @@ def matvec_many(a: torch.Tensor, x: torch.Tensor, f=None, p: int | None = None, 
         raise ValueError("a and x must be tensors (count, n) of the same shape and dtype")
     y = torch.empty_like(a) if out is None else out
     ctx = context(a.device)
-    L.check(L.lib().fcirc_matvec_many(ctx.handle, _ptr(a), _ptr(x), _ptr(y), a.shape[1], a.shape[0], C.byref(fv),
-                                      ring, _stream(a)), "fcirc_matvec_many")
+    with ctx.enqueue(a.device) as s:
+        L.check(L.lib().fcirc_matvec_many(ctx.handle, _ptr(a), _ptr(x), _ptr(y), a.shape[1], a.shape[0], C.byref(fv),
+                                          ring, s), "fcirc_matvec_many")
     return y
 
 
@@ -167,8 +191,9 @@ def polymul_i64(a: torch.Tensor, b: torch.Tensor, out: torch.Tensor | None = Non
         raise TypeError("polymul_i64 takes int32 coefficient tensors")
     c = torch.empty(a.numel() + b.numel() - 1, dtype=torch.int64, device=a.device) if out is None else out
     ctx = context(a.device)
-    L.check(L.lib().fcirc_polymul_i64(ctx.handle, _ptr(a), a.numel(), _ptr(b), b.numel(), _ptr(c), _stream(a)),
-            "fcirc_polymul_i64")
+    with ctx.enqueue(a.device) as s:
+        L.check(L.lib().fcirc_polymul_i64(ctx.handle, _ptr(a), a.numel(), _ptr(b), b.numel(), _ptr(c), s),
+                "fcirc_polymul_i64")
     return c
 
 
@@ -180,8 +205,9 @@ def bigint_mul(a: torch.Tensor, b: torch.Tensor, out: torch.Tensor | None = None
         raise TypeError("bigint_mul takes uint16 (or int16-viewed) limb tensors")
     c = torch.empty(a.numel() + b.numel(), dtype=a.dtype, device=a.device) if out is None else out
     ctx = context(a.device)
-    L.check(L.lib().fcirc_bigint_mul(ctx.handle, _ptr(a), a.numel(), _ptr(b), b.numel(), _ptr(c), _stream(a)),
-            "fcirc_bigint_mul")
+    with ctx.enqueue(a.device) as s:
+        L.check(L.lib().fcirc_bigint_mul(ctx.handle, _ptr(a), a.numel(), _ptr(b), b.numel(), _ptr(c), s),
+                "fcirc_bigint_mul")
     return c
 
 
@@ -199,8 +225,9 @@ def fermat_matvec(a: torch.Tensor, x: torch.Tensor, K: int, f_shift: int = 0, ou
     y = torch.empty_like(a) if out is None else out
     _need(y, "out")
     ctx = context(a.device)
-    L.check(L.lib().fcirc_fermat_matvec(ctx.handle, _ptr(a), _ptr(x), _ptr(y), a.shape[0], int(K), int(f_shift),
-                                        _stream(a)), "fcirc_fermat_matvec")
+    with ctx.enqueue(a.device) as s:
+        L.check(L.lib().fcirc_fermat_matvec(ctx.handle, _ptr(a), _ptr(x), _ptr(y), a.shape[0], int(K), int(f_shift),
+                                            s), "fcirc_fermat_matvec")
     return y
 
 
@@ -212,15 +239,17 @@ def bigint_mul_fermat(a: torch.Tensor, b: torch.Tensor, out: torch.Tensor | None
         raise TypeError("bigint_mul_fermat takes uint16 (or int16-viewed) limb tensors")
     c = torch.empty(a.numel() + b.numel(), dtype=a.dtype, device=a.device) if out is None else out
     ctx = context(a.device)
-    L.check(L.lib().fcirc_bigint_mul_fermat(ctx.handle, _ptr(a), a.numel(), _ptr(b), b.numel(), _ptr(c), _stream(a)),
-            "fcirc_bigint_mul_fermat")
+    with ctx.enqueue(a.device) as s:
+        L.check(L.lib().fcirc_bigint_mul_fermat(ctx.handle, _ptr(a), a.numel(), _ptr(b), b.numel(), _ptr(c), s),
+                "fcirc_bigint_mul_fermat")
     return c
 
 
 def check(device=None):
     """Synchronise the current stream and raise on a sticky device-side error (ERANGE)."""
     ctx = context(device)
-    L.check(L.lib().fcirc_check(ctx.handle, C.c_void_p(torch.cuda.current_stream().cuda_stream)), "fcirc_check")
+    with ctx.enqueue(device) as s:
+        L.check(L.lib().fcirc_check(ctx.handle, s), "fcirc_check")
 
 
 CHECK_INPUTS = 1  # Z/p and GF(p^2) inputs must be canonical; EINVAL otherwise (synchronises)
@@ -229,35 +258,45 @@ CHECK_SYNC = 2    # synchronise after every kernel
 
 def set_checks(flags: int, device=None):
     """Debugging checks of the device's context (defaults: FCIRC_VALIDATE, FCIRC_DEBUG_SYNC)."""
-    L.check(L.lib().fcirc_set_checks(context(device).handle, int(flags)), "fcirc_set_checks")
+    ctx = context(device)
+    with ctx.lock:
+        L.check(L.lib().fcirc_set_checks(ctx.handle, int(flags)), "fcirc_set_checks")
 
 
 def set_timing(enable: bool, device=None):
-    L.check(L.lib().fcirc_set_timing(context(device).handle, int(bool(enable))), "fcirc_set_timing")
+    ctx = context(device)
+    with ctx.lock:
+        L.check(L.lib().fcirc_set_timing(ctx.handle, int(bool(enable))), "fcirc_set_timing")
 
 
 def stage_times(device=None) -> dict:
     """{kernel name: (launches, total ms)} since the last set_timing()."""
     ctx = context(device)
-    n = L.lib().fcirc_stage_times(ctx.handle, None, None, None, 0)
-    names = (C.c_char_p * max(n, 1))()
-    launches = (C.c_uint64 * max(n, 1))()
-    ms = (C.c_double * max(n, 1))()
-    n = L.lib().fcirc_stage_times(ctx.handle, names, launches, ms, n)
+    with ctx.lock:
+        n = L.lib().fcirc_stage_times(ctx.handle, None, None, None, 0)
+        names = (C.c_char_p * max(n, 1))()
+        launches = (C.c_uint64 * max(n, 1))()
+        ms = (C.c_double * max(n, 1))()
+        n = L.lib().fcirc_stage_times(ctx.handle, names, launches, ms, n)
     return {names[i].decode(): (int(launches[i]), float(ms[i])) for i in range(n)}
 
 
 def set_split(top_levels: int, device=None):
-    L.check(L.lib().fcirc_set_split(context(device).handle, int(top_levels)), "fcirc_set_split")
+    ctx = context(device)
+    with ctx.lock:
+        L.check(L.lib().fcirc_set_split(ctx.handle, int(top_levels)), "fcirc_set_split")
 
 
 def get_split(n: int, ring: int, device=None) -> int:
-    return int(L.lib().fcirc_get_split(context(device).handle, n, ring))
+    ctx = context(device)
+    with ctx.lock:
+        return int(L.lib().fcirc_get_split(ctx.handle, n, ring))
 
 
 def tune(n: int, ring: int, device=None):
-    L.check(L.lib().fcirc_tune(context(device).handle, n, ring, C.c_void_p(torch.cuda.current_stream().cuda_stream)),
-            "fcirc_tune")
+    ctx = context(device)
+    with ctx.enqueue(device) as s:
+        L.check(L.lib().fcirc_tune(ctx.handle, n, ring, s), "fcirc_tune")
 
 
 SCHED_XCD = 1       # XCD-aware tile order in the top passes
@@ -266,22 +305,30 @@ SCHED_SEPARATE = 2  # split passes take the row and the vector in separate workg
 
 def set_schedule(n: int, ring: int, top_levels: int = -1, tile_log: int = -1, flags: int = SCHED_XCD, device=None):
     """Fix the pass schedule for (ring, n): see fcirc_set_schedule in include/fcirc.h."""
-    L.check(L.lib().fcirc_set_schedule(context(device).handle, ring, n, top_levels, tile_log, flags), "fcirc_set_schedule")
+    ctx = context(device)
+    with ctx.lock:
+        L.check(L.lib().fcirc_set_schedule(ctx.handle, ring, n, top_levels, tile_log, flags), "fcirc_set_schedule")
 
 
 def save_schedules(path: str, device=None):
     """Write the device context's tuned/set schedules to a text file."""
-    L.check(L.lib().fcirc_save_schedules(context(device).handle, str(path).encode()), "fcirc_save_schedules")
+    ctx = context(device)
+    with ctx.lock:
+        L.check(L.lib().fcirc_save_schedules(ctx.handle, str(path).encode()), "fcirc_save_schedules")
 
 
 def load_schedules(path: str, device=None):
     """Take the schedules a file holds for this device (EINVAL and no change if malformed)."""
-    L.check(L.lib().fcirc_load_schedules(context(device).handle, str(path).encode()), "fcirc_load_schedules")
+    ctx = context(device)
+    with ctx.lock:
+        L.check(L.lib().fcirc_load_schedules(ctx.handle, str(path).encode()), "fcirc_load_schedules")
 
 
 def get_schedule(n: int, ring: int, device=None) -> dict:
     top, tile, flags = C.c_int(), C.c_int(), C.c_int()
-    ntop = L.lib().fcirc_get_schedule(context(device).handle, ring, n, C.byref(top), C.byref(tile), C.byref(flags))
+    ctx = context(device)
+    with ctx.lock:
+        ntop = L.lib().fcirc_get_schedule(ctx.handle, ring, n, C.byref(top), C.byref(tile), C.byref(flags))
     return {"top_passes": ntop, "top_levels": top.value, "tile_log": tile.value, "flags": flags.value}
 
 
@@ -306,8 +353,9 @@ def layer_forward(a: torch.Tensor, x: torch.Tensor) -> torch.Tensor:
         raise ValueError("a must be (n,) and x (batch, n) of the same dtype")
     y = torch.empty_like(x)
     ctx = context(a.device)
-    L.check(L.lib().fcirc_matvec_fwd_shared(ctx.handle, _ptr(a), _ptr(x), _ptr(y), a.shape[0], x.shape[0],
-                                            _layer_ring(a), _stream(a)), "fcirc_matvec_fwd_shared")
+    with ctx.enqueue(a.device) as s:
+        L.check(L.lib().fcirc_matvec_fwd_shared(ctx.handle, _ptr(a), _ptr(x), _ptr(y), a.shape[0], x.shape[0],
+                                                _layer_ring(a), s), "fcirc_matvec_fwd_shared")
     return y
 
 
@@ -319,11 +367,12 @@ def layer_backward(a: torch.Tensor, x: torch.Tensor, gy: torch.Tensor, need_a: b
     ga = torch.empty_like(a) if need_a else None
     gx = torch.empty_like(x) if need_x else None
     ctx = context(a.device)
-    L.check(L.lib().fcirc_matvec_backward(ctx.handle, _ptr(a), _ptr(x), _ptr(gy),
-                                          _ptr(ga) if ga is not None else None,
-                                          _ptr(gx) if gx is not None else None,
-                                          a.shape[0], x.shape[0], _layer_ring(a), _stream(a)),
-            "fcirc_matvec_backward")
+    with ctx.enqueue(a.device) as s:
+        L.check(L.lib().fcirc_matvec_backward(ctx.handle, _ptr(a), _ptr(x), _ptr(gy),
+                                              _ptr(ga) if ga is not None else None,
+                                              _ptr(gx) if gx is not None else None,
+                                              a.shape[0], x.shape[0], _layer_ring(a), s),
+                "fcirc_matvec_backward")
     return ga, gx
 
 
