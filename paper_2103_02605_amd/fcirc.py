@@ -12,7 +12,6 @@ Conventions (Rosowski, arXiv 2103.02605):
 """
 from __future__ import annotations
 
-import contextlib
 import ctypes as C
 import threading
 
@@ -41,18 +40,10 @@ class Context:
         L.check(L.lib().fcirc_create(C.byref(h), device), "fcirc_create")
         self.handle = h
 
-    @contextlib.contextmanager
-    def enqueue(self, device=None, stream: torch.cuda.Stream | None = None):
+    def enqueue(self, device=None, stream: torch.cuda.Stream | None = None) -> "_Enqueue":
         """Hold the context for one call on `stream` (default: the current stream of
-        `device`); yields that stream as the library's stream argument."""
-        with self.lock:
-            s = stream if stream is not None else torch.cuda.current_stream(self.device if device is None else device)
-            if self._last_stream is not None and self._last_stream != s:
-                s.wait_stream(self._last_stream)
-            try:
-                yield C.c_void_p(s.cuda_stream)
-            finally:
-                self._last_stream = s
+        `device`); the with-statement yields that stream as the library's argument."""
+        return _Enqueue(self, self.device if device is None else device, stream)
 
     def close(self):
         if self.handle:
@@ -66,12 +57,42 @@ class Context:
             pass
 
 
+class _Enqueue:
+    """Context manager of Context.enqueue (a class: it runs on every call)."""
+    __slots__ = ("ctx", "device", "stream")
+
+    def __init__(self, ctx: Context, device, stream):
+        self.ctx, self.device, self.stream = ctx, device, stream
+
+    def __enter__(self) -> C.c_void_p:
+        ctx = self.ctx
+        ctx.lock.acquire()
+        try:
+            s = self.stream if self.stream is not None else torch.cuda.current_stream(self.device)
+            last = ctx._last_stream
+            if last is not None and last.cuda_stream != s.cuda_stream:
+                s.wait_stream(last)
+        except BaseException:
+            ctx.lock.release()
+            raise
+        self.stream = s
+        return C.c_void_p(s.cuda_stream)
+
+    def __exit__(self, *exc):
+        self.ctx._last_stream = self.stream
+        self.ctx.lock.release()
+        return False
+
+
 _contexts: dict[int, Context] = {}
 _contexts_lock = threading.Lock()
 
 
 def context(device=None) -> Context:
     idx = torch.cuda.current_device() if device is None else torch.device(device).index or 0
+    c = _contexts.get(idx)
+    if c is not None:
+        return c
     with _contexts_lock:
         if idx not in _contexts:
             _contexts[idx] = Context(idx)
