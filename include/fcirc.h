@@ -84,6 +84,7 @@ fcirc_status fcirc_matvec(fcirc_ctx *ctx, const void *a, const void *x, void *y,
 /*
  * `count` independent products of the same size n and the same f, stored back to back
  * (instance k at element offset k*n of a, x and y). Same rules as fcirc_matvec.
+ * count = 0 enqueues nothing and returns FCIRC_OK (the pointers must still be non-null).
  */
 fcirc_status fcirc_matvec_many(fcirc_ctx *ctx, const void *a, const void *x, void *y, uint64_t n,
                                uint32_t count, const void *f, fcirc_ring ring, void *stream);
@@ -126,6 +127,7 @@ fcirc_status fcirc_toeplitz_matvec(fcirc_ctx *ctx, const void *row, const void *
  * is computed modulo 998244353, 469762049 and 167772161 and combined by the Chinese
  * remainder theorem. It is exact when every |c_k| < 998244353*469762049 (about 4.7e17);
  * a coefficient outside that range is written as 0 and makes fcirc_check return ERANGE.
+ * EINVAL: null pointers, na = 0 or nb = 0, c overlapping a or b. ESIZE: N above 2^23.
  */
 fcirc_status fcirc_polymul_i64(fcirc_ctx *ctx, const int32_t *a, uint64_t na, const int32_t *b,
                                uint64_t nb, int64_t *c, void *stream);
@@ -135,6 +137,7 @@ fcirc_status fcirc_polymul_i64(fcirc_ctx *ctx, const int32_t *a, uint64_t na, co
  * (section 3.2 applies Algorithm 1 to large integers).
  *   a : device uint16[na], b : device uint16[nb], c : device uint16[na+nb] (written).
  * Requires N = smallest power of two >= na+nb-1 to be <= 2^23 and min(na,nb) <= 2^20.
+ * EINVAL: null pointers, na = 0 or nb = 0, c overlapping a or b; ESIZE otherwise.
  */
 fcirc_status fcirc_bigint_mul(fcirc_ctx *ctx, const uint16_t *a, uint64_t na, const uint16_t *b,
                               uint64_t nb, uint16_t *c, void *stream);
@@ -164,7 +167,8 @@ fcirc_status fcirc_fermat_matvec(fcirc_ctx *ctx, const uint32_t *a, const uint32
  * K-bit products at the leaves), and the coefficients are added back with carries. K and
  * the number of pieces are chosen so that no coefficient reaches 2^K.
  *   a : device uint16[na], b : device uint16[nb], c : device uint16[na+nb] (written).
- * Requires na + nb - 1 <= 2^24; ESIZE if no parameter choice fits.
+ * Requires na + nb - 1 <= 2^24; ESIZE if no parameter choice fits. EINVAL: null
+ * pointers, na = 0 or nb = 0, c overlapping a or b.
  */
 fcirc_status fcirc_bigint_mul_fermat(fcirc_ctx *ctx, const uint16_t *a, uint64_t na, const uint16_t *b,
                                      uint64_t nb, uint16_t *c, void *stream);
@@ -175,6 +179,9 @@ fcirc_status fcirc_bigint_mul_fermat(fcirc_ctx *ctx, const uint16_t *a, uint64_t
  * x_base and y_base and its log2 size (0 <= log2n <= 16). All instances share ring
  * and f. The launch is captured in a HIP graph on first use of an item list and
  * replayed when the same list (same pointers, offsets and sizes) comes again.
+ * count = 0 enqueues nothing and returns FCIRC_OK (the pointers must still be non-null).
+ * EINVAL: null pointers, a ring other than the three primes and C64, a nonzero reserved
+ * field; ESIZE: log2n > 16.
  */
 typedef struct {
   uint64_t a_off, x_off, y_off; /* element offsets */
@@ -193,6 +200,8 @@ fcirc_status fcirc_matvec_batched(fcirc_ctx *ctx, const void *a_base, const void
  *             gradients of a real loss with upstream gradient gy (PyTorch's convention
  *             for complex tensors; the conjugates drop out for real data).
  * ga or gx may be NULL to skip that gradient.
+ * EINVAL: null pointers (x is needed when ga is asked for), batch = 0, another ring;
+ * ESIZE: n not a power of two in [16, 2^24].
  */
 fcirc_status fcirc_matvec_fwd_shared(fcirc_ctx *ctx, const void *a, const void *x, void *y,
                                      uint64_t n, uint32_t batch, fcirc_ring ring, void *stream);

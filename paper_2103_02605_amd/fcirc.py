@@ -197,6 +197,8 @@ def matvec_many(a: torch.Tensor, x: torch.Tensor, f=None, p: int | None = None, 
     if a.shape != x.shape or a.dim() != vdim or a.dtype != x.dtype:
         raise ValueError("a and x must be tensors (count, n) of the same shape and dtype")
     y = torch.empty_like(a) if out is None else out
+    if a.shape[0] == 0:  # an empty batch: nothing to compute (empty tensors have null pointers)
+        return y
     ctx = context(a.device)
     with ctx.enqueue(a.device) as s:
         L.check(L.lib().fcirc_matvec_many(ctx.handle, _ptr(a), _ptr(x), _ptr(y), a.shape[1], a.shape[0], C.byref(fv),

@@ -72,6 +72,39 @@ def test_all_sizes_bit_exact(F, p, L):
         np.testing.assert_array_equal(host_u32(y), oracle_modp(a, x, f, p), err_msg=f"p={p} n={n} f={f}")
 
 
+def test_zero_sizes(F):
+    """Empty inputs through the C-ABI: n = 0 is ESIZE; an empty batch (count 0) enqueues
+    nothing and returns OK; an empty factor (na = 0) or an empty layer batch is EINVAL."""
+    import ctypes as C
+    import torch
+    from paper_2103_02605_amd import _lib
+    lib, ctx = _lib.lib(), F.context(0).handle
+    buf = torch.full((64,), 7, dtype=torch.int32, device="cuda")
+    out = torch.full((64,), 7, dtype=torch.int32, device="cuda")
+    p, q = C.c_void_p(buf.data_ptr()), C.c_void_p(out.data_ptr())
+    one = C.c_uint32(1)
+    OK, EINVAL, ESIZE = 0, 1, 2
+    assert lib.fcirc_matvec(ctx, p, p, q, 0, C.byref(one), _lib.FCIRC_ZP_998244353, None) == ESIZE
+    assert lib.fcirc_matvec_any(ctx, p, p, q, 0, C.byref(one), _lib.FCIRC_ZP_998244353, None) == ESIZE
+    assert lib.fcirc_toeplitz_matvec(ctx, p, p, p, q, 0, _lib.FCIRC_ZP_998244353, None) == ESIZE
+    assert lib.fcirc_fermat_matvec(ctx, p, p, q, 0, 2048, 0, None) == ESIZE
+    assert lib.fcirc_matvec_many(ctx, p, p, q, 16, 0, C.byref(one), _lib.FCIRC_ZP_998244353, None) == OK
+    assert lib.fcirc_matvec_many(ctx, None, p, q, 16, 0, C.byref(one), _lib.FCIRC_ZP_998244353, None) == EINVAL
+    items = (_lib.fcirc_item * 1)()
+    assert lib.fcirc_matvec_batched(ctx, p, p, q, items, 0, C.byref(one), _lib.FCIRC_ZP_998244353, None) == OK
+    assert lib.fcirc_polymul_i64(ctx, p, 0, p, 4, q, None) == EINVAL
+    assert lib.fcirc_bigint_mul(ctx, p, 4, p, 0, q, None) == EINVAL
+    assert lib.fcirc_bigint_mul_fermat(ctx, p, 0, p, 0, q, None) == EINVAL
+    assert lib.fcirc_matvec_fwd_shared(ctx, p, p, q, 16, 0, _lib.FCIRC_R32, None) == EINVAL
+    assert lib.fcirc_matvec_backward(ctx, p, p, p, q, None, 16, 0, _lib.FCIRC_R32, None) == EINVAL
+    torch.cuda.synchronize()
+    assert (out.cpu().numpy() == 7).all()  # nothing was written
+    # through the binding: an empty batch gives an empty result
+    y = F.matvec_many(torch.empty((0, 16), dtype=torch.int32, device="cuda"),
+                      torch.empty((0, 16), dtype=torch.int32, device="cuda"), f=1, p=P1)
+    assert y.shape == (0, 16)
+
+
 @pytest.mark.parametrize("L,top", [(8, 2), (8, 7), (13, 1), (13, 9), (15, 3), (16, 12), (17, 14), (18, 5)])
 def test_forced_splits_bit_exact(F, L, top):
     """Every split point of the recursion between HBM passes and the LDS block gives the
