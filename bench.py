@@ -237,8 +237,8 @@ def gfp2_product(torch, F, quick: bool):
 
 
 def batched_vs_plain(torch, F, W, quick: bool):
-    """4096 complex64 products of sizes 2^6..2^16 (seed 6): one graph-replayed persistent
-    launch against one fcirc_matvec call per instance, on the same device buffers."""
+    """4096 complex64 products of sizes 2^6..2^16 (seed 6): one persistent launch (its work
+    queue reused) against one fcirc_matvec call per instance, on the same device buffers."""
     from paper_2103_02605_amd.batched import BatchPlan
     e, a_list, x_list = W.batched_c64(4096, W.SEED_BATCHED)
     plan = BatchPlan(a_list, x_list, dtype=np.complex64)

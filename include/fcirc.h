@@ -16,7 +16,7 @@
  * void*; NULL means the null stream). Every entry point validates its arguments on the
  * host first and returns an error without enqueueing anything when they are invalid.
  * The caller owns every data buffer. The context owns plans, twiddle tables, workspaces
- * and captured graphs, and frees them in fcirc_destroy.
+ * and the work queues of batched launches, and frees them in fcirc_destroy.
  *
  * Threading: one context serves one host thread at a time (calls that share a context
  * must be serialised by the caller). The context's workspace is shared by its calls, so
@@ -177,8 +177,9 @@ fcirc_status fcirc_bigint_mul_fermat(fcirc_ctx *ctx, const uint16_t *a, uint64_t
  * Many independent products of different power-of-two sizes in one persistent launch.
  * items (host array of `count`) give each instance's element offsets into a_base,
  * x_base and y_base and its log2 size (0 <= log2n <= 16). All instances share ring
- * and f. The launch is captured in a HIP graph on first use of an item list and
- * replayed when the same list (same pointers, offsets and sizes) comes again.
+ * and f. The work queue is built and uploaded on first use of an item list and reused
+ * when the same list (same pointers, offsets and sizes) comes again; each call then
+ * enqueues two kernels (counter reset, persistent kernel).
  * count = 0 enqueues nothing and returns FCIRC_OK (the pointers must still be non-null).
  * EINVAL: null pointers, a ring other than the three primes and C64, a nonzero reserved
  * field; ESIZE: log2n > 16.

@@ -1,10 +1,10 @@
 """Batched products of different sizes in one persistent launch (fcirc_matvec_batched).
 
 Instances are packed back to back into three device buffers (rows, vectors, results);
-the item list gives each instance's element offsets and log2 size. The library captures
-the launch in a HIP graph the first time it sees an item list and replays it after that,
-so a BatchPlan that is run repeatedly (with new inputs loaded into the same buffers)
-costs one graph launch per run.
+the item list gives each instance's element offsets and log2 size. The library builds
+the work queue the first time it sees an item list and keeps it, so a BatchPlan that is
+run repeatedly (with new inputs loaded into the same buffers) costs two kernel launches
+per run (counter reset, persistent kernel).
 """
 from __future__ import annotations
 

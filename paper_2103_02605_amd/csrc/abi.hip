@@ -206,7 +206,7 @@ void fcirc_destroy(fcirc_ctx* ctx) {
     (void)hipFree(t.twi);
     (void)hipFree(t.dU);
   }
-  release_graphs(ctx->c);
+  release_batches(ctx->c);
   if (ctx->c.ws) (void)hipFree(ctx->c.ws);
   if (ctx->c.ws2) (void)hipFree(ctx->c.ws2);
   if (ctx->c.d_status) (void)hipFree(ctx->c.d_status);

@@ -1,6 +1,7 @@
 // Many independent f-circulant products of different power-of-two sizes in one persistent
 // launch (the recursion of Algorithm 1, Rosowski arXiv 2103.02605, section 2, applied to each
-// instance), captured in a HIP graph and replayed for a repeated batch.
+// instance). The queue built for an item list is kept and reused when the same list comes
+// again, so a repeated batch costs two launches (counter reset, persistent kernel).
 //
 // Work items, issued from one queue in this order:
 //   SPLIT  one top-split tile (row or vector) of a large instance (2^13 .. 2^16)
@@ -14,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <functional>
 #include <cstring>
 #include <vector>
 
@@ -309,24 +311,22 @@ __global__ void k_zero(uint32_t* p, uint32_t n) {
 
 }  // namespace
 
-// A captured batch: device copies of the work list, counters, workspace and the graph.
-struct GraphEntry {
+// One cached batched launch: the device item queue and instance table built for one item
+// list, and the two launches (counter reset, persistent kernel) with their arguments.
+struct BatchEntry {
   std::vector<uint64_t> key;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
   void* dev = nullptr;  // items | insts | counters
   void* ws = nullptr;
-  ~GraphEntry() {
-    if (exec) (void)hipGraphExecDestroy(exec);
-    if (graph) (void)hipGraphDestroy(graph);
+  std::function<void(hipStream_t)> run;
+  ~BatchEntry() {
     if (dev) (void)hipFree(dev);
     if (ws) (void)hipFree(ws);
   }
 };
 
-void release_graphs(Ctx& c) {
-  for (GraphEntry* g : c.graphs) delete g;
-  c.graphs.clear();
+void release_batches(Ctx& c) {
+  for (BatchEntry* g : c.batches) delete g;
+  c.batches.clear();
 }
 
 namespace {
@@ -337,11 +337,11 @@ fcirc_status build_and_launch(Ctx& c, const std::vector<uint64_t>& key, const vo
                               typename Ring::Tw const* twi, typename Ring::DeepW const* U,
                               const typename Ring::Params* rp_by_L, hipStream_t s) {
   using T = typename Ring::T;
-  for (GraphEntry* g : c.graphs)
+  for (BatchEntry* g : c.batches)
     if (g->key == key)
       return hip_status(launch(c, "fcirc_batched", s, [&](hipEvent_t e0_, hipEvent_t e1_) {
         if (e0_) (void)hipEventRecord(e0_, s);
-        (void)hipGraphLaunch(g->exec, s);
+        g->run(s);
         if (e1_) (void)hipEventRecord(e1_, s);
       }));
 
@@ -393,7 +393,7 @@ fcirc_status build_and_launch(Ctx& c, const std::vector<uint64_t>& key, const vo
     if (insts[k].big != ~0u)
       for (uint32_t v = 0; v < (1u << (insts[k].L - TILE_LOG)); ++v) q.push_back(BItem{IT_MERGE, insts[k].L, k, v});
 
-  GraphEntry* g = new GraphEntry;
+  BatchEntry* g = new BatchEntry;
   g->key = key;
   const size_t items_b = q.size() * sizeof(BItem), insts_b = insts.size() * sizeof(BInst);
   const uint32_t ncnt = 1 + 2 * nbig;  // head + counters
@@ -433,28 +433,15 @@ fcirc_status build_and_launch(Ctx& c, const std::vector<uint64_t>& key, const vo
     per_cu = 1;
   const uint32_t grid = (uint32_t)std::min<size_t>((size_t)per_cu * c.prop.multiProcessorCount, q.size());
 
-  hipStream_t cap = nullptr;
-  if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) {
-    delete g;
-    return FCIRC_EDEVICE;
-  }
-  hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed);
-  if (e == hipSuccess) {
-    hipLaunchKernelGGL(k_zero, dim3(1), dim3(256), 0, cap, B.head, ncnt);
-    hipLaunchKernelGGL(kb, dim3(grid), dim3(BT), lds, cap, B);
-    e = hipStreamEndCapture(cap, &g->graph);
-  }
-  if (e == hipSuccess) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
-  (void)hipStreamDestroy(cap);
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    delete g;
-    return FCIRC_EDEVICE;
-  }
-  c.graphs.push_back(g);
+  const uint32_t* head = B.head;
+  g->run = [B, kb, grid, lds, head, ncnt](hipStream_t st) {
+    hipLaunchKernelGGL(k_zero, dim3(1), dim3(256), 0, st, const_cast<uint32_t*>(head), ncnt);
+    hipLaunchKernelGGL(kb, dim3(grid), dim3(BT), lds, st, B);
+  };
+  c.batches.push_back(g);
   return hip_status(launch(c, "fcirc_batched", s, [&](hipEvent_t e0_, hipEvent_t e1_) {
     if (e0_) (void)hipEventRecord(e0_, s);
-    (void)hipGraphLaunch(g->exec, s);
+    g->run(s);
     if (e1_) (void)hipEventRecord(e1_, s);
   }));
 }

@@ -136,7 +136,7 @@ struct TuneVal {
   int flags = 1;      // FCIRC_SCHED_* bits
 };
 
-struct GraphEntry;  // batched launches captured in HIP graphs (batched.hip)
+struct BatchEntry;  // cached batched launches: device item queue and kernel arguments (batched.hip)
 
 struct Ctx {
   int device = 0;
@@ -154,7 +154,7 @@ struct Ctx {
   int forced_top = -1;
   std::map<TuneKey, TuneVal> tuned;
   Timer timer;
-  std::vector<GraphEntry*> graphs;  // owned; freed by release_graphs
+  std::vector<BatchEntry*> batches;  // owned; freed by release_batches
   bool debug_sync = false;
 };
 
@@ -527,7 +527,7 @@ fcirc_status embed_product(Ctx& c, fcirc_ring ring, const void* r, const void* c
                            uint64_t n, hipStream_t s);
 fcirc_status polymul_i64(Ctx& c, const int32_t* a, uint64_t na, const int32_t* b, uint64_t nb, int64_t* out, hipStream_t s);
 fcirc_status bigint_mul(Ctx& c, const uint16_t* a, uint64_t na, const uint16_t* b, uint64_t nb, uint16_t* out, hipStream_t s);
-void release_graphs(Ctx& c);
+void release_batches(Ctx& c);
 // Limbs of sum_k coef[k] 2^(16 k) (coef[k] < 2^64, k < nc) into out[0, nl); u holds nl and
 // summ 2 carry_blocks(nl) words of scratch.
 uint64_t carry_blocks(uint64_t nl);

@@ -25,7 +25,7 @@ P_GF = (1 << 31) - 1  # GF(p^2) = Z/p[sqrt 3] of section 3.1: tensors (..., 2) i
 
 
 class Context:
-    """A libfcirc context on one HIP device (plans, workspaces, graphs).
+    """A libfcirc context on one HIP device (plans, workspaces, batched work queues).
 
     The library requires calls that share a context to be serialised, and their device
     work to be ordered (they share the context's workspace). enqueue() does both for the

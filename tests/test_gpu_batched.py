@@ -1,5 +1,5 @@
 """GPU parity of the batched persistent launch (many products of different sizes in one
-launch, replayed from a HIP graph) against the CPU oracle."""
+launch, its work queue reused for a repeated item list) against the CPU oracle."""
 import numpy as np
 import pytest
 
@@ -53,9 +53,9 @@ def test_mixed_sizes_modp(B, p, f):
         np.testing.assert_array_equal(ys[k], want, err_msg=f"instance {k} n={n}")
 
 
-def test_graph_replays_with_eager_work_between(B):
-    """Capture once, replay several times with other GPU work and synchronisations in
-    between; every replay must match the eager single-product results."""
+def test_repeated_runs_with_eager_work_between(B):
+    """Build the queue once, run it several times with other GPU work and synchronisations
+    in between; every run must match the eager single-product results."""
     import torch
     from paper_2103_02605_amd import fcirc as F
     logs = [3, 8, 12, 13, 15, 16, 6, 6, 6, 11]
@@ -70,7 +70,7 @@ def test_graph_replays_with_eager_work_between(B):
         for k in range(len(logs)):
             assert rel_l2(ys[k], eager[k]) <= 1e-6, (rep, k)
         del junk
-    # new inputs in the same buffers, same graph: results follow the inputs
+    # new inputs in the same buffers, same queue: results follow the inputs
     new = [W.complex_pair(1 << L, seed=90 + k) for k, L in enumerate(logs)]
     plan.load([a for a, _ in new], [x for _, x in new])
     plan.run()
