@@ -179,7 +179,9 @@ fcirc_status fcirc_bigint_mul_fermat(fcirc_ctx *ctx, const uint16_t *a, uint64_t
  * x_base and y_base and its log2 size (0 <= log2n <= 16). All instances share ring
  * and f. The work queue is built and uploaded on first use of an item list and reused
  * when the same list (same pointers, offsets and sizes) comes again; each call then
- * enqueues two kernels (counter reset, persistent kernel).
+ * enqueues two kernels (counter reset, persistent kernel). Calls with one item list
+ * share its counters, so they must be ordered on the device (one stream, or streams that
+ * wait for each other).
  * count = 0 enqueues nothing and returns FCIRC_OK (the pointers must still be non-null).
  * EINVAL: null pointers, a ring other than the three primes and C64, a nonzero reserved
  * field; ESIZE: log2n > 16.
