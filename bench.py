@@ -145,7 +145,8 @@ def copy_ceiling(torch) -> float:
 
 def c1_latency(torch, F, W):
     """n = 1024 over Z/998244353 (seeds 1 and 2 for f = 1 and f = p - 1): one call per
-    product, and 1024 products of that size (seed 11) in one batched launch."""
+    product, and 1024 products of that size (seed 11) in one batched launch and in one
+    uniform-size call."""
     from paper_2103_02605_amd.batched import BatchPlan
     out = {}
     for f, seed, name in ((1, W.SEED_C1_CYCLIC, "f1"), (P1 - 1, W.SEED_C1_NEGACYCLIC, "f_pm1")):
@@ -160,6 +161,12 @@ def c1_latency(torch, F, W):
     ms = time_steps(torch, lambda i: plan.run(), 50, 5)
     out["batched_1024x1024_us_per_product"] = round(ms * 1e3 / 1024, 4)
     out["batched_1024x1024_us_per_launch"] = round(ms * 1e3, 2)
+    # the same 1024 products as one uniform-size call (fcirc_matvec_many: one block launch)
+    da, dx = torch.from_numpy(ab.view(np.int32)).cuda(), torch.from_numpy(xb.view(np.int32)).cuda()
+    dy = torch.empty_like(da)
+    ms = time_steps(torch, lambda i: F.matvec_many(da, dx, f=1, p=P1, out=dy), 50, 5)
+    out["many_1024x1024_us_per_product"] = round(ms * 1e3 / 1024, 4)
+    out["many_1024x1024_us_per_call"] = round(ms * 1e3, 2)
     return out
 
 
