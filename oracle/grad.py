@@ -44,6 +44,35 @@ def dense_autograd(a, x, g):
     return y.detach().numpy(), at.grad.numpy(), xt.grad.numpy()
 
 
+def layer_entries(a, x, g, idx):
+    """Entries i in idx of y (every row), grad_x (every row) and grad_a, each by its O(n)
+    sum (FP64/complex128), for sizes where the whole vectors are too costly on the CPU:
+      y[b, i]      = sum_k a_k x_b[(i + k) mod n]               (Definition 2, f = 1)
+      grad_x[b, i] = sum_k conj(a_k) g_b[(i - k) mod n]          (column i of C(a)^H)
+                   = sum_k r_k g_b[(i + k) mod n], r_k = conj(a_((-k) mod n))
+      grad_a[i]    = sum_b sum_j g_b[j] conj(x_b[(j + i) mod n]) (y_b[j] depends on a_i
+                                                                  through x_b[(j + i) mod n])
+    A cyclic shift by i is two contiguous pieces, so every sum is two dot products.
+    Returns arrays of shape (batch, len(idx)), (len(idx),), (batch, len(idx))."""
+    cplx = np.iscomplexobj(a) or np.iscomplexobj(x) or np.iscomplexobj(g)
+    dt = np.complex128 if cplx else np.float64
+    a = np.asarray(a, dtype=dt)
+    x = np.atleast_2d(np.asarray(x, dtype=dt))
+    g = np.atleast_2d(np.asarray(g, dtype=dt))
+    n = a.shape[0]
+    r = np.conj(np.concatenate([a[:1], a[:0:-1]]))  # r_k = conj(a_((-k) mod n))
+
+    def shifted_dot(u, v, i):  # sum_k u_k v_((i + k) mod n)
+        return np.dot(u[:n - i], v[i:]) + np.dot(u[n - i:], v[:i])
+
+    y = np.array([[shifted_dot(a, xb, int(i)) for i in idx] for xb in x])
+    gx = np.array([[shifted_dot(r, gb, int(i)) for i in idx] for gb in g])
+    # sum_j g_j conj(x_(j+i)): np.vdot conjugates its first argument
+    ga = np.array([sum(np.vdot(xb[int(i):], gb[:n - int(i)]) + np.vdot(xb[:int(i)], gb[n - int(i):])
+                       for gb, xb in zip(g, x)) for i in idx])
+    return y, ga, gx
+
+
 def finite_differences(a, x, g, h: float = 1e-6):
     """Central differences of L = sum(g * y(a, x)) for real a (n,), x (batch, n)."""
     a = np.asarray(a, dtype=np.float64)

@@ -203,6 +203,30 @@ def test_layer_large_batches(F, L, batch, real):
 
 
 @pytest.mark.parametrize("real", [False, True])
+def test_layer_2p23_sampled(F, real):
+    """One instance of 2^23, where the forward, grad_x and grad_a each take 10 top levels:
+    sampled entries of all three against their O(n) definitions, each within 1e-5 of the
+    sampled entries' RMS (the FFT references cost tens of seconds per vector here)."""
+    import torch
+    n = 1 << 23
+    rng = np.random.default_rng(2323 + real)
+    if real:
+        a, x, g = (rng.standard_normal(s).astype(np.float32) for s in (n, (1, n), (1, n)))
+    else:
+        a, x, g = ((rng.standard_normal(s) + 1j * rng.standard_normal(s)).astype(np.complex64)
+                   for s in (n, (1, n), (1, n)))
+    ta, tx, tg = (torch.from_numpy(v).cuda() for v in (a, x, g))
+    y = F.layer_forward(ta, tx).cpu().numpy()
+    ga, gx = F.layer_backward(ta, tx, tg)
+    ga, gx = ga.cpu().numpy(), gx.cpu().numpy()
+    idx = np.array([0, 1, n // 2, n - 1] + list(rng.integers(0, n, 4)))
+    y_ref, ga_ref, gx_ref = OG.layer_entries(a, x, g, idx)
+    for got, want in ((y[:, idx], y_ref), (gx[:, idx], gx_ref), (ga[idx], ga_ref)):
+        scale = np.sqrt(np.mean(np.abs(want) ** 2))
+        assert np.max(np.abs(got - want)) <= TOL * scale, (np.max(np.abs(got - want)) / scale)
+
+
+@pytest.mark.parametrize("real", [False, True])
 @pytest.mark.parametrize("L", list(range(4, 21)))
 def test_layer_every_size(F, L, real):
     """Forward, grad_x and grad_a at every size, for one instance and a small batch."""

@@ -400,6 +400,22 @@ def test_fft_grads_match_dense_autograd(cplx):
         np.testing.assert_allclose(v, u, rtol=1e-10, atol=1e-10)
 
 
+@pytest.mark.parametrize("cplx", [False, True])
+def test_layer_entries_match_dense_autograd(cplx):
+    """The O(n) entry formulas (used for sampled checks at sizes the dense and FFT
+    references cannot reach) against torch autograd on the dense matrix, every entry."""
+    rng = np.random.default_rng(16)
+    n, batch = 32, 3
+    def draw(*shape):
+        v = rng.standard_normal(shape)
+        return v + 1j * rng.standard_normal(shape) if cplx else v
+    a, x, g = draw(n), draw(batch, n), draw(batch, n)
+    y, ga, gx = OG.dense_autograd(a, x, g)
+    y2, ga2, gx2 = OG.layer_entries(a, x, g, np.arange(n))
+    for u, v in ((y, y2), (ga, ga2), (gx, gx2)):
+        np.testing.assert_allclose(v, u, rtol=1e-10, atol=1e-10)
+
+
 # P9b: Toeplitz products and the f-circulant of any size by embedding ----------------------
 
 def test_p9b_toeplitz_matrix_is_scipy_toeplitz():
