@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <cmath>
 
 #include "host.hpp"
@@ -443,9 +444,19 @@ hipError_t acc_block_b(Ctx& c, const PassArgs<C32>& A, float scale, uint32_t chu
   });
 }
 
+// Top levels of grad_a's accumulating pass: lf_top's, except for packed real pairs at 2^13,
+// which take one top level instead of none. Reading pairs straight from the batch, the
+// 13-level pass needs more registers than 512 threads allow and spills (81 registers);
+// measured on MI355X for 512 pairs, one top level and a 12-level pass take 75 us against
+// 82 us. Complex rows spill little there and keep the single pass (61 against 75 us).
+int ga_top(int L, uint32_t count, bool packed_real) {
+  const int t = lf_top(L, count);
+  return (packed_real && t == 0 && L == 13) ? 1 : t;
+}
+
 // Chunks of the batch for grad_a: about 256 workgroups over (block, chunk).
-uint32_t ga_chunks(int L, uint32_t count) {
-  const uint32_t blocks = 1u << lf_top(L, count);
+uint32_t ga_chunks(int L, uint32_t count, bool packed_real) {
+  const uint32_t blocks = 1u << ga_top(L, count, packed_real);
   return std::min<uint32_t>(count, std::max<uint32_t>(1, 256 / blocks));
 }
 
@@ -453,8 +464,9 @@ template <class SrcA, class SrcX, class Dst>
 hipError_t grad_a_acc(Ctx& c, const C32Tables* T, int L, uint32_t count, SrcA srca, SrcX srcx, const LayerWs& w, Dst dst,
                       hipStream_t s) {
   const uint64_t n = 1ull << L;
-  const int top = lf_top(L, count);
-  const uint32_t chunks = ga_chunks(L, count), per_chunk = (count + chunks - 1) / chunks;
+  constexpr bool packed_real = std::is_same_v<SrcA, LdPair>;
+  const int top = ga_top(L, count, packed_real);
+  const uint32_t chunks = ga_chunks(L, count, packed_real), per_chunk = (count + chunks - 1) / chunks;
   PassArgs<C32> A = layer_args(T, L, count);
   A.d0 = top;
   A.logr = L - top;
@@ -468,7 +480,12 @@ hipError_t grad_a_acc(Ctx& c, const C32Tables* T, int L, uint32_t count, SrcA sr
       case 10: return acc_block_b<10>(c, A, scale, chunks, per_chunk, sa, sx, w.part, s);
       case 11: return acc_block_b<11>(c, A, scale, chunks, per_chunk, sa, sx, w.part, s);
       case 12: return acc_block_b<12>(c, A, scale, chunks, per_chunk, sa, sx, w.part, s);
-      case 13: return acc_block_b<13>(c, A, scale, chunks, per_chunk, sa, sx, w.part, s);
+      case 13:
+        if constexpr (std::is_same_v<decltype(sa), LdPair>) {
+          return hipErrorInvalidValue;  // ga_top never leaves 13 levels to packed pairs
+        } else {
+          return acc_block_b<13>(c, A, scale, chunks, per_chunk, sa, sx, w.part, s);
+        }
       default: return hipErrorInvalidValue;
     }
   };
@@ -547,7 +564,7 @@ extern "C" fcirc_status fcirc_matvec_backward(fcirc_ctx* ctx, const void* a, con
   const bool real = ring == FCIRC_R32;
   const uint32_t count = real ? (batch + 1) / 2 : batch;
   LayerWs w;
-  st = layer_ws(c, n, count, (ga && L >= 10) ? ga_chunks(L, count) : 0, &w);
+  st = layer_ws(c, n, count, (ga && L >= 10) ? ga_chunks(L, count, real) : 0, &w);
   if (st != FCIRC_OK) return st;
   const float scale = (float)std::ldexp(1.0, -L);
   hipError_t e = hipSuccess;

@@ -45,7 +45,7 @@ def test_real_n64_against_dense_autograd_and_finite_differences(F):
 
 @pytest.mark.parametrize("n,batch", [(16, 1), (64, 3), (1024, 7), (1 << 13, 4), (1 << 14, 33), (1 << 14, 64), (1 << 16, 2), (1 << 21, 1),
                                      # grad_a by 13-level accumulating blocks: no top split at 2^13
-                                     # (512 instances), one top level at 2^14 (256 instances)
+                                     # (512 complex instances), one top level at 2^14 (256)
                                      (1 << 13, 512), (1 << 14, 256)])
 def test_complex_layer(F, n, batch):
     import torch
@@ -82,8 +82,9 @@ def test_real_odd_batches(F, batch):
 
 
 def test_real_13_level_accumulation(F):
-    """Real batch of 1024 at n = 2^13: 512 packed pairs, so grad_a's accumulating blocks take
-    all 13 levels straight from the real rows (no top split)."""
+    """Real batch of 1024 at n = 2^13: 512 packed pairs, enough for 13-level accumulating
+    blocks; packed pairs take one top level and 12-level blocks there instead (the 13-level
+    pass reading pairs directly would spill registers)."""
     import torch
     rng = np.random.default_rng(13)
     n, batch = 1 << 13, 1024
