@@ -374,75 +374,61 @@ __device__ __forceinline__ uint32_t root_shift(uint32_t f_shift, uint32_t K, uin
   return (v >> (d + 1)) % (2u * K);
 }
 
-// One split level d: butterfly t of the row (u + g v, u - g v) and of the vector
-// (g u + v, g u - v), one wave each. src may equal dst (in place).
-template <int Q>
-__global__ void __launch_bounds__(64 * FM_WAVES) k_fm_split(const uint32_t* a_in, const uint32_t* x_in, uint32_t* wa,
-                                                            uint32_t* wx, uint32_t n, uint32_t d, uint32_t f_shift) {
-  constexpr uint32_t W = 64u * Q, K = 32u * W, S = W + 1;
-  const uint32_t t = __builtin_amdgcn_readfirstlane(blockIdx.x * FM_WAVES + (threadIdx.x >> 6));  // one per wave
-  if (t >= n / 2) return;
-  const uint32_t h = n >> (d + 1), b = t / h, k = b * 2 * h + (t - b * h);
-  const uint32_t e = root_shift(f_shift, K, d, b);
-  {
-    const FE<Q> u = fload<Q>(a_in + (size_t)k * S), v = fload<Q>(a_in + (size_t)(k + h) * S);
-    const FE<Q> gv = fshl<Q>(v, e);
-    const FE<Q> r0 = fadd<Q>(u, gv), r1 = fsub<Q>(u, gv);
-    fstore<Q>(wa + (size_t)k * S, r0);
-    fstore<Q>(wa + (size_t)(k + h) * S, r1);
-  }
-  {
-    const FE<Q> u = fload<Q>(x_in + (size_t)k * S), v = fload<Q>(x_in + (size_t)(k + h) * S);
-    const FE<Q> gu = fshl<Q>(u, e);
-    const FE<Q> r0 = fadd<Q>(gu, v), r1 = fsub<Q>(gu, v);
-    fstore<Q>(wx + (size_t)k * S, r0);
-    fstore<Q>(wx + (size_t)(k + h) * S, r1);
+// R split levels d .. d + R - 1 in one pass. A wave takes the E = 2^R elements
+// k + j q (j < E, q = n / 2^(d+R)) of one depth-d block b: at level d + l the pairs
+// (j, j + E / 2^(l+1)) of sub-block s use the root of node (d + l, b 2^l + s). Row
+// (IS_X false): (u, v) -> (u + g v, u - g v); vector: (u, v) -> (g u + v, g u - v).
+// src may equal dst.
+// Split level l of a pass (then the levels below it), with compile-time indices so that
+// the E elements stay in registers.
+template <int Q, int R, int l, bool IS_X>
+__device__ __forceinline__ void fm_split_from(FE<Q>* v, uint32_t b, uint32_t d, uint32_t f_shift) {
+  if constexpr (l < R) {
+    constexpr uint32_t K = 32u * 64u * Q;
+    constexpr int E = 1 << R, h = E >> (l + 1);
+#pragma unroll
+    for (int sb = 0; sb < (1 << l); ++sb) {
+      const uint32_t e = root_shift(f_shift, K, d + l, (b << l) + sb);
+#pragma unroll
+      for (int i = 0; i < h; ++i) {
+        const int j = sb * 2 * h + i;
+        if constexpr (IS_X) {
+          const FE<Q> g = fshl<Q>(v[j], e);
+          v[j] = fadd<Q>(g, v[j + h]);
+          v[j + h] = fsub<Q>(g, v[j + h]);
+        } else {
+          const FE<Q> g = fshl<Q>(v[j + h], e);
+          v[j + h] = fsub<Q>(v[j], g);
+          v[j] = fadd<Q>(v[j], g);
+        }
+      }
+    }
+    fm_split_from<Q, R, l + 1, IS_X>(v, b, d, f_shift);
   }
 }
 
-// Two split levels d, d + 1 in one pass: a wave takes elements k, k + m/4, k + m/2,
-// k + 3m/4 of a depth-d block of m elements, splits them with node (d, b)'s root, then each
-// half with the root of its child node (d + 1, 2b) or (d + 1, 2b + 1).
-template <int Q>
-__global__ void __launch_bounds__(64 * FM_WAVES) k_fm_split2(const uint32_t* a_in, const uint32_t* x_in, uint32_t* wa,
-                                                             uint32_t* wx, uint32_t n, uint32_t d, uint32_t f_shift) {
-  constexpr uint32_t W = 64u * Q, K = 32u * W, S = W + 1;
+template <int Q, int R, bool IS_X>
+__device__ __forceinline__ void fm_split_levels(const uint32_t* src, uint32_t* dst, uint32_t k, uint32_t q, uint32_t b,
+                                                uint32_t d, uint32_t f_shift) {
+  constexpr uint32_t S = 64u * Q + 1;
+  constexpr int E = 1 << R;
+  FE<Q> v[E];
+#pragma unroll
+  for (int j = 0; j < E; ++j) v[j] = fload<Q>(src + (size_t)(k + j * q) * S);
+  fm_split_from<Q, R, 0, IS_X>(v, b, d, f_shift);
+#pragma unroll
+  for (int j = 0; j < E; ++j) fstore<Q>(dst + (size_t)(k + j * q) * S, v[j]);
+}
+
+template <int Q, int R>
+__global__ void __launch_bounds__(64 * FM_WAVES) k_fm_split(const uint32_t* a_in, const uint32_t* x_in, uint32_t* wa,
+                                                            uint32_t* wx, uint32_t n, uint32_t d, uint32_t f_shift) {
+  constexpr int E = 1 << R;
   const uint32_t t = __builtin_amdgcn_readfirstlane(blockIdx.x * FM_WAVES + (threadIdx.x >> 6));  // one per wave
-  if (t >= n / 4) return;
-  const uint32_t q4 = n >> (d + 2), b = t / q4, k = b * 4 * q4 + (t - b * q4);
-  const uint32_t e0 = root_shift(f_shift, K, d, b);
-  const uint32_t e1 = root_shift(f_shift, K, d + 1, 2 * b), e2 = root_shift(f_shift, K, d + 1, 2 * b + 1);
-  const size_t o0 = (size_t)k * S, o1 = (size_t)(k + q4) * S, o2 = (size_t)(k + 2 * q4) * S, o3 = (size_t)(k + 3 * q4) * S;
-  {  // row: (u, v) -> (u + g v, u - g v)
-    FE<Q> v0 = fload<Q>(a_in + o0), v1 = fload<Q>(a_in + o1), v2 = fload<Q>(a_in + o2), v3 = fload<Q>(a_in + o3);
-    FE<Q> g = fshl<Q>(v2, e0);
-    v2 = fsub<Q>(v0, g);
-    v0 = fadd<Q>(v0, g);
-    g = fshl<Q>(v3, e0);
-    v3 = fsub<Q>(v1, g);
-    v1 = fadd<Q>(v1, g);
-    g = fshl<Q>(v1, e1);
-    fstore<Q>(wa + o1, fsub<Q>(v0, g));
-    fstore<Q>(wa + o0, fadd<Q>(v0, g));
-    g = fshl<Q>(v3, e2);
-    fstore<Q>(wa + o3, fsub<Q>(v2, g));
-    fstore<Q>(wa + o2, fadd<Q>(v2, g));
-  }
-  {  // vector: (u, v) -> (g u + v, g u - v)
-    FE<Q> v0 = fload<Q>(x_in + o0), v1 = fload<Q>(x_in + o1), v2 = fload<Q>(x_in + o2), v3 = fload<Q>(x_in + o3);
-    FE<Q> g = fshl<Q>(v0, e0);
-    v0 = fadd<Q>(g, v2);
-    v2 = fsub<Q>(g, v2);
-    g = fshl<Q>(v1, e0);
-    v1 = fadd<Q>(g, v3);
-    v3 = fsub<Q>(g, v3);
-    g = fshl<Q>(v0, e1);
-    fstore<Q>(wx + o0, fadd<Q>(g, v1));
-    fstore<Q>(wx + o1, fsub<Q>(g, v1));
-    g = fshl<Q>(v2, e2);
-    fstore<Q>(wx + o2, fadd<Q>(g, v3));
-    fstore<Q>(wx + o3, fsub<Q>(g, v3));
-  }
+  if (t >= (n >> R)) return;
+  const uint32_t q = n >> (d + R), b = t / q, k = b * E * q + (t - b * q);
+  fm_split_levels<Q, R, false>(a_in, wa, k, q, b, d, f_shift);
+  fm_split_levels<Q, R, true>(x_in, wx, k, q, b, d, f_shift);
 }
 
 // Leaves: y_k = a_k x_k / n (1/n = 2^(2K - L)), one wave per element.
@@ -458,47 +444,42 @@ __global__ void __launch_bounds__(64 * FM_WAVES) k_fm_leaf(const uint32_t* a, co
   fstore<Q>(y + (size_t)k * S, fshl<Q>(p, (2u * K - L) % (2u * K)));
 }
 
-// One merge level d (the 1/2 of each level is folded into the leaves):
-// (M1, M2) -> ((M1 + M2) / g, M1 - M2).
-template <int Q>
-__global__ void __launch_bounds__(64 * FM_WAVES) k_fm_merge(uint32_t* y, uint32_t n, uint32_t d, uint32_t f_shift) {
-  constexpr uint32_t W = 64u * Q, K = 32u * W, S = W + 1;
-  const uint32_t t = __builtin_amdgcn_readfirstlane(blockIdx.x * FM_WAVES + (threadIdx.x >> 6));  // one per wave
-  if (t >= n / 2) return;
-  const uint32_t h = n >> (d + 1), b = t / h, k = b * 2 * h + (t - b * h);
-  const uint32_t e = root_shift(f_shift, K, d, b);
-  const FE<Q> m1 = fload<Q>(y + (size_t)k * S), m2 = fload<Q>(y + (size_t)(k + h) * S);
-  const FE<Q> c1 = fshl<Q>(fadd<Q>(m1, m2), (2u * K - e) % (2u * K));
-  const FE<Q> c2 = fsub<Q>(m1, m2);
-  fstore<Q>(y + (size_t)k * S, c1);
-  fstore<Q>(y + (size_t)(k + h) * S, c2);
+// R merge levels d + R - 1 .. d in one pass (the inverse order of k_fm_split; the 1/2 of
+// each level is folded into the leaves): (M1, M2) -> ((M1 + M2) / g, M1 - M2), in place.
+// Merge level l of a pass (then the levels above it), compile-time indices as above.
+template <int Q, int R, int l>
+__device__ __forceinline__ void fm_merge_from(FE<Q>* v, uint32_t b, uint32_t d, uint32_t f_shift) {
+  if constexpr (l >= 0) {
+    constexpr uint32_t K = 32u * 64u * Q;
+    constexpr int E = 1 << R, h = E >> (l + 1);
+#pragma unroll
+    for (int sb = 0; sb < (1 << l); ++sb) {
+      const uint32_t e = root_shift(f_shift, K, d + l, (b << l) + sb);
+#pragma unroll
+      for (int i = 0; i < h; ++i) {
+        const int j = sb * 2 * h + i;
+        const FE<Q> sum = fadd<Q>(v[j], v[j + h]);
+        v[j + h] = fsub<Q>(v[j], v[j + h]);
+        v[j] = fshl<Q>(sum, (2u * K - e) % (2u * K));
+      }
+    }
+    fm_merge_from<Q, R, l - 1>(v, b, d, f_shift);
+  }
 }
 
-// Two merge levels d + 1, d in one pass (the inverse order of k_fm_split2).
-template <int Q>
-__global__ void __launch_bounds__(64 * FM_WAVES) k_fm_merge2(uint32_t* y, uint32_t n, uint32_t d, uint32_t f_shift) {
-  constexpr uint32_t W = 64u * Q, K = 32u * W, S = W + 1;
+template <int Q, int R>
+__global__ void __launch_bounds__(64 * FM_WAVES) k_fm_merge(uint32_t* y, uint32_t n, uint32_t d, uint32_t f_shift) {
+  constexpr uint32_t S = 64u * Q + 1;
+  constexpr int E = 1 << R;
   const uint32_t t = __builtin_amdgcn_readfirstlane(blockIdx.x * FM_WAVES + (threadIdx.x >> 6));  // one per wave
-  if (t >= n / 4) return;
-  const uint32_t q4 = n >> (d + 2), b = t / q4, k = b * 4 * q4 + (t - b * q4);
-  const uint32_t e0 = root_shift(f_shift, K, d, b);
-  const uint32_t e1 = root_shift(f_shift, K, d + 1, 2 * b), e2 = root_shift(f_shift, K, d + 1, 2 * b + 1);
-  const size_t o0 = (size_t)k * S, o1 = (size_t)(k + q4) * S, o2 = (size_t)(k + 2 * q4) * S, o3 = (size_t)(k + 3 * q4) * S;
-  FE<Q> v0 = fload<Q>(y + o0), v1 = fload<Q>(y + o1), v2 = fload<Q>(y + o2), v3 = fload<Q>(y + o3);
-  // level d + 1: (M1, M2) -> ((M1 + M2) / g, M1 - M2) in both children
-  FE<Q> sum = fadd<Q>(v0, v1);
-  v1 = fsub<Q>(v0, v1);
-  v0 = fshl<Q>(sum, (2u * K - e1) % (2u * K));
-  sum = fadd<Q>(v2, v3);
-  v3 = fsub<Q>(v2, v3);
-  v2 = fshl<Q>(sum, (2u * K - e2) % (2u * K));
-  // level d
-  sum = fadd<Q>(v0, v2);
-  fstore<Q>(y + o2, fsub<Q>(v0, v2));
-  fstore<Q>(y + o0, fshl<Q>(sum, (2u * K - e0) % (2u * K)));
-  sum = fadd<Q>(v1, v3);
-  fstore<Q>(y + o3, fsub<Q>(v1, v3));
-  fstore<Q>(y + o1, fshl<Q>(sum, (2u * K - e0) % (2u * K)));
+  if (t >= (n >> R)) return;
+  const uint32_t q = n >> (d + R), b = t / q, k = b * E * q + (t - b * q);
+  FE<Q> v[E];
+#pragma unroll
+  for (int j = 0; j < E; ++j) v[j] = fload<Q>(y + (size_t)(k + j * q) * S);
+  fm_merge_from<Q, R, R - 1>(v, b, d, f_shift);
+#pragma unroll
+  for (int j = 0; j < E; ++j) fstore<Q>(y + (size_t)(k + j * q) * S, v[j]);
 }
 
 // Canonical form of n elements (the input check): the top word is 0 or 1, and 1 only
@@ -554,45 +535,69 @@ __global__ void k_fm_coef(const uint32_t* __restrict__ y, uint32_t n, uint32_t W
   coef[k] = s;
 }
 
+// Levels per split or merge pass (the pass holds 2^R elements of Q words per lane). Two:
+// measured on MI355X for the 2 x 2^24-bit product (K = 8192, 2^14 pieces), passes of 3 and
+// 4 levels took 545 and 720 us against 499 us, their registers (200 and 256 per lane in
+// the split) cutting occupancy more than the fewer passes save.
+constexpr int fm_pass_levels(int) { return 2; }
+
+template <int Q, int R>
+hipError_t fm_split_pass(Ctx& c, const uint32_t* sa, const uint32_t* sx, uint32_t* wa, uint32_t* wx, uint32_t n, uint32_t d,
+                         uint32_t f_shift, hipStream_t s) {
+  const uint32_t grid = ((n >> R) + FM_WAVES - 1) / FM_WAVES;
+  return launch(c, "fcirc_fermat_split", s, [&](hipEvent_t e0_, hipEvent_t e1_) {
+    FCIRC_LAUNCH(e0_, e1_, (k_fm_split<Q, R>), dim3(grid), dim3(64 * FM_WAVES), 0, s, sa, sx, wa, wx, n, d, f_shift);
+  });
+}
+
+template <int Q, int R>
+hipError_t fm_merge_pass(Ctx& c, uint32_t* y, uint32_t n, uint32_t d, uint32_t f_shift, hipStream_t s) {
+  const uint32_t grid = ((n >> R) + FM_WAVES - 1) / FM_WAVES;
+  return launch(c, "fcirc_fermat_merge", s, [&](hipEvent_t e0_, hipEvent_t e1_) {
+    FCIRC_LAUNCH(e0_, e1_, (k_fm_merge<Q, R>), dim3(grid), dim3(64 * FM_WAVES), 0, s, y, n, d, f_shift);
+  });
+}
+
 template <int Q>
 hipError_t fm_product_q(Ctx& c, const uint32_t* a, const uint32_t* x, uint32_t* y, int L, uint32_t f_shift, uint32_t* wa,
                         uint32_t* wx, hipStream_t s) {
+  constexpr int RM = fm_pass_levels(Q);
   const uint32_t n = 1u << L;
-  const uint32_t gb = (n / 2 + FM_WAVES - 1) / FM_WAVES, gl = (n + FM_WAVES - 1) / FM_WAVES;
-  const uint32_t g4 = (n / 4 + FM_WAVES - 1) / FM_WAVES;
   hipError_t e = hipSuccess;
   const uint32_t* sa = a;
   const uint32_t* sx = x;
-  // levels in pairs (radix 4); an odd last level alone
-  for (int d = 0; d < L && e == hipSuccess; d += 2) {
+  // levels in passes of RM from the top; the last pass takes what is left
+  for (int d = 0; d < L && e == hipSuccess; d += RM) {
+    const int r = std::min(RM, L - d);
     const uint32_t dd = (uint32_t)d;
-    if (d + 1 < L)
-      e = launch(c, "fcirc_fermat_split", s, [&](hipEvent_t e0_, hipEvent_t e1_) {
-        FCIRC_LAUNCH(e0_, e1_, k_fm_split2<Q>, dim3(g4), dim3(64 * FM_WAVES), 0, s, sa, sx, wa, wx, n, dd, f_shift);
-      });
-    else
-      e = launch(c, "fcirc_fermat_split", s, [&](hipEvent_t e0_, hipEvent_t e1_) {
-        FCIRC_LAUNCH(e0_, e1_, k_fm_split<Q>, dim3(gb), dim3(64 * FM_WAVES), 0, s, sa, sx, wa, wx, n, dd, f_shift);
-      });
+    if (r == 1) e = fm_split_pass<Q, 1>(c, sa, sx, wa, wx, n, dd, f_shift, s);
+    else if (r == 2) e = fm_split_pass<Q, 2>(c, sa, sx, wa, wx, n, dd, f_shift, s);
+    else if constexpr (RM >= 3) {
+      if (r == 3) e = fm_split_pass<Q, 3>(c, sa, sx, wa, wx, n, dd, f_shift, s);
+      else if constexpr (RM >= 4) {
+        if (r == 4) e = fm_split_pass<Q, 4>(c, sa, sx, wa, wx, n, dd, f_shift, s);
+      }
+    }
     sa = wa;
     sx = wx;
   }
   if (e != hipSuccess) return e;
-  const uint32_t LL = (uint32_t)L;
+  const uint32_t LL = (uint32_t)L, gl = (n + FM_WAVES - 1) / FM_WAVES;
   e = launch(c, "fcirc_fermat_leaf", s, [&](hipEvent_t e0_, hipEvent_t e1_) {
     FCIRC_LAUNCH(e0_, e1_, k_fm_leaf<Q>, dim3(gl), dim3(64 * FM_WAVES), 0, s, sa, sx, y, n, LL);
   });
-  // the same pairs in reverse: the odd last level first, alone
-  for (int d = (L - 1) & ~1; d >= 0 && e == hipSuccess; d -= 2) {
+  // the same passes in reverse order (none when n = 1)
+  for (int d = L > 0 ? ((L - 1) / RM) * RM : -1; d >= 0 && e == hipSuccess; d -= RM) {
+    const int r = std::min(RM, L - d);
     const uint32_t dd = (uint32_t)d;
-    if (d + 1 < L)
-      e = launch(c, "fcirc_fermat_merge", s, [&](hipEvent_t e0_, hipEvent_t e1_) {
-        FCIRC_LAUNCH(e0_, e1_, k_fm_merge2<Q>, dim3(g4), dim3(64 * FM_WAVES), 0, s, y, n, dd, f_shift);
-      });
-    else
-      e = launch(c, "fcirc_fermat_merge", s, [&](hipEvent_t e0_, hipEvent_t e1_) {
-        FCIRC_LAUNCH(e0_, e1_, k_fm_merge<Q>, dim3(gb), dim3(64 * FM_WAVES), 0, s, y, n, dd, f_shift);
-      });
+    if (r == 1) e = fm_merge_pass<Q, 1>(c, y, n, dd, f_shift, s);
+    else if (r == 2) e = fm_merge_pass<Q, 2>(c, y, n, dd, f_shift, s);
+    else if constexpr (RM >= 3) {
+      if (r == 3) e = fm_merge_pass<Q, 3>(c, y, n, dd, f_shift, s);
+      else if constexpr (RM >= 4) {
+        if (r == 4) e = fm_merge_pass<Q, 4>(c, y, n, dd, f_shift, s);
+      }
+    }
   }
   return e;
 }
