@@ -15,8 +15,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
-#include <functional>
 #include <cstring>
+#include <functional>
 #include <vector>
 
 #include "host.hpp"

@@ -17,8 +17,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
-#include <type_traits>
 #include <cmath>
+#include <type_traits>
 
 #include "host.hpp"
 
