@@ -67,7 +67,7 @@ class BatchPlan:
 
     def run(self, stream=None):
         ctx = context(self.a.device)
-        with ctx.enqueue(self.a.device, stream) as s:
+        with ctx.enqueue(stream) as s:
             L.check(L.lib().fcirc_matvec_batched(ctx.handle, C.c_void_p(self.a.data_ptr()), C.c_void_p(self.x.data_ptr()),
                                                  C.c_void_p(self.y.data_ptr()), self.items, len(self.sizes),
                                                  C.byref(self.f), self.ring, s),

@@ -40,10 +40,10 @@ class Context:
         L.check(L.lib().fcirc_create(C.byref(h), device), "fcirc_create")
         self.handle = h
 
-    def enqueue(self, device=None, stream: torch.cuda.Stream | None = None) -> "_Enqueue":
-        """Hold the context for one call on `stream` (default: the current stream of
-        `device`); the with-statement yields that stream as the library's argument."""
-        return _Enqueue(self, self.device if device is None else device, stream)
+    def enqueue(self, stream: torch.cuda.Stream | None = None) -> "_Enqueue":
+        """Hold the context for one call on `stream` (default: the current stream of the
+        context's device); the with-statement yields that stream as the library's argument."""
+        return _Enqueue(self, stream)
 
     def close(self):
         if self.handle:
@@ -57,29 +57,41 @@ class Context:
             pass
 
 
+# The raw handle of a device's current stream, without building a Stream object (the
+# common case needs only the handle; Stream objects are built when the stream changes).
+_raw_current_stream = getattr(torch._C, "_cuda_getCurrentRawStream", None)
+
+
+def _current_stream_handle(device: int) -> int:
+    if _raw_current_stream is not None:
+        return _raw_current_stream(device)
+    return torch.cuda.current_stream(device).cuda_stream
+
+
 class _Enqueue:
     """Context manager of Context.enqueue (a class: it runs on every call)."""
-    __slots__ = ("ctx", "device", "stream")
+    __slots__ = ("ctx", "stream", "handle")
 
-    def __init__(self, ctx: Context, device, stream):
-        self.ctx, self.device, self.stream = ctx, device, stream
+    def __init__(self, ctx: Context, stream):
+        self.ctx, self.stream, self.handle = ctx, stream, None
 
     def __enter__(self) -> C.c_void_p:
         ctx = self.ctx
         ctx.lock.acquire()
         try:
-            s = self.stream if self.stream is not None else torch.cuda.current_stream(self.device)
+            h = self.stream.cuda_stream if self.stream is not None else _current_stream_handle(ctx.device)
             last = ctx._last_stream
-            if last is not None and last.cuda_stream != s.cuda_stream:
-                s.wait_stream(last)
+            if last is not None and last != h:
+                cur = self.stream if self.stream is not None else torch.cuda.current_stream(ctx.device)
+                cur.wait_stream(torch.cuda.ExternalStream(last, device=ctx.device))
         except BaseException:
             ctx.lock.release()
             raise
-        self.stream = s
-        return C.c_void_p(s.cuda_stream)
+        self.handle = h
+        return C.c_void_p(h)
 
     def __exit__(self, *exc):
-        self.ctx._last_stream = self.stream
+        self.ctx._last_stream = self.handle  # raw handle of the stream of this call
         self.ctx.lock.release()
         return False
 
@@ -147,7 +159,7 @@ def matvec(a: torch.Tensor, x: torch.Tensor, f=None, p: int | None = None, out: 
     y = torch.empty_like(a) if out is None else out
     _need(y, "out")
     ctx = context(a.device)
-    with ctx.enqueue(a.device) as s:
+    with ctx.enqueue() as s:
         L.check(L.lib().fcirc_matvec(ctx.handle, _ptr(a), _ptr(x), _ptr(y), a.shape[0], C.byref(fv), ring, s),
                 "fcirc_matvec")
     return y
@@ -164,7 +176,7 @@ def matvec_any(a: torch.Tensor, x: torch.Tensor, f=None, p: int | None = None, o
     y = torch.empty_like(a) if out is None else out
     _need(y, "out")
     ctx = context(a.device)
-    with ctx.enqueue(a.device) as s:
+    with ctx.enqueue() as s:
         L.check(L.lib().fcirc_matvec_any(ctx.handle, _ptr(a), _ptr(x), _ptr(y), a.numel(), C.byref(fv), ring, s),
                 "fcirc_matvec_any")
     return y
@@ -181,7 +193,7 @@ def toeplitz_matvec(row: torch.Tensor, col: torch.Tensor, x: torch.Tensor, p: in
     y = torch.empty_like(row) if out is None else out
     _need(y, "out")
     ctx = context(row.device)
-    with ctx.enqueue(row.device) as s:
+    with ctx.enqueue() as s:
         L.check(L.lib().fcirc_toeplitz_matvec(ctx.handle, _ptr(row), _ptr(col), _ptr(x), _ptr(y), row.numel(), ring,
                                               s), "fcirc_toeplitz_matvec")
     return y
@@ -200,7 +212,7 @@ def matvec_many(a: torch.Tensor, x: torch.Tensor, f=None, p: int | None = None, 
     if a.shape[0] == 0:  # an empty batch: nothing to compute (empty tensors have null pointers)
         return y
     ctx = context(a.device)
-    with ctx.enqueue(a.device) as s:
+    with ctx.enqueue() as s:
         L.check(L.lib().fcirc_matvec_many(ctx.handle, _ptr(a), _ptr(x), _ptr(y), a.shape[1], a.shape[0], C.byref(fv),
                                           ring, s), "fcirc_matvec_many")
     return y
@@ -214,7 +226,7 @@ def polymul_i64(a: torch.Tensor, b: torch.Tensor, out: torch.Tensor | None = Non
         raise TypeError("polymul_i64 takes int32 coefficient tensors")
     c = torch.empty(a.numel() + b.numel() - 1, dtype=torch.int64, device=a.device) if out is None else out
     ctx = context(a.device)
-    with ctx.enqueue(a.device) as s:
+    with ctx.enqueue() as s:
         L.check(L.lib().fcirc_polymul_i64(ctx.handle, _ptr(a), a.numel(), _ptr(b), b.numel(), _ptr(c), s),
                 "fcirc_polymul_i64")
     return c
@@ -228,7 +240,7 @@ def bigint_mul(a: torch.Tensor, b: torch.Tensor, out: torch.Tensor | None = None
         raise TypeError("bigint_mul takes uint16 (or int16-viewed) limb tensors")
     c = torch.empty(a.numel() + b.numel(), dtype=a.dtype, device=a.device) if out is None else out
     ctx = context(a.device)
-    with ctx.enqueue(a.device) as s:
+    with ctx.enqueue() as s:
         L.check(L.lib().fcirc_bigint_mul(ctx.handle, _ptr(a), a.numel(), _ptr(b), b.numel(), _ptr(c), s),
                 "fcirc_bigint_mul")
     return c
@@ -248,7 +260,7 @@ def fermat_matvec(a: torch.Tensor, x: torch.Tensor, K: int, f_shift: int = 0, ou
     y = torch.empty_like(a) if out is None else out
     _need(y, "out")
     ctx = context(a.device)
-    with ctx.enqueue(a.device) as s:
+    with ctx.enqueue() as s:
         L.check(L.lib().fcirc_fermat_matvec(ctx.handle, _ptr(a), _ptr(x), _ptr(y), a.shape[0], int(K), int(f_shift),
                                             s), "fcirc_fermat_matvec")
     return y
@@ -262,7 +274,7 @@ def bigint_mul_fermat(a: torch.Tensor, b: torch.Tensor, out: torch.Tensor | None
         raise TypeError("bigint_mul_fermat takes uint16 (or int16-viewed) limb tensors")
     c = torch.empty(a.numel() + b.numel(), dtype=a.dtype, device=a.device) if out is None else out
     ctx = context(a.device)
-    with ctx.enqueue(a.device) as s:
+    with ctx.enqueue() as s:
         L.check(L.lib().fcirc_bigint_mul_fermat(ctx.handle, _ptr(a), a.numel(), _ptr(b), b.numel(), _ptr(c), s),
                 "fcirc_bigint_mul_fermat")
     return c
@@ -271,7 +283,7 @@ def bigint_mul_fermat(a: torch.Tensor, b: torch.Tensor, out: torch.Tensor | None
 def check(device=None):
     """Synchronise the current stream and raise on a sticky device-side error (ERANGE)."""
     ctx = context(device)
-    with ctx.enqueue(device) as s:
+    with ctx.enqueue() as s:
         L.check(L.lib().fcirc_check(ctx.handle, s), "fcirc_check")
 
 
@@ -318,7 +330,7 @@ def get_split(n: int, ring: int, device=None) -> int:
 
 def tune(n: int, ring: int, device=None):
     ctx = context(device)
-    with ctx.enqueue(device) as s:
+    with ctx.enqueue() as s:
         L.check(L.lib().fcirc_tune(ctx.handle, n, ring, s), "fcirc_tune")
 
 
@@ -376,7 +388,7 @@ def layer_forward(a: torch.Tensor, x: torch.Tensor) -> torch.Tensor:
         raise ValueError("a must be (n,) and x (batch, n) of the same dtype")
     y = torch.empty_like(x)
     ctx = context(a.device)
-    with ctx.enqueue(a.device) as s:
+    with ctx.enqueue() as s:
         L.check(L.lib().fcirc_matvec_fwd_shared(ctx.handle, _ptr(a), _ptr(x), _ptr(y), a.shape[0], x.shape[0],
                                                 _layer_ring(a), s), "fcirc_matvec_fwd_shared")
     return y
@@ -390,7 +402,7 @@ def layer_backward(a: torch.Tensor, x: torch.Tensor, gy: torch.Tensor, need_a: b
     ga = torch.empty_like(a) if need_a else None
     gx = torch.empty_like(x) if need_x else None
     ctx = context(a.device)
-    with ctx.enqueue(a.device) as s:
+    with ctx.enqueue() as s:
         L.check(L.lib().fcirc_matvec_backward(ctx.handle, _ptr(a), _ptr(x), _ptr(gy),
                                               _ptr(ga) if ga is not None else None,
                                               _ptr(gx) if gx is not None else None,
