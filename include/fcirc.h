@@ -76,7 +76,8 @@ const char *fcirc_strerror(fcirc_status s);
  * 2^23 / 2^26 / 2^25 for the three primes and 2^26 for the complex rings and GF(p^2)),
  * ENOROOT (f = 0 or f has no n-th root in Z/p; f other than 1 or -1 in GF(p^2)). Complex
  * rings accept any nonzero f; the accuracy statement (relative L2 error near 1e-6 for
- * n <= 2^16) holds for |f| = 1.
+ * n <= 2^16) is made for |f| = 1, and the tests also hold f = 2, 0.5i and 1.5 + 0.5i to
+ * 1e-5 up to n = 2^15.
  */
 fcirc_status fcirc_matvec(fcirc_ctx *ctx, const void *a, const void *x, void *y, uint64_t n,
                           const void *f, fcirc_ring ring, void *stream);

@@ -204,6 +204,19 @@ def test_complex_unit_f(F, f):
         assert rel_l2(got, want) <= TOL, (L, f)
 
 
+@pytest.mark.parametrize("f", [2.0, 0.5j, 1.5 + 0.5j])
+def test_complex_non_unit_f(F, f):
+    """f off the unit circle (accepted by the ABI; the node roots then have moduli
+    |f|^(1/2^(d+1))): every entry against the FP64 oracle, whose error measure is taken
+    relative to the result's own norm as for unit f."""
+    for L in (1, 6, 12, 15):
+        n = 1 << L
+        a, x = W.complex_pair(n, seed=L + 70)
+        want = O.levels_matvec_c128(a.astype(np.complex128), x.astype(np.complex128), f)
+        got = F.matvec(dev(a), dev(x), f=f).cpu().numpy()
+        assert rel_l2(got, want) <= TOL, (L, f, rel_l2(got, want))
+
+
 @pytest.mark.parametrize("L", [0, 1, 5, 11, 12, 14, 16])
 def test_real_ring(F, L):
     n = 1 << L
