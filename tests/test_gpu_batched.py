@@ -37,6 +37,22 @@ def test_mixed_sizes_complex(B):
         assert rel_l2(ys[k], want) <= TOL, (k, logs[k])
 
 
+@pytest.mark.parametrize("f", [-1.0, np.exp(0.7j)])
+def test_mixed_sizes_complex_f(B, f):
+    """The batched launch with f != 1 (its twiddle tables are f's), sizes 2^0 .. 2^16."""
+    rng = np.random.default_rng(7)
+    logs = [0, 1, 4, 8, 12, 13, 16] + list(rng.integers(0, 17, 12))
+    a_list, x_list = [], []
+    for k, L in enumerate(logs):
+        a, x = W.complex_pair(1 << int(L), seed=2000 + k)
+        a_list.append(a)
+        x_list.append(x)
+    ys = B.matvec_batched_c64(a_list, x_list, f=f)
+    for k in range(len(logs)):
+        want = O.levels_matvec_c128(a_list[k].astype(np.complex128), x_list[k].astype(np.complex128), f)
+        assert rel_l2(ys[k], want) <= TOL, (k, logs[k])
+
+
 @pytest.mark.parametrize("p,f", [(W.P1, 1), (W.P2, W.P2 - 1), (W.P3, 1)])
 def test_mixed_sizes_modp(B, p, f):
     rng = np.random.default_rng(p % 1000)
