@@ -44,6 +44,15 @@ OPS_LEAF = 8.0
 # Schedule bytes per coefficient of each kernel (uint32 data): split reads a, x and writes
 # both; the block reads both and writes y; the merge reads and writes y.
 BYTES_PER_COEF = {"fcirc_top_split": 16, "fcirc_block": 12, "fcirc_top_merge": 8}
+# Secondary rows. Garner CRT of three residues to one coefficient (three Shoup products,
+# their corrections and the 64-bit combination) and the carry passes of the large-integer
+# product, in lane-operations per output coefficient (limb).
+OPS_CRT = 30.0
+OPS_CARRY = 20.0
+# Complex FP32 rows: FP32 operations per coefficient per level of one transform (split of
+# a, split of x or merge of y: half a complex product by the twiddle, 4 operations with
+# fused multiply-adds, plus a complex sum and difference, 4 operations; 13 for all three).
+FP32_OPS_PER_COEF_LEVEL_TRANSFORM = 13.0 / 3.0
 
 
 # The sources the headline product's kernels and launches are built from (the Z/p plan and
@@ -135,6 +144,39 @@ def headline(torch, F, W, steps, warmup, nsets=24):
     return n, ms, stages, T, spread
 
 
+def negacyclic_headline(torch, F, W, steps, warmup, nsets=24):
+    """The headline product with f = p - 1 (a negacyclic correlation): n = 2^21 over
+    Z/998244353, same inputs (seed 3 + 1000 k), same 24 rotating sets."""
+    n = 1 << 21
+    sets = []
+    for k in range(nsets):
+        a, x = W.modp_pair(n, P1, seed=W.SEED_HEADLINE + 1000 * k)
+        sets.append((torch.from_numpy(a.view(np.int32)).cuda(), torch.from_numpy(x.view(np.int32)).cuda(),
+                     torch.empty(n, dtype=torch.int32, device="cuda")))
+
+    def step(i):
+        a, x, y = sets[i % nsets]
+        F.matvec(a, x, f=P1 - 1, p=P1, out=y)
+    ms = time_steps(torch, step, steps, warmup)
+    return {"ms": ms, "Gcoeff_per_s": n / ms / 1e6, **fractions(12 * n, ALU_OPS_PER_COEF_ZP(21) * n, ms)}
+
+
+def fractions(bytes_compulsory: float, lane_ops: float | None, ms: float) -> dict:
+    """HBM fraction (compulsory bytes over the whole call against 8 TB/s) and VALU fraction
+    (modelled 32-bit lane-operations against 39.3 T/s) of one measured call."""
+    out = {"hbm_frac": round(bytes_compulsory / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+           "compulsory_bytes": int(bytes_compulsory)}
+    if lane_ops is not None:
+        out["valu_frac"] = round(lane_ops / (ms * 1e-3) / 1e12 / VALU_PEAK_TOPS, 4)
+        out["model_lane_ops"] = int(lane_ops)
+    return out
+
+
+def ALU_OPS_PER_COEF_ZP(L: int) -> float:  # noqa: N802 - a model constant, written as a function of L
+    """Lane-operations per coefficient of one Z/p product of length 2^L (cost model above)."""
+    return 3 * L * OPS_PER_COEF_LEVEL + OPS_LEAF
+
+
 def copy_ceiling(torch) -> float:
     """GB/s (read + write) of a plain 64 MiB device copy: the same-box HBM reference."""
     src = torch.ones(1 << 24, dtype=torch.int32, device="cuda")
@@ -155,6 +197,8 @@ def c1_latency(torch, F, W):
         ty = torch.empty_like(ta)
         ms = time_steps(torch, lambda i: F.matvec(ta, tx, f=f, p=P1, out=ty), 200, 20)
         out[f"plain_us_per_call_{name}"] = round(ms * 1e3, 3)
+        if name == "f1":
+            out.update(fractions(12 * 1024, ALU_OPS_PER_COEF_ZP(10) * 1024, ms))
     ab, xb = W.modp_batch(1024, 1024, P1)
     al, xl = list(ab), list(xb)
     plan = BatchPlan(al, xl, p=P1, f=1)
@@ -177,15 +221,21 @@ def secondary(torch, F, W, quick: bool):
     ta, tb = torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda()
     c = torch.empty((1 << 21) - 1, dtype=torch.int64, device="cuda")
     ms = time_steps(torch, lambda i: F.polymul_i64(ta, tb, out=c), 20 if quick else 100, 5)
-    out["polymul_i64_2x2^20"] = {"ms": ms, "Gcoeff_per_s": ((1 << 21) - 1) / ms / 1e6}
+    N, nc = 1 << 21, (1 << 21) - 1
+    out["polymul_i64_2x2^20"] = {"ms": ms, "Gcoeff_per_s": nc / ms / 1e6,
+                                 **fractions(2 * (1 << 20) * 4 + nc * 8,
+                                             3 * ALU_OPS_PER_COEF_ZP(21) * N + OPS_CRT * nc, ms)}
     # C3: big integers, 2 x 2^24 bits -> 2^21 limbs
     a, b = W.bigint_u16(1 << 20, W.SEED_BIGINT)
     ta, tb = torch.from_numpy(a.view(np.int16)).cuda(), torch.from_numpy(b.view(np.int16)).cuda()
     c = torch.empty(1 << 21, dtype=torch.int16, device="cuda")
     ms = time_steps(torch, lambda i: F.bigint_mul(ta, tb, out=c), 20 if quick else 100, 5)
-    out["bigint_mul_2x2^24bit"] = {"ms": ms, "Glimb_per_s": (1 << 21) / ms / 1e6}
+    out["bigint_mul_2x2^24bit"] = {"ms": ms, "Glimb_per_s": N / ms / 1e6,
+                                   **fractions(2 * (1 << 20) * 2 + N * 2,
+                                               3 * ALU_OPS_PER_COEF_ZP(21) * N + (OPS_CRT + OPS_CARRY) * N, ms)}
     out["bigint_fermat_2x2^24bit"] = bigint_fermat(torch, F, ta, tb, ms, quick)
     out["c1_n1024_latency"] = c1_latency(torch, F, W)
+    out["headline_negacyclic_f_p-1_2^21"] = negacyclic_headline(torch, F, W, 20 if quick else 200, 10)
     out["circulant_vs_fft_c64_2^21"] = circulant_vs_fft(torch, F, W, quick)
     out["gfp2_section3_ring_2^21"] = gfp2_product(torch, F, quick)
     out["batched_c64_4096"] = batched_vs_plain(torch, F, W, quick)
@@ -227,7 +277,8 @@ def circulant_vs_fft(torch, F, W, quick: bool):
     ms_f = time_steps(torch, classic, 20 if quick else 200, 10)
     yc = classic(0)
     rel = float(torch.linalg.vector_norm(ty - yc) / torch.linalg.vector_norm(yc))
-    return {"circulant_ms": ms_c, "fft_ms": ms_f, "fft_over_circulant": ms_f / ms_c, "rel_l2_between": rel}
+    return {"circulant_ms": ms_c, "fft_ms": ms_f, "fft_over_circulant": ms_f / ms_c, "rel_l2_between": rel,
+            **fractions(24 * n, 3 * FP32_OPS_PER_COEF_LEVEL_TRANSFORM * 21 * n, ms_c)}
 
 
 def gfp2_product(torch, F, quick: bool):
@@ -240,7 +291,7 @@ def gfp2_product(torch, F, quick: bool):
              torch.from_numpy(rng.integers(0, p, (n, 2)).astype(np.int32)).cuda()) for _ in range(8)]
     ty = torch.empty_like(sets[0][0])
     ms = time_steps(torch, lambda i: F.matvec(sets[i % 8][0], sets[i % 8][1], f=1, p=p, out=ty), 20 if quick else 200, 10)
-    return {"ms": ms, "Gcoeff_per_s": n / ms / 1e6}
+    return {"ms": ms, "Gcoeff_per_s": n / ms / 1e6, **fractions(24 * n, None, ms)}
 
 
 def batched_vs_plain(torch, F, W, quick: bool):
@@ -258,9 +309,10 @@ def batched_vs_plain(torch, F, W, quick: bool):
         for a, x, y in views:
             F.matvec(a, x, out=y)
     ms_p = time_steps(torch, plain, 1 if quick else 3, 1)
+    ops = sum(3 * FP32_OPS_PER_COEF_LEVEL_TRANSFORM * int(L) * (1 << int(L)) for L in e)
     return {"coefficients": total, "batched_ms": ms_b, "plain_ms": ms_p,
             "batched_Gcoeff_per_s": total / ms_b / 1e6, "plain_Gcoeff_per_s": total / ms_p / 1e6,
-            "batched_over_plain": ms_p / ms_b}
+            "batched_over_plain": ms_p / ms_b, **fractions(24 * total, ops, ms_b)}
 
 
 def layer_vs_plain(torch, F, W, quick: bool):
@@ -286,8 +338,117 @@ def layer_vs_plain(torch, F, W, quick: bool):
             F.matvec(tg[b], tx[b], out=parts[b])
         parts.sum(0)
     ms_p = time_steps(torch, plain, 1 if quick else 3, 1)
+    # compulsory: forward reads x, writes y; backward reads x and gy, writes gx (float32),
+    # plus the row and its gradient; work: per row, the forward splits x and merges y, the
+    # backward splits gy twice, x once, and merges grad_x (grad_a's merge is shared)
+    rows, L = tx.shape[0], n.bit_length() - 1
+    nbytes = 4 * (5 * rows * n + 3 * n)
+    ops = rows * 6 * FP32_OPS_PER_COEF_LEVEL_TRANSFORM * L * n
     return {"fwd_bwd_ms": ms_f, "plain_ms": ms_p, "fused_over_plain": ms_p / ms_f,
-            "coefficients_per_pass": int(tx.numel())}
+            "coefficients_per_pass": int(tx.numel()), **fractions(nbytes, ops, ms_f)}
+
+
+def _pool_cores() -> int:
+    """Worker processes for the pooled oracle runs: the cores this process may use, at most 16."""
+    return max(1, min(16, len(os.sched_getaffinity(0))))
+
+
+def _oracle_residues(args):
+    """One prime's residues of the polynomial product (pool worker; oracle only)."""
+    a, b, p = args
+    from oracle import polymul as OP
+    return OP.poly_residues(a, b, p)
+
+
+def _oracle_c128(args):
+    """One complex product by the oracle's level form (pool worker)."""
+    a, x = args
+    from oracle import fcirc as O
+    O.levels_matvec_c128(a.astype(np.complex128), x.astype(np.complex128))
+    return a.shape[0]
+
+
+def _timed(fn):
+    t0 = time.perf_counter()
+    r = fn()
+    return r, time.perf_counter() - t0
+
+
+def cpu_baselines_secondary(W) -> dict:
+    """The oracle on each secondary configuration, timed on this host (reported baselines,
+    not targets). Runs before the GPU is touched, so the spawned pool workers start from a
+    process with no device state. Single products run on 1 core; the independent parts of
+    a configuration (the three primes of C2 and C3, the instances of C4) also run on a
+    process pool."""
+    import multiprocessing as mp
+
+    from oracle import bigint as OB
+    from oracle import fcirc as O
+    from oracle import polymul as OP
+    host = cpu_model()
+    cores = _pool_cores()
+    spawn = mp.get_context("spawn")
+    out = {}
+    # C1: the dense O(n^2) definition, n = 1024, f = 1 and f = p - 1
+    vals = {}
+    for f, seed, name in ((1, W.SEED_C1_CYCLIC, "f1"), (P1 - 1, W.SEED_C1_NEGACYCLIC, "f_pm1")):
+        a, x = W.modp_pair(1024, P1, seed=seed)
+        runs, t0 = 0, time.perf_counter()
+        while time.perf_counter() - t0 < 1.0:
+            O.dense_matvec_modp(a, x, f, P1)
+            runs += 1
+        vals[name] = (time.perf_counter() - t0) / runs
+    out["c1_n1024_latency"] = {"value": round(vals["f1"] * 1e6, 1), "unit": "us per product", "cores": 1, "kind": "oracle",
+                               "f_pm1_us": round(vals["f_pm1"] * 1e6, 1),
+                               "sample": f"dense definition (Definition 2) in numpy int64, n=1024, repeated for 1 s per f; {host}"}
+    # C2: three circulant products + the textbook CRT, full size; then the primes on a pool
+    a, b = W.poly_i32(1 << 20, W.SEED_POLY)
+    nc = (1 << 21) - 1
+    _, dt1 = _timed(lambda: OP.poly_via_circulant(a, b, W.PRIMES))
+    with spawn.Pool(3) as pool:
+        _, dtp = _timed(lambda: OP.crt_textbook(pool.map(_oracle_residues, [(a, b, p) for p in W.PRIMES]), W.PRIMES))
+    out["polymul_i64_2x2^20"] = {"value": nc / dt1 / 1e9, "unit": "Gcoeff/s", "cores": 1, "kind": "oracle",
+                                 "pool": {"value": nc / dtp / 1e9, "cores": 3, "what": "one prime per process, CRT in the parent"},
+                                 "sample": f"one full C2 product (3 level-form products of 2^21 + textbook CRT), {dt1:.1f} s; {host}"}
+    # C3: Python's integer multiply (1 core); the circulant route with its primes on a pool
+    a, b = W.bigint_u16(1 << 20, W.SEED_BIGINT)
+    _, dt1 = _timed(lambda: OB.bigint_mul_pyint(a, b))
+    a64, b64 = a.astype(np.int64), b.astype(np.int64)
+    with spawn.Pool(3) as pool:
+        _, dtp = _timed(lambda: OB.carry_propagate(
+            OP.crt_textbook(pool.map(_oracle_residues, [(a64, b64, p) for p in W.PRIMES]), W.PRIMES), 1 << 21))
+    out["bigint_mul_2x2^24bit"] = {"value": (1 << 21) / dt1 / 1e9, "unit": "Glimb/s", "cores": 1, "kind": "oracle",
+                                   "pool": {"value": (1 << 21) / dtp / 1e9, "cores": 3,
+                                            "what": "circulant route: one prime per process, CRT and carries in the parent"},
+                                   "sample": f"one full C3 product by Python int multiply, {dt1:.1f} s; {host}"}
+    # C4: a seeded sample of 512 of the 4096 instances (all sizes), 1 core and a pool
+    e, a_list, x_list = W.batched_c64(4096, W.SEED_BATCHED)
+    pick = np.random.default_rng(0).choice(len(a_list), 512, replace=False)
+    work = [(a_list[k], x_list[k]) for k in pick]
+    coefs = sum(int(a.shape[0]) for a, _ in work)
+    _, dt1 = _timed(lambda: [_oracle_c128(w) for w in work])
+    with spawn.Pool(cores) as pool:
+        pool.map(_oracle_c128, work[:cores])  # workers started and warm
+        _, dtp = _timed(lambda: pool.map(_oracle_c128, work, chunksize=4))
+    out["batched_c64_4096"] = {"value": coefs / dt1 / 1e9, "unit": "Gcoeff/s", "cores": 1, "kind": "oracle",
+                               "pool": {"value": coefs / dtp / 1e9, "cores": cores, "what": "instances over a process pool"},
+                               "sample": f"512 of the 4096 instances (seeded choice, {coefs} coefficients), complex128 level form; {host}"}
+    # C5: forward and backward of 16 of the 256 rows (one product each for y, grad_x, grad_a)
+    ra, rx, rg = W.circ_layer_f32()
+    n = ra.shape[0]
+    rev = ra[(-np.arange(n)) % n]
+    rows = 16
+
+    def layer_rows():
+        for b in range(rows):
+            O.levels_matvec_c128(ra.astype(np.complex128), rx[b].astype(np.complex128))
+            O.levels_matvec_c128(rev.astype(np.complex128), rg[b].astype(np.complex128))
+            O.levels_matvec_c128(rg[b].astype(np.complex128), rx[b].astype(np.complex128))
+    _, dt1 = _timed(layer_rows)
+    out["layer_fwd_bwd_256x2^14"] = {"value": dt1 * 256 / rows * 1e3, "unit": "ms per forward+backward (256 rows)",
+                                     "cores": 1, "kind": "oracle",
+                                     "sample": f"{rows} of 256 rows, 3 complex128 level-form products each, scaled to 256; {host}"}
+    return out
 
 
 def cpu_baseline(W, budget_s: float = 15.0):
@@ -322,9 +483,12 @@ def main():
               "(multi-GPU sharding is a design note, not built). Use --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
+    from paper_2103_02605_amd import workloads as W
+    # the pooled oracle runs start worker processes: do them before the GPU is touched
+    sec_cpu = cpu_baselines_secondary(W) if not (args.no_cpu_baseline or args.no_secondary) else {}
+
     import torch
     from paper_2103_02605_amd import fcirc as F
-    from paper_2103_02605_amd import workloads as W
 
     torch.cuda.set_device(0)
     if args.calib_copy:
@@ -352,12 +516,16 @@ def main():
     digest = source_digest()
     dk = kern[dom]
     traffic = read_traffic(dom, digest)
+    hbm_frac = round(12 * n / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
     roofline = {"bound": "alu", "kernel": dom, "achieved": round(dk["alu_Tops"], 3), "peak": round(VALU_PEAK_TOPS, 2),
                 "unit": "Tops/s (32-bit VALU lane-ops)", "frac": round(dk["alu_Tops"] / VALU_PEAK_TOPS, 4),
+                "hbm_frac": hbm_frac,
+                "hbm_frac_is": "the metric's % HBM roofline: 12 compulsory bytes per coefficient over the whole "
+                               "step (all kernels) against 8 TB/s",
                 "traffic": traffic,
                 "per_unit": f"{ops_coef[dom]} lane-ops per coefficient x {n} coefficients per launch",
                 "hbm": {"achieved_GBs": round(12 * n / (ms * 1e-3) / 1e9, 1), "peak_GBs": HBM_PEAK_GBS,
-                        "frac": round(12 * n / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                        "frac": hbm_frac,
                         "copy_ceiling_GBs": round(copy_gbs, 1),
                         "per_unit": "12 compulsory bytes per coefficient (a, x read, y written), whole step"},
                 "kernels": {k: {kk: round(vv, 3) for kk, vv in v.items()} for k, v in kern.items()},
@@ -372,6 +540,8 @@ def main():
             "roofline": roofline}
     if not args.no_secondary:
         line["secondary"] = secondary(torch, F, W, quick=args.quick_secondary)
+        for row, cb in sec_cpu.items():
+            line["secondary"][row]["cpu_baseline"] = cb
     if not args.no_cpu_baseline:
         cb = cpu_baseline(W)
         line["cpu_baseline"] = cb

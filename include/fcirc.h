@@ -55,7 +55,10 @@ typedef enum {
   FCIRC_ERANGE = 4,  /* a product coefficient fell outside the exactly representable range
                         (reported by fcirc_check after the work has run)                  */
   FCIRC_ENOMEM = 5,  /* device allocation failed or exceeded FCIRC_WORKSPACE_LIMIT        */
-  FCIRC_EDEVICE = 6  /* no usable gfx950 device, or a HIP call failed                     */
+  FCIRC_EDEVICE = 6, /* no usable gfx950 device, or a HIP call failed                     */
+  FCIRC_ESCHED = 7   /* fcirc_matvec_batched: a work item gave up waiting (bounded spin) for
+                        the items it depends on; the outputs of that launch are unspecified
+                        (reported by fcirc_check after the work has run)                  */
 } fcirc_status;
 
 /* Create a context on HIP device `hip_device` (must be gfx950). */
@@ -213,7 +216,9 @@ fcirc_status fcirc_matvec_backward(fcirc_ctx *ctx, const void *a, const void *x,
                                    void *ga, void *gx, uint64_t n, uint32_t batch,
                                    fcirc_ring ring, void *stream);
 
-/* Synchronise `stream` and return (then clear) the sticky device status (ERANGE). */
+/* Synchronise `stream` and return (then clear) the sticky device status: ESCHED if a
+ * batched launch gave up a dependency wait since the last check, else ERANGE if a CRT
+ * result was out of range, else OK. */
 fcirc_status fcirc_check(fcirc_ctx *ctx, void *stream);
 
 /*

@@ -16,7 +16,7 @@ FCIRC_C64 = 3
 FCIRC_R32 = 4
 FCIRC_GFP2 = 5
 
-STATUS = {0: "OK", 1: "EINVAL", 2: "ESIZE", 3: "ENOROOT", 4: "ERANGE", 5: "ENOMEM", 6: "EDEVICE"}
+STATUS = {0: "OK", 1: "EINVAL", 2: "ESIZE", 3: "ENOROOT", 4: "ERANGE", 5: "ENOMEM", 6: "EDEVICE", 7: "ESCHED"}
 
 
 class fcirc_item(C.Structure):

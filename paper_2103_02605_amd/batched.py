@@ -65,14 +65,25 @@ class BatchPlan:
         self.a.copy_(self._pack(a_list))
         self.x.copy_(self._pack(x_list))
 
-    def run(self, stream=None):
+    def run(self, stream=None, check: bool = False):
+        """Enqueue the batch. With check=True, also wait for it and raise FcircError (ESCHED)
+        if a work item gave up waiting for the items it depends on (see check())."""
         ctx = context(self.a.device)
         with ctx.enqueue(stream) as s:
             L.check(L.lib().fcirc_matvec_batched(ctx.handle, C.c_void_p(self.a.data_ptr()), C.c_void_p(self.x.data_ptr()),
                                                  C.c_void_p(self.y.data_ptr()), self.items, len(self.sizes),
                                                  C.byref(self.f), self.ring, s),
                     "fcirc_matvec_batched")
+        if check:
+            self.check(stream)
         return self.y
+
+    def check(self, stream=None):
+        """Synchronise and raise FcircError if the device status of the context reports a
+        failure (ESCHED: a dependency wait of a batched launch gave up)."""
+        ctx = context(self.a.device)
+        with ctx.enqueue(stream) as s:
+            L.check(L.lib().fcirc_check(ctx.handle, s), "fcirc_check")
 
     def outputs(self):
         """Per-instance results as host numpy arrays."""
@@ -84,11 +95,11 @@ class BatchPlan:
 
 def matvec_batched_c64(a_list, x_list, f=None):
     plan = BatchPlan(a_list, x_list, dtype=np.complex64, f=f)
-    plan.run()
+    plan.run(check=True)
     return plan.outputs()
 
 
 def matvec_batched_modp(a_list, x_list, p: int, f=1):
     plan = BatchPlan(a_list, x_list, p=p, f=f)
-    plan.run()
+    plan.run(check=True)
     return plan.outputs()

@@ -148,6 +148,7 @@ const char* fcirc_strerror(fcirc_status s) {
     case FCIRC_ERANGE: return "a result coefficient is outside the exactly representable range";
     case FCIRC_ENOMEM: return "device memory allocation failed or exceeded the workspace limit";
     case FCIRC_EDEVICE: return "no usable gfx950 device, or a HIP call failed";
+    case FCIRC_ESCHED: return "a batched launch gave up waiting for an earlier work item; its outputs are unspecified";
   }
   return "unknown status";
 }
@@ -338,7 +339,8 @@ fcirc_status fcirc_check(fcirc_ctx* ctx, void* stream) {
   if (hipMemcpy(&st, ctx->c.d_status, sizeof st, hipMemcpyDeviceToHost) != hipSuccess) return FCIRC_EDEVICE;
   if (st) {
     if (hipMemset(ctx->c.d_status, 0, sizeof(uint32_t)) != hipSuccess) return FCIRC_EDEVICE;
-    return FCIRC_ERANGE;
+    // a scheduling failure makes every output of its launch unspecified: report it first
+    return (st & FCIRC_STATUS_SCHED) ? FCIRC_ESCHED : FCIRC_ERANGE;
   }
   return FCIRC_OK;
 }

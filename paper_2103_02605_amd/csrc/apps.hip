@@ -86,7 +86,7 @@ __global__ void k_crt_i64(const uint32_t* __restrict__ res, uint64_t N, uint64_t
     v = (int64_t)c - (int64_t)((uint64_t)Q1 * Q2);
   } else {
     v = 0;
-    atomicOr(status, 1u);
+    atomicOr(status, FCIRC_STATUS_RANGE);
   }
   out[k] = v;
 }
@@ -100,7 +100,7 @@ __global__ void k_crt_u64(const uint32_t* __restrict__ res, uint64_t N, uint64_t
   const uint32_t v3 = garner(res[k], res[N + k], res[2 * N + k], K, &c);
   if (v3 != 0) {
     c = 0;
-    atomicOr(status, 1u);
+    atomicOr(status, FCIRC_STATUS_RANGE);
   }
   out[k] = c;
 }

@@ -144,18 +144,23 @@ struct InstIn {
 // Counters: every thread waits for its own (coherent) stores, the workgroup meets, then one
 // thread publishes with a relaxed agent-scope add. A waiter polls with relaxed loads; the
 // workgroup barrier after the poll orders the item's loads after it.
-__device__ __forceinline__ void wait_count(uint32_t* c, uint32_t target, uint32_t* status) {
+// Returns false (for every thread of the workgroup) when the wait gave up; the item is then
+// skipped and the launch's status gets FCIRC_STATUS_SCHED.
+__device__ __forceinline__ bool wait_count(uint32_t* c, uint32_t target, uint32_t* status, uint32_t* s_ok) {
   if (threadIdx.x == 0) {
-    uint32_t spins = 0;
+    uint32_t spins = 0, ok = 1;
     while (__hip_atomic_load(c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
       __builtin_amdgcn_s_sleep(2);
       if (++spins > SPIN_LIMIT) {
-        atomicOr(status, 2u);
+        atomicOr(status, FCIRC_STATUS_SCHED);
+        ok = 0;
         break;
       }
     }
+    *s_ok = ok;
   }
   __syncthreads();
+  return *s_ok != 0;
 }
 
 __device__ __forceinline__ void signal_done(uint32_t* c) {
@@ -256,7 +261,7 @@ __device__ __forceinline__ void do_block(const BatchArgs<Ring>& B, const BItem& 
 template <class Ring>
 __global__ void __launch_bounds__(BT) k_batched(BatchArgs<Ring> B) {
   extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ uint32_t s_item;
+  __shared__ uint32_t s_item, s_ok;
   for (;;) {
     if (threadIdx.x == 0) s_item = atomicAdd(B.head, 1u);
     __syncthreads();
@@ -288,11 +293,11 @@ __global__ void __launch_bounds__(BT) k_batched(BatchArgs<Ring> B) {
       signal_done(&B.cnt[2 * B.insts[it.inst].big]);
     } else if (it.type == IT_BLOCK) {
       const uint32_t tiles = 1u << (it.L - TILE_LOG);
-      wait_count(&B.cnt[2 * B.insts[it.inst].big], 2 * tiles, B.status);
-      do_block<Ring>(B, it, tid, smem);
+      // after a failed wait the item is skipped but still counted, so that its dependents
+      // do not wait out their own bound as well
+      if (wait_count(&B.cnt[2 * B.insts[it.inst].big], 2 * tiles, B.status, &s_ok)) do_block<Ring>(B, it, tid, smem);
       signal_done(&B.cnt[2 * B.insts[it.inst].big + 1]);
-    } else {
-      wait_count(&B.cnt[2 * B.insts[it.inst].big + 1], 1u << (it.L - BLOCK_LOG), B.status);
+    } else if (wait_count(&B.cnt[2 * B.insts[it.inst].big + 1], 1u << (it.L - BLOCK_LOG), B.status, &s_ok)) {
       switch (it.L - BLOCK_LOG) {
         case 1: do_merge<Ring, 1>(B, it, tid, smem); break;
         case 2: do_merge<Ring, 2>(B, it, tid, smem); break;
@@ -313,11 +318,20 @@ __global__ void k_zero(uint32_t* p, uint32_t n) {
 
 // One cached batched launch: the device item queue and instance table built for one item
 // list, and the two launches (counter reset, persistent kernel) with their arguments.
+// The twiddle tables are not part of the entry: a later product with the same f may
+// rebuild them with more levels (and free the old ones), so every run takes the tables the
+// context holds at that moment.
+struct BatchTables {
+  const void* tw;
+  const void* twi;
+  const void* U;
+};
+
 struct BatchEntry {
   std::vector<uint64_t> key;
   void* dev = nullptr;  // items | insts | counters
   void* ws = nullptr;
-  std::function<void(hipStream_t)> run;
+  std::function<void(hipStream_t, const BatchTables&)> run;
   ~BatchEntry() {
     if (dev) (void)hipFree(dev);
     if (ws) (void)hipFree(ws);
@@ -331,19 +345,43 @@ void release_batches(Ctx& c) {
 
 namespace {
 
+// At most this many item lists keep their queue and workspace; the least recently used
+// one is dropped (after the device has finished with it) when another is added.
+constexpr size_t MAX_BATCH_ENTRIES = 16;
+
+fcirc_status evict_batches(Ctx& c) {
+  if (c.batches.size() < MAX_BATCH_ENTRIES) return FCIRC_OK;
+  if (hipDeviceSynchronize() != hipSuccess) return FCIRC_EDEVICE;
+  while (c.batches.size() >= MAX_BATCH_ENTRIES) {
+    delete c.batches.front();
+    c.batches.erase(c.batches.begin());
+  }
+  return FCIRC_OK;
+}
+
+}  // namespace
+
+namespace {
+
 template <class Ring>
 fcirc_status build_and_launch(Ctx& c, const std::vector<uint64_t>& key, const void* a_base, const void* x_base,
                               void* y_base, const fcirc_item* items, uint32_t count, typename Ring::Tw const* tw,
                               typename Ring::Tw const* twi, typename Ring::DeepW const* U,
                               const typename Ring::Params* rp_by_L, hipStream_t s) {
   using T = typename Ring::T;
-  for (BatchEntry* g : c.batches)
-    if (g->key == key)
+  const BatchTables tabs{tw, twi, U};
+  for (size_t i = 0; i < c.batches.size(); ++i)
+    if (c.batches[i]->key == key) {
+      BatchEntry* g = c.batches[i];
+      c.batches.erase(c.batches.begin() + i);  // most recently used last
+      c.batches.push_back(g);
       return hip_status(launch(c, "fcirc_batched", s, [&](hipEvent_t e0_, hipEvent_t e1_) {
         if (e0_) (void)hipEventRecord(e0_, s);
-        g->run(s);
+        g->run(s, tabs);
         if (e1_) (void)hipEventRecord(e1_, s);
       }));
+    }
+  if (fcirc_status st = evict_batches(c); st != FCIRC_OK) return st;
 
   // instances sorted by size, largest first
   std::vector<uint32_t> order(count);
@@ -434,14 +472,18 @@ fcirc_status build_and_launch(Ctx& c, const std::vector<uint64_t>& key, const vo
   const uint32_t grid = (uint32_t)std::min<size_t>((size_t)per_cu * c.prop.multiProcessorCount, q.size());
 
   const uint32_t* head = B.head;
-  g->run = [B, kb, grid, lds, head, ncnt](hipStream_t st) {
+  g->run = [B, kb, grid, lds, head, ncnt](hipStream_t st, const BatchTables& t) {
+    BatchArgs<Ring> Bt = B;
+    Bt.tw = static_cast<typename Ring::Tw const*>(t.tw);
+    Bt.twi = static_cast<typename Ring::Tw const*>(t.twi);
+    Bt.U = static_cast<typename Ring::DeepW const*>(t.U);
     hipLaunchKernelGGL(k_zero, dim3(1), dim3(256), 0, st, const_cast<uint32_t*>(head), ncnt);
-    hipLaunchKernelGGL(kb, dim3(grid), dim3(BT), lds, st, B);
+    hipLaunchKernelGGL(kb, dim3(grid), dim3(BT), lds, st, Bt);
   };
   c.batches.push_back(g);
   return hip_status(launch(c, "fcirc_batched", s, [&](hipEvent_t e0_, hipEvent_t e1_) {
     if (e0_) (void)hipEventRecord(e0_, s);
-    g->run(s);
+    g->run(s, tabs);
     if (e1_) (void)hipEventRecord(e1_, s);
   }));
 }

@@ -136,6 +136,10 @@ struct TuneVal {
   int flags = 1;      // FCIRC_SCHED_* bits
 };
 
+// Bits of the sticky device status word (Ctx::d_status[0]), reported by fcirc_check.
+constexpr uint32_t FCIRC_STATUS_RANGE = 1u;  // a CRT result fell outside the exact range (ERANGE)
+constexpr uint32_t FCIRC_STATUS_SCHED = 2u;  // a batched launch's dependency wait gave up (ESCHED)
+
 struct BatchEntry;  // cached batched launches: device item queue and kernel arguments (batched.hip)
 
 struct Ctx {

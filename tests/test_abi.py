@@ -41,8 +41,8 @@ def test_library_exports_every_declared_symbol(lib):
 
 
 def test_strerror(lib):
-    for code in range(7):
-        assert lib.fcirc_strerror(code)
+    for code in range(8):
+        assert b"unknown" not in lib.fcirc_strerror(code), code
     assert b"unknown" in lib.fcirc_strerror(99)
 
 

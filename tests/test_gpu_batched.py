@@ -106,3 +106,54 @@ def test_c4_config_all_instances(B):
         want = O.cyclic_matvec_fft_c128(a_list[k].astype(np.complex128), x_list[k].astype(np.complex128))
         worst = max(worst, rel_l2(ys[k], want))
     assert worst <= TOL, worst
+
+
+def test_tables_rebuilt_between_runs(B):
+    """A reused batched launch takes the twiddle tables the context holds at each run: a
+    larger single product with the same f in between rebuilds them (the old ones are
+    freed), and the next run of the same item list must still be exact."""
+    import torch
+    from paper_2103_02605_amd import fcirc as F
+    p = W.P1
+    f = pow(12345, 1 << 23, p)  # has 2^23-th roots; used by no other test
+    logs = [5, 12, 13, 16, 16, 9]
+    inst = [W.modp_pair(1 << L, p, seed=300 + k) for k, L in enumerate(logs)]
+    want = [O.levels_matvec_modp(a, x, f, p) for a, x in inst]
+    plan = B.BatchPlan([a for a, _ in inst], [x for _, x in inst], p=p, f=f)
+    plan.run(check=True)
+    for k, y in enumerate(plan.outputs()):
+        np.testing.assert_array_equal(y, want[k], err_msg=f"first run, instance {k}")
+    a, x = W.modp_pair(1 << 21, p, seed=301)
+    F.matvec(torch.from_numpy(a.view(np.int32)).cuda(), torch.from_numpy(x.view(np.int32)).cuda(), f=f, p=p)
+    plan.y.zero_()
+    plan.run(check=True)
+    for k, y in enumerate(plan.outputs()):
+        np.testing.assert_array_equal(y, want[k], err_msg=f"run after the tables grew, instance {k}")
+    # the same for the complex ring (tables computed on the GPU)
+    fc = np.exp(0.37j)
+    cinst = [W.complex_pair(1 << L, seed=400 + k) for k, L in enumerate(logs)]
+    cwant = [O.levels_matvec_c128(a.astype(np.complex128), x.astype(np.complex128), fc) for a, x in cinst]
+    cplan = B.BatchPlan([a for a, _ in cinst], [x for _, x in cinst], dtype=np.complex64, f=fc)
+    cplan.run(check=True)
+    a, x = W.complex_pair(1 << 21, seed=401)
+    F.matvec(torch.from_numpy(a).cuda(), torch.from_numpy(x).cuda(), f=fc)
+    cplan.y.zero_()
+    cplan.run(check=True)
+    for k, y in enumerate(cplan.outputs()):
+        assert rel_l2(y, cwant[k]) <= TOL, k
+
+
+def test_many_item_lists_bounded(B):
+    """More distinct item lists than the context keeps: older queues are dropped and
+    rebuilt on demand, results stay exact."""
+    p = W.P3
+    plans = []
+    for k in range(20):
+        logs = [4 + (k % 9), 13]
+        inst = [W.modp_pair(1 << L, p, seed=500 + 10 * k + j) for j, L in enumerate(logs)]
+        plans.append((B.BatchPlan([a for a, _ in inst], [x for _, x in inst], p=p, f=1), inst))
+    for rep in range(2):
+        for plan, inst in plans:
+            plan.run(check=True)
+            for j, y in enumerate(plan.outputs()):
+                np.testing.assert_array_equal(y, O.levels_matvec_modp(inst[j][0], inst[j][1], 1, p))
