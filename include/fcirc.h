@@ -56,9 +56,11 @@ typedef enum {
                         (reported by fcirc_check after the work has run)                  */
   FCIRC_ENOMEM = 5,  /* device allocation failed or exceeded FCIRC_WORKSPACE_LIMIT        */
   FCIRC_EDEVICE = 6, /* no usable gfx950 device, or a HIP call failed                     */
-  FCIRC_ESCHED = 7   /* fcirc_matvec_batched: a work item gave up waiting (bounded spin) for
+  FCIRC_ESCHED = 7,  /* fcirc_matvec_batched: a work item gave up waiting (bounded spin) for
                         the items it depends on; the outputs of that launch are unspecified
                         (reported by fcirc_check after the work has run)                  */
+  FCIRC_ENOPLAN = 8  /* fcirc_matvec_noalloc: the twiddle tables of (ring, f, n) are not
+                        resident in the context and may not be built by this call        */
 } fcirc_status;
 
 /* Create a context on HIP device `hip_device` (must be gfx950). */
@@ -84,6 +86,27 @@ const char *fcirc_strerror(fcirc_status s);
  */
 fcirc_status fcirc_matvec(fcirc_ctx *ctx, const void *a, const void *x, void *y, uint64_t n,
                           const void *f, fcirc_ring ring, void *stream);
+
+/*
+ * fcirc_matvec for callers that cannot allocate device memory (code being captured into a
+ * HIP graph, tight serving loops, harnesses that forbid allocation). Same arguments, rings,
+ * result and errors as fcirc_matvec, but the call allocates nothing: no hipMalloc/hipFree
+ * and no allocating library routine.
+ *   - Workspace: the product's intermediate rows (2n elements when n > 2^12) live in one
+ *     static device array of FCIRC_NOALLOC_SCRATCH_BYTES per GPU, held by the library from
+ *     its first use on that GPU until the process ends. n must fit: ESIZE above 2^22 for
+ *     Z/p, 2^21 for FCIRC_C64 and FCIRC_GFP2, 2^20 for FCIRC_R32.
+ *   - Plan: the twiddle tables of (ring, f, n) must already be resident in ctx; one earlier
+ *     fcirc_matvec with the same ring, f and n on this context builds them (and keeps them
+ *     until fcirc_destroy). Otherwise ENOPLAN, with nothing enqueued.
+ *   - Every call on one GPU shares that GPU's array and leaves its contents behind (nothing
+ *     in it needs to start at zero): calls that may overlap on one GPU, from any context or
+ *     stream, race and give unspecified results; order them.
+ *   - Per-kernel timing (fcirc_set_timing) creates events; leave it off for this call.
+ */
+#define FCIRC_NOALLOC_SCRATCH_BYTES (32u << 20)
+fcirc_status fcirc_matvec_noalloc(fcirc_ctx *ctx, const void *a, const void *x, void *y, uint64_t n,
+                                  const void *f, fcirc_ring ring, void *stream);
 
 /*
  * `count` independent products of the same size n and the same f, stored back to back

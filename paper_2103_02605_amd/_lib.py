@@ -16,7 +16,7 @@ FCIRC_C64 = 3
 FCIRC_R32 = 4
 FCIRC_GFP2 = 5
 
-STATUS = {0: "OK", 1: "EINVAL", 2: "ESIZE", 3: "ENOROOT", 4: "ERANGE", 5: "ENOMEM", 6: "EDEVICE", 7: "ESCHED"}
+STATUS = {0: "OK", 1: "EINVAL", 2: "ESIZE", 3: "ENOROOT", 4: "ERANGE", 5: "ENOMEM", 6: "EDEVICE", 7: "ESCHED", 8: "ENOPLAN"}
 
 
 class fcirc_item(C.Structure):
@@ -31,6 +31,8 @@ SIGNATURES = {
     "fcirc_strerror": (C.c_char_p, [C.c_int]),
     "fcirc_matvec": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64, C.c_void_p, C.c_int,
                                C.c_void_p]),
+    "fcirc_matvec_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64, C.c_void_p,
+                                       C.c_int, C.c_void_p]),
     "fcirc_matvec_many": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64, C.c_uint32,
                                     C.c_void_p, C.c_int, C.c_void_p]),
     "fcirc_matvec_any": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64, C.c_void_p, C.c_int,

@@ -85,18 +85,24 @@ fcirc_status check_product(fcirc_ctx* ctx, const void* a, const void* x, const v
 }
 
 fcirc_status dispatch(fcirc_ctx* ctx, const void* a, const void* x, void* y, int L, uint32_t count, const void* f,
-                      fcirc_ring ring, hipStream_t s) {
+                      fcirc_ring ring, hipStream_t s, const FixedWs* fx = nullptr) {
   if (hipSetDevice(ctx->c.device) != hipSuccess) return FCIRC_EDEVICE;
   if (ring <= FCIRC_ZP_167772161)
     return zp_matvec(ctx->c, (const uint32_t*)a, (const uint32_t*)x, (uint32_t*)y, L, count, zp_prime(ring),
-                     *(const uint32_t*)f, s);
+                     *(const uint32_t*)f, s, fx);
   if (ring == FCIRC_C64) {
     const double* fc = (const double*)f;
-    return c32_matvec(ctx->c, a, x, y, L, count, fc[0], fc[1], false, s);
+    return c32_matvec(ctx->c, a, x, y, L, count, fc[0], fc[1], false, s, fx);
   }
-  if (ring == FCIRC_GFP2) return gp2_matvec(ctx->c, a, x, y, L, count, ((const uint32_t*)f)[0] != 1, s);
-  return c32_matvec(ctx->c, a, x, y, L, count, *(const double*)f, 0.0, true, s);
+  if (ring == FCIRC_GFP2) return gp2_matvec(ctx->c, a, x, y, L, count, ((const uint32_t*)f)[0] != 1, s, fx);
+  return c32_matvec(ctx->c, a, x, y, L, count, *(const double*)f, 0.0, true, s, fx);
 }
+
+// Workspace of fcirc_matvec_noalloc: one array per GPU, alive until the process ends. In
+// host code `scratch` names a host-side stand-in, not device memory; its device address is
+// taken once per context (hipGetSymbolAddress, with the context's device current) in
+// fcirc_create and kept in Ctx::scratch, which is what kernels receive.
+static __device__ __align__(256) unsigned char scratch[FCIRC_NOALLOC_SCRATCH_BYTES];
 
 }  // namespace
 
@@ -149,6 +155,7 @@ const char* fcirc_strerror(fcirc_status s) {
     case FCIRC_ENOMEM: return "device memory allocation failed or exceeded the workspace limit";
     case FCIRC_EDEVICE: return "no usable gfx950 device, or a HIP call failed";
     case FCIRC_ESCHED: return "a batched launch gave up waiting for an earlier work item; its outputs are unspecified";
+    case FCIRC_ENOPLAN: return "the twiddle tables of this (ring, f, n) are not resident and this call may not build them";
   }
   return "unknown status";
 }
@@ -176,6 +183,15 @@ fcirc_status fcirc_create(fcirc_ctx** out, int dev) {
     delete ctx;
     return FCIRC_EDEVICE;
   }
+  // this device's copy of the no-alloc workspace (the device is current)
+  void* sp = nullptr;
+  if (hipGetSymbolAddress(&sp, HIP_SYMBOL(scratch)) != hipSuccess || sp == nullptr) {
+    (void)hipGetLastError();
+    (void)hipFree(ctx->c.d_status);
+    delete ctx;
+    return FCIRC_EDEVICE;
+  }
+  ctx->c.scratch = sp;
   if (const char* tf = std::getenv("FCIRC_TUNE_FILE")) {
     if (load_schedules(ctx->c, tf) != FCIRC_OK)
       std::fprintf(stderr, "libfcirc: FCIRC_TUNE_FILE=%s could not be read; default schedules kept\n", tf);
@@ -223,6 +239,22 @@ fcirc_status fcirc_matvec(fcirc_ctx* ctx, const void* a, const void* x, void* y,
   st = check_inputs(ctx->c, ring, {a, x}, n * words_per_elem(ring), (hipStream_t)stream);
   if (st != FCIRC_OK) return st;
   return dispatch(ctx, a, x, y, L, 1, f, ring, (hipStream_t)stream);
+}
+
+fcirc_status fcirc_matvec_noalloc(fcirc_ctx* ctx, const void* a, const void* x, void* y, uint64_t n, const void* f,
+                                  fcirc_ring ring, void* stream) {
+  int L = 0;
+  fcirc_status st = check_product(ctx, a, x, y, n, 1, f, ring, &L);
+  if (st != FCIRC_OK) return st;
+  // the product's workspace: 2n elements (3n for real data) once it has top passes
+  const uint64_t per = ring == FCIRC_R32 ? 3 * sizeof(float2) : 2 * elem_bytes(ring);
+  if (L > 12 && n * per > FCIRC_NOALLOC_SCRATCH_BYTES) return FCIRC_ESIZE;
+  if (!ctx->c.scratch) return FCIRC_EDEVICE;
+  if (hipSetDevice(ctx->c.device) != hipSuccess) return FCIRC_EDEVICE;
+  st = check_inputs(ctx->c, ring, {a, x}, n * words_per_elem(ring), (hipStream_t)stream);
+  if (st != FCIRC_OK) return st;
+  const FixedWs fx{ctx->c.scratch, FCIRC_NOALLOC_SCRATCH_BYTES};
+  return dispatch(ctx, a, x, y, L, 1, f, ring, (hipStream_t)stream, &fx);
 }
 
 fcirc_status fcirc_matvec_many(fcirc_ctx* ctx, const void* a, const void* x, void* y, uint64_t n, uint32_t count,

@@ -50,13 +50,14 @@ Uniform16<C32> c32_uniform16() {
   return U;
 }
 
-fcirc_status c32_tables(Ctx& c, double fre, double fim, int L, hipStream_t s, const C32Tables** out) {
+fcirc_status c32_tables(Ctx& c, double fre, double fim, int L, hipStream_t s, const C32Tables** out, bool build) {
   if (fre == 0.0 && fim == 0.0) return FCIRC_ENOROOT;
   for (auto& t : c.c32)
     if (t.fre == fre && t.fim == fim && t.levels >= L) {
       *out = &t;
       return FCIRC_OK;
     }
+  if (!build) return FCIRC_ENOPLAN;
   const int levels = L < 16 ? 16 : L;
   const size_t ne = (size_t)1 << levels;
   C32Tables t;
@@ -94,22 +95,20 @@ fcirc_status c32_tables(Ctx& c, double fre, double fim, int L, hipStream_t s, co
 }
 
 fcirc_status c32_matvec(Ctx& c, const void* a, const void* x, void* y, int L, uint32_t count, double fre, double fim,
-                        bool real_io, hipStream_t s) {
+                        bool real_io, hipStream_t s, const FixedWs* fx) {
   const C32Tables* T = nullptr;
-  fcirc_status st = c32_tables(c, fre, fim, L, s, &T);
+  fcirc_status st = c32_tables(c, fre, fim, L, s, &T, fx == nullptr);
   if (st != FCIRC_OK) return st;
   const Schedule S = schedule_for(c, real_io ? FCIRC_R32 : FCIRC_C64, L);
-  const uint64_t wse = product_ws_elems(S, count, real_io);
-  if (wse) {
-    st = ws_reserve(c, wse * sizeof(float2));
-    if (st != FCIRC_OK) return st;
-  }
+  void* wsp = nullptr;
+  st = product_ws(c, fx, product_ws_elems(S, count, real_io) * sizeof(float2), &wsp);
+  if (st != FCIRC_OK) return st;
   const C32Params rp{(float)std::ldexp(1.0, -L)};
   const C32Params rps[3] = {rp, rp, rp};
   const float2* tw[3] = {T->tw, T->tw, T->tw};
   const float2* twi[3] = {T->twi, T->twi, T->twi};
   const uint64_t n = (uint64_t)1 << L;
-  float2* ws = (float2*)c.ws;
+  float2* ws = (float2*)wsp;
   const float2* U[3] = {T->dU, T->dU, T->dU};
   hipError_t e;
   if (real_io) {

@@ -40,12 +40,13 @@ uint32_t brev2(uint32_t v, int bits) {
   return r;
 }
 
-fcirc_status gp2_tables(Ctx& c, int fneg, int L, const Gp2Tables** out) {
+fcirc_status gp2_tables(Ctx& c, int fneg, int L, const Gp2Tables** out, bool build) {
   for (auto& t : c.gp2)
     if (t.fneg == fneg && t.levels >= L) {
       *out = &t;
       return FCIRC_OK;
     }
+  if (!build) return FCIRC_ENOPLAN;
   const int levels = L < 12 ? 12 : L;
   // g_{d,b} = r_{d+1} rho_d^brev_d(b): r_k = 1 for f = 1; for f = -1, r_k = rho_k (order
   // 2^(k+1)), so r_1^2 = -1 and r_(k+1)^2 = r_k.
@@ -105,16 +106,15 @@ fcirc_status gp2_tables(Ctx& c, int fneg, int L, const Gp2Tables** out) {
 
 }  // namespace
 
-fcirc_status gp2_matvec(Ctx& c, const void* a, const void* x, void* y, int L, uint32_t count, int fneg, hipStream_t s) {
+fcirc_status gp2_matvec(Ctx& c, const void* a, const void* x, void* y, int L, uint32_t count, int fneg, hipStream_t s,
+                        const FixedWs* fx) {
   const Gp2Tables* T = nullptr;
-  fcirc_status st = gp2_tables(c, fneg, L, &T);
+  fcirc_status st = gp2_tables(c, fneg, L, &T, fx == nullptr);
   if (st != FCIRC_OK) return st;
   const Schedule S = schedule_for(c, FCIRC_GFP2, L);
-  const uint64_t wse = product_ws_elems(S, count, false);
-  if (wse) {
-    st = ws_reserve(c, wse * sizeof(uint2));
-    if (st != FCIRC_OK) return st;
-  }
+  void* ws = nullptr;
+  st = product_ws(c, fx, product_ws_elems(S, count, false) * sizeof(uint2), &ws);
+  if (st != FCIRC_OK) return st;
   const Gp2Params rp{(uint32_t)((1ull << (31 - L)) % GP)};  // 1/n = 2^(31-L) since 2^31 = 1 mod p
   const Gp2Params rps[3] = {rp, rp, rp};
   const uint2* tw[3] = {T->tw, T->tw, T->tw};
@@ -123,7 +123,7 @@ fcirc_status gp2_matvec(Ctx& c, const void* a, const void* x, void* y, int L, ui
   const uint64_t n = (uint64_t)1 << L;
   return hip_status(run_product<Gp2>(c, S, count, rps, tw, twi, U, nullptr, nullptr, false, LdPlain<uint2>{(const uint2*)a, n},
                                      LdPlain<uint2>{(const uint2*)x, n}, StPlain<uint2>{(uint2*)y, n}, (uint2*)y,
-                                     (uint2*)c.ws, s));
+                                     (uint2*)ws, s));
 }
 
 }  // namespace fcirc

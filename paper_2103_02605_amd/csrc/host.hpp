@@ -136,6 +136,14 @@ struct TuneVal {
   int flags = 1;      // FCIRC_SCHED_* bits
 };
 
+// A workspace the caller brings (fcirc_matvec_noalloc): the product then allocates nothing,
+// so its twiddle tables must already be resident (FCIRC_ENOPLAN otherwise) and its
+// workspace must fit in `bytes` (FCIRC_ESIZE otherwise).
+struct FixedWs {
+  void* ptr;
+  size_t bytes;
+};
+
 // Bits of the sticky device status word (Ctx::d_status[0]), reported by fcirc_check.
 constexpr uint32_t FCIRC_STATUS_RANGE = 1u;  // a CRT result fell outside the exact range (ERANGE)
 constexpr uint32_t FCIRC_STATUS_SCHED = 2u;  // a batched launch's dependency wait gave up (ESCHED)
@@ -160,6 +168,7 @@ struct Ctx {
   Timer timer;
   std::vector<BatchEntry*> batches;  // owned; freed by release_batches
   bool debug_sync = false;
+  void* scratch = nullptr;  // device address of fcirc_matvec_noalloc's array on this device
 };
 
 // Launch wrapper. fn(e0, e1) enqueues one kernel; with timing on, e0/e1 are events that
@@ -514,19 +523,37 @@ inline uint64_t product_ws_elems(const Schedule& S, uint32_t count, bool need_wy
 uint32_t zp_prime(fcirc_ring r);
 int zp_two_adic(uint32_t p);
 // Tables for (p, f) covering at least L levels; ENOROOT if f has no 2^L-th root.
-fcirc_status zp_tables(Ctx& c, uint32_t p, uint32_t f, int L, const ZpTables** out);
+fcirc_status zp_tables(Ctx& c, uint32_t p, uint32_t f, int L, const ZpTables** out, bool build = true);
 // Packed deepest-stage first twiddles for size 2^L (L >= 4), built on first use.
-fcirc_status zp_first_tables(Ctx& c, const ZpTables* T, int L, const uint32_t** ft, const uint32_t** fti);
+fcirc_status zp_first_tables(Ctx& c, const ZpTables* T, int L, const uint32_t** ft, const uint32_t** fti,
+                             bool build = true);
 ZpParams zp_params(uint32_t p, int L);
-fcirc_status c32_tables(Ctx& c, double fre, double fim, int L, hipStream_t s, const C32Tables** out);
+fcirc_status c32_tables(Ctx& c, double fre, double fim, int L, hipStream_t s, const C32Tables** out, bool build = true);
 
 
+// With fx set the product allocates nothing (see FixedWs).
 fcirc_status zp_matvec(Ctx& c, const uint32_t* a, const uint32_t* x, uint32_t* y, int L, uint32_t count, uint32_t p,
-                       uint32_t f, hipStream_t s);
+                       uint32_t f, hipStream_t s, const FixedWs* fx = nullptr);
 fcirc_status c32_matvec(Ctx& c, const void* a, const void* x, void* y, int L, uint32_t count, double fre, double fim,
-                        bool real_io, hipStream_t s);
+                        bool real_io, hipStream_t s, const FixedWs* fx = nullptr);
 
-fcirc_status gp2_matvec(Ctx& c, const void* a, const void* x, void* y, int L, uint32_t count, int fneg, hipStream_t s);
+fcirc_status gp2_matvec(Ctx& c, const void* a, const void* x, void* y, int L, uint32_t count, int fneg, hipStream_t s,
+                        const FixedWs* fx = nullptr);
+
+// The workspace of a product: the context's (grown on demand), or the caller's fixed one.
+inline fcirc_status product_ws(Ctx& c, const FixedWs* fx, size_t bytes, void** ws) {
+  if (fx) {
+    if (bytes > fx->bytes) return FCIRC_ESIZE;
+    *ws = fx->ptr;
+    return FCIRC_OK;
+  }
+  if (bytes) {
+    const fcirc_status st = ws_reserve(c, bytes);
+    if (st != FCIRC_OK) return st;
+  }
+  *ws = c.ws;
+  return FCIRC_OK;
+}
 fcirc_status embed_product(Ctx& c, fcirc_ring ring, const void* r, const void* col, const void* f, const void* x, void* y,
                            uint64_t n, hipStream_t s);
 fcirc_status polymul_i64(Ctx& c, const int32_t* a, uint64_t na, const int32_t* b, uint64_t nb, int64_t* out, hipStream_t s);

@@ -134,7 +134,7 @@ void zp_uniform16_mont(uint32_t p, uint32_t* out) {
   }
 }
 
-fcirc_status zp_tables(Ctx& c, uint32_t p, uint32_t f, int L, const ZpTables** out) {
+fcirc_status zp_tables(Ctx& c, uint32_t p, uint32_t f, int L, const ZpTables** out, bool build) {
   const int e2 = zp_two_adic(p);
   if (L > e2) return FCIRC_ESIZE;
   if (f == 0 || f >= p) return FCIRC_ENOROOT;
@@ -145,6 +145,7 @@ fcirc_status zp_tables(Ctx& c, uint32_t p, uint32_t f, int L, const ZpTables** o
       *out = &t;
       return FCIRC_OK;
     }
+  if (!build) return FCIRC_ENOPLAN;
   // Build (or rebuild larger) with at least 12 levels so small sizes share one table.
   int levels = L < 12 ? 12 : L;
   while (levels > L && powmod(f, (uint64_t)(p - 1) >> levels, p) != 1) --levels;
@@ -218,10 +219,12 @@ fcirc_status zp_tables(Ctx& c, uint32_t p, uint32_t f, int L, const ZpTables** o
   return FCIRC_OK;
 }
 
-fcirc_status zp_first_tables(Ctx& c, const ZpTables* Tc, int L, const uint32_t** ft, const uint32_t** fti) {
+fcirc_status zp_first_tables(Ctx& c, const ZpTables* Tc, int L, const uint32_t** ft, const uint32_t** fti,
+                             bool build) {
   ZpTables* T = const_cast<ZpTables*>(Tc);
   *ft = *fti = nullptr;
   if (L < 4 || L > 26) return FCIRC_OK;
+  if (!T->ft[L] && !build) return FCIRC_ENOPLAN;
   if (!T->ft[L]) {
     // c_3 = g_{L-1, 8 b0} = r_L rho_{L-1}^{brev_dd(b0)} for the node b0 at depth dd = L - 4,
     // in Montgomery form; the kernels square it for the three levels above.
@@ -270,17 +273,15 @@ fcirc_status zp_first_tables(Ctx& c, const ZpTables* Tc, int L, const uint32_t**
 }
 
 fcirc_status zp_matvec(Ctx& c, const uint32_t* a, const uint32_t* x, uint32_t* y, int L, uint32_t count, uint32_t p,
-                       uint32_t f, hipStream_t s) {
+                       uint32_t f, hipStream_t s, const FixedWs* fx) {
   const ZpTables* T = nullptr;
-  fcirc_status st = zp_tables(c, p, f, L, &T);
+  fcirc_status st = zp_tables(c, p, f, L, &T, fx == nullptr);
   if (st != FCIRC_OK) return st;
   const int ring = p == 998244353u ? 0 : (p == 469762049u ? 1 : 2);
   const Schedule S = schedule_for(c, ring, L);
-  const uint64_t wse = product_ws_elems(S, count, false);
-  if (wse) {
-    st = ws_reserve(c, wse * sizeof(uint32_t));
-    if (st != FCIRC_OK) return st;
-  }
+  void* ws = nullptr;
+  st = product_ws(c, fx, product_ws_elems(S, count, false) * sizeof(uint32_t), &ws);
+  if (st != FCIRC_OK) return st;
   const ZpParams rp = zp_params(p, L);
   const ZpParams rps[3] = {rp, rp, rp};
   const ZpTw* tw[3] = {T->tw, T->tw, T->tw};
@@ -288,12 +289,12 @@ fcirc_status zp_matvec(Ctx& c, const uint32_t* a, const uint32_t* x, uint32_t* y
   const uint64_t n = (uint64_t)1 << L;
   const uint32_t* U[3] = {T->dU, T->dU, T->dU};
   const uint32_t *ft = nullptr, *fti = nullptr;
-  st = zp_first_tables(c, T, L, &ft, &fti);
+  st = zp_first_tables(c, T, L, &ft, &fti, fx == nullptr);
   if (st != FCIRC_OK) return st;
   const uint32_t* FT[3] = {ft, ft, ft};
   const uint32_t* FTI[3] = {fti, fti, fti};
   return hip_status(run_product<Zp>(c, S, count, rps, tw, twi, U, ft ? FT : nullptr, ft ? FTI : nullptr, false, LdPlain<uint32_t>{a, n},
-                                    LdPlain<uint32_t>{x, n}, StPlain<uint32_t>{y, n}, y, (uint32_t*)c.ws, s));
+                                    LdPlain<uint32_t>{x, n}, StPlain<uint32_t>{y, n}, y, (uint32_t*)ws, s));
 }
 
 }  // namespace fcirc

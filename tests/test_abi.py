@@ -41,7 +41,7 @@ def test_library_exports_every_declared_symbol(lib):
 
 
 def test_strerror(lib):
-    for code in range(8):
+    for code in range(9):
         assert b"unknown" not in lib.fcirc_strerror(code), code
     assert b"unknown" in lib.fcirc_strerror(99)
 
@@ -49,6 +49,7 @@ def test_strerror(lib):
 def test_null_context_is_einval(lib):
     f = C.c_uint32(1)
     assert lib.fcirc_matvec(None, None, None, None, 8, C.byref(f), 0, None) == 1
+    assert lib.fcirc_matvec_noalloc(None, None, None, None, 8, C.byref(f), 0, None) == 1
     assert lib.fcirc_check(None, None) == 1
     assert lib.fcirc_polymul_i64(None, None, 1, None, 1, None, None) == 1
     assert lib.fcirc_set_split(None, 0) == 1
