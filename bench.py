@@ -298,10 +298,20 @@ def batched_vs_plain(torch, F, W, quick: bool):
     """4096 complex64 products of sizes 2^6..2^16 (seed 6): one persistent launch (its work
     queue reused) against one fcirc_matvec call per instance, on the same device buffers."""
     from paper_2103_02605_amd.batched import BatchPlan
+    from paper_2103_02605_amd import _lib
     e, a_list, x_list = W.batched_c64(4096, W.SEED_BATCHED)
     plan = BatchPlan(a_list, x_list, dtype=np.complex64)
     total = int(plan.offsets[-1])
+    ms_default = time_steps(torch, lambda i: plan.run(), 5 if quick else 20, 2)
+    # the launch's parameters per instance size picked by the autotuner (fcirc_tune), then
+    # the timed runs of the same batch
+    t0 = time.perf_counter()
+    for L in range(int(min(e)), int(max(e)) + 1):
+        F.tune(1 << L, _lib.FCIRC_C64)
+    tune_s = time.perf_counter() - t0
+    params = {f"2^{L}": F.get_batch_schedule(1 << L, _lib.FCIRC_C64) for L in range(int(min(e)), int(max(e)) + 1)}
     ms_b = time_steps(torch, lambda i: plan.run(), 5 if quick else 20, 2)
+    plan.check()
     views = [(plan.a[plan.offsets[k]:plan.offsets[k + 1]], plan.x[plan.offsets[k]:plan.offsets[k + 1]],
               plan.y[plan.offsets[k]:plan.offsets[k + 1]]) for k in range(len(a_list))]
 
@@ -312,7 +322,8 @@ def batched_vs_plain(torch, F, W, quick: bool):
     ops = sum(3 * FP32_OPS_PER_COEF_LEVEL_TRANSFORM * int(L) * (1 << int(L)) for L in e)
     return {"coefficients": total, "batched_ms": ms_b, "plain_ms": ms_p,
             "batched_Gcoeff_per_s": total / ms_b / 1e6, "plain_Gcoeff_per_s": total / ms_p / 1e6,
-            "batched_over_plain": ms_p / ms_b, **fractions(24 * total, ops, ms_b)}
+            "batched_over_plain": ms_p / ms_b, "batched_ms_default_parameters": ms_default,
+            "tuned_parameters": params, "tuning_s": round(tune_s, 2), **fractions(24 * total, ops, ms_b)}
 
 
 def layer_vs_plain(torch, F, W, quick: bool):

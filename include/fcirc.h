@@ -224,6 +224,28 @@ fcirc_status fcirc_matvec_batched(fcirc_ctx *ctx, const void *a_base, const void
                                   const void *f, fcirc_ring ring, void *stream);
 
 /*
+ * Parameters of fcirc_matvec_batched for its instances of size n (a power of two <= 2^16)
+ * over `ring` (the three primes or FCIRC_C64), as fcirc_tune sets them.
+ *   workgroup    : 256 or 512 threads (16 elements per thread per stage); -1 drops the
+ *                  setting of this size (back to the defaults).
+ *   block_levels : 0 = each instance is one work item (split, leaf products and merge in
+ *                  one workgroup; n <= 2^12 at 256 threads, n <= 2^13 at 512), or the levels
+ *                  of the LDS-resident block of the three-pass form (10 .. 12 at 256 threads,
+ *                  10 .. 13 at 512; n >= 2^12 resp. 2^13 and at most 6 levels above the block).
+ * A launch uses 512 threads when the sizes in it whose times fcirc_tune measured (or that
+ * this call set: the given workgroup size counts as the faster) favour it, weighted by
+ * their coefficients; each size then takes its parameters for that workgroup size, and a
+ * size without them the default (one item up to n = 2^12, resp. 2^13, else blocks of 2^12).
+ * Defaults without any setting: 256 threads. EINVAL for other values.
+ * fcirc_get_batch_schedule reports what a launch of instances of size n alone would use;
+ * it returns 0, or -1 for invalid arguments.
+ */
+fcirc_status fcirc_set_batch_schedule(fcirc_ctx *ctx, fcirc_ring ring, uint64_t n, int workgroup,
+                                      int block_levels);
+int fcirc_get_batch_schedule(fcirc_ctx *ctx, fcirc_ring ring, uint64_t n, int *workgroup,
+                             int *block_levels);
+
+/*
  * Circulant layer over a batch with one shared row (f = 1; rings C64 or R32; 16 <= n <= 2^24):
  *   forward : y[b] = C(a) x[b] for b < batch (x, y: batch*n elements, row-major).
  *   backward: gx[b] = C(a)^H gy[b] and ga = sum_b C(gy[b]) conj(x[b]), i.e. the
@@ -275,6 +297,11 @@ int fcirc_stage_times(fcirc_ctx *ctx, const char **names, uint64_t *launches, do
 /*
  * Tuning. fcirc_tune times the candidate split points and tile shapes for one
  * (ring, n) on scratch buffers and keeps the fastest for later calls with this context.
+ * For the three primes and FCIRC_C64 with n <= 2^16 it also tunes fcirc_matvec_batched for
+ * instances of size n (see fcirc_set_batch_schedule): on a scratch batch of
+ * max(1, 2^24 / n) such instances (at most 4096) it times every valid form at both
+ * workgroup sizes and keeps, per workgroup size, the fastest form and its time per
+ * coefficient.
  * fcirc_set_split forces the number of top levels streamed through HBM before the
  * LDS-resident block (0 = single block kernel when it fits; -1 = back to automatic).
  * fcirc_get_split reports the split that fcirc_matvec would use for (ring, n).
@@ -300,7 +327,11 @@ int fcirc_get_schedule(fcirc_ctx *ctx, fcirc_ring ring, uint64_t n, int *top_lev
 
 /*
  * Schedules chosen by fcirc_tune or fcirc_set_schedule kept in a text file, one line per
- * (ring, n): "<arch> <compute units> <ring> <log2 n> <top_levels> <tile_log> <flags>".
+ * (ring, n): "<arch> <compute units> <ring> <log2 n> <top_levels> <tile_log> <flags>", and
+ * the batched-launch parameters of fcirc_tune or fcirc_set_batch_schedule, one line per
+ * (ring, n): "<arch> <compute units> batch <ring> <log2 n> <block_levels at 256 threads>
+ * <ns per coefficient> <block_levels at 512 threads> <ns per coefficient>" (block levels
+ * -1: not set).
  * fcirc_save_schedules writes every schedule the context holds (replacing the file).
  * fcirc_load_schedules reads such a file and takes the lines written for this device's
  * architecture and compute-unit count (other lines are skipped). A file that cannot be

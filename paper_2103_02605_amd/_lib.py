@@ -49,6 +49,8 @@ SIGNATURES = {
                                           C.c_void_p]),
     "fcirc_matvec_batched": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(fcirc_item),
                                        C.c_uint32, C.c_void_p, C.c_int, C.c_void_p]),
+    "fcirc_set_batch_schedule": (C.c_int, [C.c_void_p, C.c_int, C.c_uint64, C.c_int, C.c_int]),
+    "fcirc_get_batch_schedule": (C.c_int, [C.c_void_p, C.c_int, C.c_uint64, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
     "fcirc_matvec_fwd_shared": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64, C.c_uint32,
                                           C.c_int, C.c_void_p]),
     "fcirc_matvec_backward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,

@@ -150,6 +150,19 @@ constexpr uint32_t FCIRC_STATUS_SCHED = 2u;  // a batched launch's dependency wa
 
 struct BatchEntry;  // cached batched launches: device item queue and kernel arguments (batched.hip)
 
+// Parameters of the batched launch for one (ring, instance size), per workgroup size
+// (index 0: 256 threads, 1: 512): the block levels of the three-pass form of an instance
+// (0: the whole instance is one FULL item; -1: not set, the default applies) and the time
+// per coefficient measured by fcirc_tune (ns; negative: not measured).
+struct BatchTune {
+  int blog[2] = {-1, -1};
+  float ns[2] = {-1.f, -1.f};
+};
+// Parameters forced for one instance size while fcirc_tune times them.
+struct BatchForce {
+  int L, bt, blog;
+};
+
 struct Ctx {
   int device = 0;
   hipDeviceProp_t prop{};
@@ -167,6 +180,8 @@ struct Ctx {
   std::map<TuneKey, TuneVal> tuned;
   Timer timer;
   std::vector<BatchEntry*> batches;  // owned; freed by release_batches
+  std::map<TuneKey, BatchTune> batch_tuned;
+  uint64_t batch_gen = 0;  // bumped whenever batch_tuned changes (cached queues then rebuild)
   bool debug_sync = false;
   void* scratch = nullptr;  // device address of fcirc_matvec_noalloc's array on this device
 };
@@ -417,15 +432,12 @@ inline hipError_t launch_merge(Ctx& c, const PassArgs<Ring>& A, const typename R
 #undef FCIRC_CALL
 }
 
-template <class Ring, class SrcA, class SrcX, class Dst>
-inline hipError_t run_product(Ctx& c, const Schedule& S, uint32_t count, const typename Ring::Params* rp,
-                              typename Ring::Tw const* const* tw, typename Ring::Tw const* const* twi,
-                              typename Ring::DeepW const* const* U, typename Ring::DeepW const* const* FT,
-                              typename Ring::DeepW const* const* FTI, bool ring_per_inst, SrcA srca, SrcX srcx, Dst dst,
-                              typename Ring::T* wy, typename Ring::T* ws, hipStream_t s) {
-  using T = typename Ring::T;
-  const int L = S.L;
-  const uint64_t n = (uint64_t)1 << L;
+// The pass arguments every pass of one product shares (tables, size, instances).
+template <class Ring>
+inline PassArgs<Ring> product_pass_args(const Schedule& S, uint32_t count, typename Ring::Tw const* const* tw,
+                                        typename Ring::Tw const* const* twi, typename Ring::DeepW const* const* U,
+                                        typename Ring::DeepW const* const* FT, typename Ring::DeepW const* const* FTI,
+                                        bool ring_per_inst) {
   PassArgs<Ring> A{};
   for (int r = 0; r < 3; ++r) {
     A.tu[r] = U[r];
@@ -437,10 +449,23 @@ inline hipError_t run_product(Ctx& c, const Schedule& S, uint32_t count, const t
     A.tw[i] = tw[i];
     A.twi[i] = twi[i];
   }
-  A.logn = L;
+  A.logn = S.L;
   A.ninst = count;
   A.ring_per_inst = ring_per_inst ? 1 : 0;
   A.xcd = (S.flags & FCIRC_SCHED_XCD) ? 1 : 0;
+  return A;
+}
+
+template <class Ring, class SrcA, class SrcX, class Dst>
+inline hipError_t run_product(Ctx& c, const Schedule& S, uint32_t count, const typename Ring::Params* rp,
+                              typename Ring::Tw const* const* tw, typename Ring::Tw const* const* twi,
+                              typename Ring::DeepW const* const* U, typename Ring::DeepW const* const* FT,
+                              typename Ring::DeepW const* const* FTI, bool ring_per_inst, SrcA srca, SrcX srcx, Dst dst,
+                              typename Ring::T* wy, typename Ring::T* ws, hipStream_t s) {
+  using T = typename Ring::T;
+  const int L = S.L;
+  const uint64_t n = (uint64_t)1 << L;
+  PassArgs<Ring> A = product_pass_args<Ring>(S, count, tw, twi, U, FT, FTI, ring_per_inst);
   hipError_t e;
   if (S.ntop == 0) {
     A.d0 = 0;
@@ -559,6 +584,13 @@ fcirc_status embed_product(Ctx& c, fcirc_ring ring, const void* r, const void* c
 fcirc_status polymul_i64(Ctx& c, const int32_t* a, uint64_t na, const int32_t* b, uint64_t nb, int64_t* out, hipStream_t s);
 fcirc_status bigint_mul(Ctx& c, const uint16_t* a, uint64_t na, const uint16_t* b, uint64_t nb, uint16_t* out, hipStream_t s);
 void release_batches(Ctx& c);
+// The batched product (fcirc_matvec_batched after validation); `force` overrides one size's
+// parameters (fcirc_tune).
+fcirc_status batched_product(Ctx& c, const void* a_base, const void* x_base, void* y_base, const fcirc_item* items,
+                             uint32_t count, const void* f, fcirc_ring ring, hipStream_t s,
+                             const BatchForce* force = nullptr);
+// Whether (workgroup size bt, block levels blog) is a valid batched form of size 2^L.
+bool batch_param_ok(fcirc_ring ring, int L, int bt, int blog);
 // Limbs of sum_k coef[k] 2^(16 k) (coef[k] < 2^64, k < nc) into out[0, nl); u holds nl and
 // summ 2 carry_blocks(nl) words of scratch.
 uint64_t carry_blocks(uint64_t nl);

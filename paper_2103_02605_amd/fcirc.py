@@ -367,6 +367,26 @@ def get_schedule(n: int, ring: int, device=None) -> dict:
     return {"top_passes": ntop, "top_levels": top.value, "tile_log": tile.value, "flags": flags.value}
 
 
+def set_batch_schedule(n: int, ring: int, workgroup: int, block_levels: int = 0, device=None):
+    """Fix the batched launch's parameters for instances of size n: see
+    fcirc_set_batch_schedule in include/fcirc.h (workgroup -1 drops the setting)."""
+    ctx = context(device)
+    with ctx.lock:
+        L.check(L.lib().fcirc_set_batch_schedule(ctx.handle, ring, n, workgroup, block_levels),
+                "fcirc_set_batch_schedule")
+
+
+def get_batch_schedule(n: int, ring: int, device=None) -> dict:
+    """What a batched launch of instances of size n alone uses: workgroup size and block
+    levels (0: one work item per instance)."""
+    wg, bl = C.c_int(), C.c_int()
+    ctx = context(device)
+    with ctx.lock:
+        if L.lib().fcirc_get_batch_schedule(ctx.handle, ring, n, C.byref(wg), C.byref(bl)) != 0:
+            raise ValueError("invalid ring or size for the batched launch")
+    return {"workgroup": wg.value, "block_levels": bl.value}
+
+
 # -------------------------------------------------------------------------------------
 # Circulant layer (f = 1) with a hand-written backward: fcirc_matvec_fwd_shared and
 # fcirc_matvec_backward. x has shape (batch, n) and a shape (n,), float32 or complex64.

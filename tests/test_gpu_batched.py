@@ -157,3 +157,99 @@ def test_many_item_lists_bounded(B):
             plan.run(check=True)
             for j, y in enumerate(plan.outputs()):
                 np.testing.assert_array_equal(y, O.levels_matvec_modp(inst[j][0], inst[j][1], 1, p))
+
+
+def _ring_of(p):
+    from paper_2103_02605_amd import _lib
+    return {None: _lib.FCIRC_C64, W.P1: _lib.FCIRC_ZP_998244353}[p]
+
+
+@pytest.mark.parametrize("p", [None, W.P1])
+def test_every_batch_form(B, p):
+    """Every form the tuner may pick (workgroup 256 or 512 threads; one item per instance or
+    blocks of 2^10 .. 2^13 elements below 1 .. 6 top levels) gives the product: instances of
+    2^13, 2^14 and 2^16 next to small ones, against the oracle."""
+    from paper_2103_02605_amd import fcirc as F
+    ring = _ring_of(p)
+    small = [5, 9, 12]
+    forms = []
+    for bt in (256, 512):
+        elog = 12 if bt == 256 else 13
+        for L in (13, 14, 16):
+            for blog in (0, 10, 11, 12, 13):
+                full_ok = blog == 0 and L <= elog
+                pass_ok = blog >= 10 and blog <= elog and L > blog and L - blog <= 6 and L >= elog
+                if full_ok or pass_ok:
+                    forms.append((bt, L, blog))
+    inst = {}
+    for L in small + [13, 14, 16]:
+        if p is None:
+            inst[L] = [W.complex_pair(1 << L, seed=700 + 10 * L + k) for k in range(2)]
+        else:
+            inst[L] = [W.modp_pair(1 << L, p, seed=700 + 10 * L + k) for k in range(2)]
+    want = {}
+    for L, pairs in inst.items():
+        if p is None:
+            want[L] = [O.levels_matvec_c128(a.astype(np.complex128), x.astype(np.complex128)) for a, x in pairs]
+        else:
+            want[L] = [O.levels_matvec_modp(a, x, 1, p) for a, x in pairs]
+    try:
+        for bt, L, blog in forms:
+            for Ls in small:
+                F.set_batch_schedule(1 << Ls, ring, bt, 0)
+            F.set_batch_schedule(1 << L, ring, bt, blog)
+            assert F.get_batch_schedule(1 << L, ring) == {"workgroup": bt, "block_levels": blog}
+            sizes = small + [L]
+            a_list = [a for Ls in sizes for a, _ in inst[Ls]]
+            x_list = [x for Ls in sizes for _, x in inst[Ls]]
+            if p is None:
+                ys = B.matvec_batched_c64(a_list, x_list)
+            else:
+                ys = B.matvec_batched_modp(a_list, x_list, p=p, f=1)
+            k = 0
+            for Ls in sizes:
+                for j in range(2):
+                    if p is None:
+                        assert rel_l2(ys[k], want[Ls][j]) <= TOL, (bt, L, blog, Ls, j)
+                    else:
+                        np.testing.assert_array_equal(ys[k], want[Ls][j], err_msg=f"{bt} {L} {blog} {Ls} {j}")
+                    k += 1
+    finally:
+        for Ls in small + [13, 14, 16]:
+            F.set_batch_schedule(1 << Ls, ring, -1)
+
+
+def test_tuned_batch_parameters_saved_and_loaded(B, tmp_path):
+    """fcirc_tune picks the batched launch's form per size; the schedule file keeps it and a
+    load brings it back; a batch run with the tuned forms stays within the bar."""
+    from paper_2103_02605_amd import fcirc as F
+    from paper_2103_02605_amd import _lib
+    ring = _lib.FCIRC_C64
+    sizes = [10, 13, 15]
+    try:
+        for L in sizes:
+            F.tune(1 << L, ring)
+        tuned = {L: F.get_batch_schedule(1 << L, ring) for L in sizes}
+        path = tmp_path / "sched.txt"
+        F.save_schedules(path)
+        text = path.read_text()
+        assert " batch 3 13 " in text
+        for L in sizes:
+            F.set_batch_schedule(1 << L, ring, -1)
+        F.load_schedules(path)
+        assert {L: F.get_batch_schedule(1 << L, ring) for L in sizes} == tuned
+        logs = [10, 13, 15, 13, 10, 15, 7]
+        inst = [W.complex_pair(1 << L, seed=800 + k) for k, L in enumerate(logs)]
+        ys = B.matvec_batched_c64([a for a, _ in inst], [x for _, x in inst])
+        for k, (a, x) in enumerate(inst):
+            want = O.levels_matvec_c128(a.astype(np.complex128), x.astype(np.complex128))
+            assert rel_l2(ys[k], want) <= TOL, k
+        # a malformed batch line is refused and changes nothing
+        bad = tmp_path / "bad.txt"
+        bad.write_text(text + "gfx950 256 batch 3 13 7 0.5 0 0.5\n")
+        with pytest.raises(Exception):
+            F.load_schedules(bad)
+        assert {L: F.get_batch_schedule(1 << L, ring) for L in sizes} == tuned
+    finally:
+        for L in sizes:
+            F.set_batch_schedule(1 << L, ring, -1)
