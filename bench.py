@@ -214,32 +214,44 @@ def c1_latency(torch, F, W):
     return out
 
 
-def secondary(torch, F, W, quick: bool):
+SECONDARY_ROWS = ("polymul", "bigint", "fermat", "c1", "negacyclic", "fft", "gfp2", "batched", "layer")
+
+
+def secondary(torch, F, W, quick: bool, rows=SECONDARY_ROWS, plain: bool = True):
+    """The secondary workloads named in `rows`; plain=False skips the one-call-per-instance
+    comparisons of the batched and layer rows (for profiling runs)."""
     out = {}
-    # C2: exact polynomial product, 2 x 2^20 int32 -> 2^21 - 1 int64
-    a, b = W.poly_i32(1 << 20, W.SEED_POLY)
-    ta, tb = torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda()
-    c = torch.empty((1 << 21) - 1, dtype=torch.int64, device="cuda")
-    ms = time_steps(torch, lambda i: F.polymul_i64(ta, tb, out=c), 20 if quick else 100, 5)
     N, nc = 1 << 21, (1 << 21) - 1
-    out["polymul_i64_2x2^20"] = {"ms": ms, "Gcoeff_per_s": nc / ms / 1e6,
-                                 **fractions(2 * (1 << 20) * 4 + nc * 8,
-                                             3 * ALU_OPS_PER_COEF_ZP(21) * N + OPS_CRT * nc, ms)}
-    # C3: big integers, 2 x 2^24 bits -> 2^21 limbs
-    a, b = W.bigint_u16(1 << 20, W.SEED_BIGINT)
-    ta, tb = torch.from_numpy(a.view(np.int16)).cuda(), torch.from_numpy(b.view(np.int16)).cuda()
-    c = torch.empty(1 << 21, dtype=torch.int16, device="cuda")
-    ms = time_steps(torch, lambda i: F.bigint_mul(ta, tb, out=c), 20 if quick else 100, 5)
-    out["bigint_mul_2x2^24bit"] = {"ms": ms, "Glimb_per_s": N / ms / 1e6,
-                                   **fractions(2 * (1 << 20) * 2 + N * 2,
-                                               3 * ALU_OPS_PER_COEF_ZP(21) * N + (OPS_CRT + OPS_CARRY) * N, ms)}
-    out["bigint_fermat_2x2^24bit"] = bigint_fermat(torch, F, ta, tb, ms, quick)
-    out["c1_n1024_latency"] = c1_latency(torch, F, W)
-    out["headline_negacyclic_f_p-1_2^21"] = negacyclic_headline(torch, F, W, 20 if quick else 200, 10)
-    out["circulant_vs_fft_c64_2^21"] = circulant_vs_fft(torch, F, W, quick)
-    out["gfp2_section3_ring_2^21"] = gfp2_product(torch, F, quick)
-    out["batched_c64_4096"] = batched_vs_plain(torch, F, W, quick)
-    out["layer_fwd_bwd_256x2^14"] = layer_vs_plain(torch, F, W, quick)
+    if "polymul" in rows:  # C2: exact polynomial product, 2 x 2^20 int32 -> 2^21 - 1 int64
+        a, b = W.poly_i32(1 << 20, W.SEED_POLY)
+        ta, tb = torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda()
+        c = torch.empty(nc, dtype=torch.int64, device="cuda")
+        ms = time_steps(torch, lambda i: F.polymul_i64(ta, tb, out=c), 20 if quick else 100, 5)
+        out["polymul_i64_2x2^20"] = {"ms": ms, "Gcoeff_per_s": nc / ms / 1e6,
+                                     **fractions(2 * (1 << 20) * 4 + nc * 8,
+                                                 3 * ALU_OPS_PER_COEF_ZP(21) * N + OPS_CRT * nc, ms)}
+    if "bigint" in rows or "fermat" in rows:  # C3: big integers, 2 x 2^24 bits -> 2^21 limbs
+        a, b = W.bigint_u16(1 << 20, W.SEED_BIGINT)
+        ta, tb = torch.from_numpy(a.view(np.int16)).cuda(), torch.from_numpy(b.view(np.int16)).cuda()
+        c = torch.empty(1 << 21, dtype=torch.int16, device="cuda")
+        ms = time_steps(torch, lambda i: F.bigint_mul(ta, tb, out=c), 20 if quick else 100, 5)
+        out["bigint_mul_2x2^24bit"] = {"ms": ms, "Glimb_per_s": N / ms / 1e6,
+                                       **fractions(2 * (1 << 20) * 2 + N * 2,
+                                                   3 * ALU_OPS_PER_COEF_ZP(21) * N + (OPS_CRT + OPS_CARRY) * N, ms)}
+        if "fermat" in rows:
+            out["bigint_fermat_2x2^24bit"] = bigint_fermat(torch, F, ta, tb, ms, quick)
+    if "c1" in rows:
+        out["c1_n1024_latency"] = c1_latency(torch, F, W)
+    if "negacyclic" in rows:
+        out["headline_negacyclic_f_p-1_2^21"] = negacyclic_headline(torch, F, W, 20 if quick else 200, 10)
+    if "fft" in rows:
+        out["circulant_vs_fft_c64_2^21"] = circulant_vs_fft(torch, F, W, quick)
+    if "gfp2" in rows:
+        out["gfp2_section3_ring_2^21"] = gfp2_product(torch, F, quick)
+    if "batched" in rows:
+        out["batched_c64_4096"] = batched_vs_plain(torch, F, W, quick, plain)
+    if "layer" in rows:
+        out["layer_fwd_bwd_256x2^14"] = layer_vs_plain(torch, F, W, quick, plain)
     return out
 
 
@@ -294,7 +306,7 @@ def gfp2_product(torch, F, quick: bool):
     return {"ms": ms, "Gcoeff_per_s": n / ms / 1e6, **fractions(24 * n, None, ms)}
 
 
-def batched_vs_plain(torch, F, W, quick: bool):
+def batched_vs_plain(torch, F, W, quick: bool, with_plain: bool = True):
     """4096 complex64 products of sizes 2^6..2^16 (seed 6): one persistent launch (its work
     queue reused) against one fcirc_matvec call per instance, on the same device buffers."""
     from paper_2103_02605_amd.batched import BatchPlan
@@ -318,7 +330,7 @@ def batched_vs_plain(torch, F, W, quick: bool):
     def plain(i):
         for a, x, y in views:
             F.matvec(a, x, out=y)
-    ms_p = time_steps(torch, plain, 1 if quick else 3, 1)
+    ms_p = time_steps(torch, plain, 1 if quick else 3, 1) if with_plain else float("nan")
     ops = sum(3 * FP32_OPS_PER_COEF_LEVEL_TRANSFORM * int(L) * (1 << int(L)) for L in e)
     return {"coefficients": total, "batched_ms": ms_b, "plain_ms": ms_p,
             "batched_Gcoeff_per_s": total / ms_b / 1e6, "plain_Gcoeff_per_s": total / ms_p / 1e6,
@@ -326,7 +338,7 @@ def batched_vs_plain(torch, F, W, quick: bool):
             "tuned_parameters": params, "tuning_s": round(tune_s, 2), **fractions(24 * total, ops, ms_b)}
 
 
-def layer_vs_plain(torch, F, W, quick: bool):
+def layer_vs_plain(torch, F, W, quick: bool, with_plain: bool = True):
     """Circulant layer, batch 256 x 2^14 float32 (seed 7): library forward + backward against
     one product per row for y, grad_x and grad_a plus a torch sum."""
     a, x, g = W.circ_layer_f32()
@@ -348,7 +360,7 @@ def layer_vs_plain(torch, F, W, quick: bool):
             F.matvec(rev, tg[b], out=gx[b])
             F.matvec(tg[b], tx[b], out=parts[b])
         parts.sum(0)
-    ms_p = time_steps(torch, plain, 1 if quick else 3, 1)
+    ms_p = time_steps(torch, plain, 1 if quick else 3, 1) if with_plain else float("nan")
     # compulsory: forward reads x, writes y; backward reads x and gy, writes gx (float32),
     # plus the row and its gradient; work: per row, the forward splits x and merges y, the
     # backward splits gy twice, x once, and merges grad_x (grad_a's merge is shared)
@@ -486,6 +498,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip timing the CPU oracle")
     ap.add_argument("--no-secondary", action="store_true", help="skip the secondary workloads")
     ap.add_argument("--quick-secondary", action="store_true", help="time the secondary workloads with fewer steps")
+    ap.add_argument("--rows", default=",".join(SECONDARY_ROWS),
+                    help="comma-separated secondary workloads to run (default: all of " + ", ".join(SECONDARY_ROWS) + ")")
+    ap.add_argument("--no-plain", action="store_true",
+                    help="skip the one-call-per-instance comparisons of the batched and layer rows (profiling runs)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="first run 3 plain 64 MiB device copies (torch), the reference for HBM byte counters")
     args = ap.parse_args()
@@ -550,9 +566,14 @@ def main():
                        "split": {"top_levels": T, "block_levels": B}},
             "roofline": roofline}
     if not args.no_secondary:
-        line["secondary"] = secondary(torch, F, W, quick=args.quick_secondary)
+        rows = tuple(r for r in args.rows.split(",") if r)
+        unknown = set(rows) - set(SECONDARY_ROWS)
+        if unknown:
+            raise SystemExit(f"unknown secondary rows: {sorted(unknown)}")
+        line["secondary"] = secondary(torch, F, W, quick=args.quick_secondary, rows=rows, plain=not args.no_plain)
         for row, cb in sec_cpu.items():
-            line["secondary"][row]["cpu_baseline"] = cb
+            if row in line["secondary"]:
+                line["secondary"][row]["cpu_baseline"] = cb
     if not args.no_cpu_baseline:
         cb = cpu_baseline(W)
         line["cpu_baseline"] = cb
