@@ -13,6 +13,7 @@
 #include <memory>
 #include <mutex>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/fcirc.h"
@@ -260,11 +261,29 @@ struct LdPlain {
     return *elem32(p + (uint64_t)inst * stride, i);
   }
 };
-template <class T>
+// Store policy of a pass's output. Cached: plain stores (dirty lines stay in the XCD's L2
+// and are written back when the kernel ends, after its last wave). Stream: non-temporal
+// stores. Agent: relaxed stores at agent scope, written through the L2 as they are made.
+// The two last policies move a pass's writes into its compute time instead of a drain
+// after it.
+enum StorePolicy : int { ST_CACHED = 0, ST_STREAM = 1, ST_AGENT = 2 };
+
+template <class T, int POL = ST_CACHED>
 struct StPlain {
   T* p;
   uint64_t stride;
-  __device__ __forceinline__ void operator()(uint32_t inst, uint32_t i, T v) const { *elem32(p + (uint64_t)inst * stride, i) = v; }
+  __device__ __forceinline__ void operator()(uint32_t inst, uint32_t i, T v) const {
+    T* q = elem32(p + (uint64_t)inst * stride, i);
+    using U = std::conditional_t<sizeof(T) == 4, uint32_t, uint64_t>;
+    static_assert(sizeof(T) == sizeof(U), "4- or 8-byte elements");
+    if constexpr (POL == ST_STREAM) {
+      __builtin_nontemporal_store(__builtin_bit_cast(U, v), reinterpret_cast<U*>(q));
+    } else if constexpr (POL == ST_AGENT) {
+      __hip_atomic_store(reinterpret_cast<U*>(q), __builtin_bit_cast(U, v), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      *q = v;
+    }
+  }
 };
 struct LdR32 {  // real data promoted to complex
   const float* p;
@@ -382,8 +401,9 @@ inline hipError_t launch_split_r(Ctx& c, const PassArgs<Ring>& A, const typename
 }
 template <class Ring, int R, class SrcA, class SrcX, class Dst>
 inline hipError_t launch_split_ax_r(Ctx& c, const PassArgs<Ring>& A, const typename Ring::Params* rp, SrcA sa, SrcX sx,
-                                    Dst da, Dst dx, uint32_t grid, uint32_t nt, size_t lds, hipStream_t s) {
+                                    Dst da, Dst dx, uint32_t grid, uint32_t nt, hipStream_t s) {
   auto k = k_split_ax<Ring, R, SrcA, SrcX, Dst>;
+  const size_t lds = split_ax_lds_bytes<Ring, R>((size_t)1 << (A.logr + A.logc));
   allow_lds(k, lds);
   return launch(c, "fcirc_top_split", s, [&](hipEvent_t e0_, hipEvent_t e1_) { FCIRC_LAUNCH(e0_, e1_, k, dim3(grid), dim3(nt), lds, s, A, rp[0], rp[1], rp[2], sa, sx, da, dx); });
 }
@@ -419,8 +439,8 @@ inline hipError_t launch_split(Ctx& c, const PassArgs<Ring>& A, const typename R
 }
 template <class Ring, class SrcA, class SrcX, class Dst>
 inline hipError_t launch_split_ax(Ctx& c, const PassArgs<Ring>& A, const typename Ring::Params* rp, SrcA sa, SrcX sx, Dst da,
-                                  Dst dx, uint32_t grid, uint32_t nt, size_t lds, hipStream_t s) {
-#define FCIRC_CALL(r) launch_split_ax_r<Ring, r>(c, A, rp, sa, sx, da, dx, grid, nt, lds, s)
+                                  Dst dx, uint32_t grid, uint32_t nt, hipStream_t s) {
+#define FCIRC_CALL(r) launch_split_ax_r<Ring, r>(c, A, rp, sa, sx, da, dx, grid, nt, s)
   FCIRC_R_SWITCH(A.logr, FCIRC_CALL)
 #undef FCIRC_CALL
 }
@@ -480,7 +500,10 @@ inline hipError_t run_product(Ctx& c, const Schedule& S, uint32_t count, const t
   T* wx = ws + (uint64_t)count * n;
   if (!wy) wy = ws + 2 * (uint64_t)count * n;
   const LdPlain<T> lwa{wa, n}, lwx{wx, n}, lwy{wy, n};
-  const StPlain<T> swa{wa, n}, swx{wx, n}, swy{wy, n};
+  // Split outputs are streamed out, the block pass's output is written through at agent
+  // scope; the caller's dst keeps its own policy (measured on MI355X at n = 2^21).
+  const StPlain<T, ST_STREAM> swa{wa, n}, swx{wx, n};
+  const StPlain<T, ST_AGENT> swy{wy, n};
   for (int i = 0; i < S.ntop; ++i) {
     A.d0 = S.top_d0[i];
     A.logr = S.top_r[i];
@@ -499,12 +522,11 @@ inline hipError_t run_product(Ctx& c, const Schedule& S, uint32_t count, const t
         e = launch_split<Ring>(c, A, rp, lwa, lwx, swa, swx, grid, nt, lds, s);
     } else {  // one workgroup per tile of both
       A.narr = 1;
-      const size_t lds = 2 * tile * sizeof(T);
       const uint32_t grid = A.tiles * count;
       if (i == 0)
-        e = launch_split_ax<Ring>(c, A, rp, srca, srcx, swa, swx, grid, nt, lds, s);
+        e = launch_split_ax<Ring>(c, A, rp, srca, srcx, swa, swx, grid, nt, s);
       else
-        e = launch_split_ax<Ring>(c, A, rp, lwa, lwx, swa, swx, grid, nt, lds, s);
+        e = launch_split_ax<Ring>(c, A, rp, lwa, lwx, swa, swx, grid, nt, s);
     }
     if (e != hipSuccess) return e;
   }

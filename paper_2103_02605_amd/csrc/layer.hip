@@ -417,11 +417,11 @@ hipError_t split_top_ax(Ctx& c, const C32Tables* T, int L, int top, uint32_t cou
     hipError_t e;
     if (i == 0) {
       e = with_levels<1, 10>(r, [&](auto rr) {
-        return launch_split_ax_r<C32, decltype(rr)::value>(c, A, rp, srca, srcx, sa, sx, grid, nt, 2 * tile * sizeof(float2), s);
+        return launch_split_ax_r<C32, decltype(rr)::value>(c, A, rp, srca, srcx, sa, sx, grid, nt, s);
       });
     } else {
       e = with_levels<1, 10>(r, [&](auto rr) {
-        return launch_split_ax_r<C32, decltype(rr)::value>(c, A, rp, la, lx, sa, sx, grid, nt, 2 * tile * sizeof(float2), s);
+        return launch_split_ax_r<C32, decltype(rr)::value>(c, A, rp, la, lx, sa, sx, grid, nt, s);
       });
     }
     if (e != hipSuccess) return e;

@@ -147,6 +147,18 @@ __device__ __forceinline__ void load_tw_first(typename Ring::Tw* t, typename Rin
   for (int j = 0; j < K; ++j) t[j] = tw[tw_index(d0, blk, l0, j, sb)];
 }
 
+// The 2^K - 1 twiddles of an item from the LDS copy (levels l0 .. l0 + K - 1; level l of
+// the copy, node b at 2^l - 1 + b).
+template <class Ring, int K>
+__device__ __forceinline__ void lds_tw(typename Ring::Tw* t, const typename Ring::Tw* stw, uint32_t l0, uint32_t sb) {
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    const uint32_t ib = (1u << (l0 + j)) - 1 + (sb << j);
+#pragma unroll
+    for (int g = 0; g < (1 << j); ++g) t[(1 << j) - 1 + g] = stw[ib + g];
+  }
+}
+
 // The 2^K - 1 twiddles of a radix-2^K item in deepest-stage form, from the first twiddle
 // of each level (c[j]) and the uniform factors (level j, group g: c[j] * tu[2^j - 1 + g]).
 template <class Ring, int K>
@@ -249,35 +261,57 @@ __device__ __forceinline__ Ring make_ring(const PassArgs<Ring>& A, uint32_t inst
 
 // ---------------------------------------------------------------------------------------
 // One split stage of a top pass (one array). FIRST: read from global; LAST: write global.
+// PRE: the stage's elements were loaded ahead (pre); TWL: the twiddles come from the tile's
+// LDS copy stw (local heap order: level l of the tile, node b at 2^l - 1 + b); hook runs
+// between the stage's arithmetic and its stores.
 // ---------------------------------------------------------------------------------------
-template <class Ring, int K, bool FIRST, bool LAST, bool IS_X, class Src, class Dst>
+template <class Ring, int K>
+struct StagePre {
+  typename Ring::T v[1 << (EPT_LOG - K)][1 << K];
+};
+
+struct NoHook {
+  __device__ __forceinline__ void operator()() const {}
+};
+
+template <class Ring, int K, bool FIRST, bool LAST, bool IS_X, bool PRE = false, bool TWL = false, class Src, class Dst,
+          class Hook = NoHook>
 __device__ __forceinline__ void split_stage(const PassArgs<Ring>& A, const TilePos& P, const Ring& R,
                                             typename Ring::Tw const* tw, typename Ring::T* lds, uint32_t l0,
-                                            uint32_t nt, uint32_t tid, const Src& src, const Dst& dst) {
+                                            uint32_t nt, uint32_t tid, const Src& src, const Dst& dst,
+                                            const StagePre<Ring, K>* pre = nullptr, const Hook& hook = Hook{},
+                                            const typename Ring::Tw* stw = nullptr) {
   using T = typename Ring::T;
   using Tw = typename Ring::Tw;
   constexpr int IPT = 1 << (EPT_LOG - K);
   constexpr int E = 1 << K;
+  static_assert(!PRE || FIRST, "only a first stage takes preloaded elements");
   T v[IPT][E];
   Tw t[IPT][E - 1];
   Item it[IPT];
 #pragma unroll
   for (int u = 0; u < IPT; ++u) {
     it[u] = item_at(tid + u * nt, A.logr, A.logc, l0, K);
-    load_tw<Ring, K>(t[u], tw, A.d0, P.blk, l0, it[u].sb);
+    if constexpr (TWL)
+      lds_tw<Ring, K>(t[u], stw, l0, it[u].sb);
+    else
+      load_tw<Ring, K>(t[u], tw, A.d0, P.blk, l0, it[u].sb);
   }
 #pragma unroll
   for (int u = 0; u < IPT; ++u)
 #pragma unroll
     for (int i = 0; i < E; ++i) {
       const uint32_t row = it[u].row0 + ((uint32_t)i << it[u].sh);
-      if constexpr (FIRST)
+      if constexpr (PRE)
+        v[u][i] = pre->v[u][i];
+      else if constexpr (FIRST)
         v[u][i] = src(R, P.inst, gidx(P.base, P.rs, it[u], i));
       else
         v[u][i] = lds[(row << A.logc) + it[u].col];
     }
 #pragma unroll
   for (int u = 0; u < IPT; ++u) split_levels<Ring, K, !IS_X, IS_X>(R, v[u], v[u], t[u]);
+  hook();
 #pragma unroll
   for (int u = 0; u < IPT; ++u)
 #pragma unroll
@@ -288,6 +322,18 @@ __device__ __forceinline__ void split_stage(const PassArgs<Ring>& A, const TileP
       else
         lds[(row << A.logc) + it[u].col] = v[u][i];
     }
+}
+
+// The first-stage elements of a top pass's tile (one array), loaded ahead of the stage.
+template <class Ring, int K, class Src>
+__device__ __forceinline__ void stage_prefetch(const PassArgs<Ring>& A, const TilePos& P, const Ring& R, uint32_t nt,
+                                               uint32_t tid, const Src& src, StagePre<Ring, K>& pre) {
+#pragma unroll
+  for (int u = 0; u < (1 << (EPT_LOG - K)); ++u) {
+    const Item it = item_at(tid + u * nt, A.logr, A.logc, 0, K);
+#pragma unroll
+    for (int i = 0; i < (1 << K); ++i) pre.v[u][i] = src(R, P.inst, gidx(P.base, P.rs, it, i));
+  }
 }
 
 // Stage plan of a pass of R levels: the first stage takes the remainder.
@@ -340,74 +386,19 @@ __global__ void __launch_bounds__(TopThreads<Ring>::value) k_split(PassArgs<Ring
 }
 
 // ---------------------------------------------------------------------------------------
-// Joint split pass: one workgroup takes the same tile of the row and of the vector. Both
-// use the same twiddles (the row split and the vector split of a node share g), so they
-// are loaded once; the vector's element loads are issued before the row's arithmetic and
-// the row's stores overlap the vector's arithmetic. LDS holds two tiles.
+// Joint split pass: one workgroup takes the same tile of the row and of the vector, row
+// first. It runs every stage of the row's tile, then every stage of the vector's; the
+// vector's first-stage elements are loaded as soon as the row's first stage has its data,
+// so those loads are in flight while the row's later stages compute and write, and the
+// tile's reads of one array overlap the writes of the other (the outputs are streamed out
+// with non-temporal stores, not held in L2 until the kernel ends). Every stage takes its
+// twiddles from an LDS copy of the tile's 2^R - 1 (the row and the vector split of a node
+// share g), loaded behind the row's elements so that no global load waits behind the
+// vector's. LDS holds two tiles and the twiddles.
 // ---------------------------------------------------------------------------------------
-template <class Ring, int K, bool FIRST, bool LAST, class SrcA, class SrcX, class Dst>
-__device__ __forceinline__ void split_stage_ax(const PassArgs<Ring>& A, const TilePos& P, const Ring& R,
-                                               typename Ring::Tw const* tw, typename Ring::T* lda, typename Ring::T* ldx,
-                                               uint32_t l0, uint32_t nt, uint32_t tid, const SrcA& srca,
-                                               const SrcX& srcx, const Dst& dsta, const Dst& dstx) {
-  using T = typename Ring::T;
-  using Tw = typename Ring::Tw;
-  constexpr int IPT = 1 << (EPT_LOG - K);
-  constexpr int E = 1 << K;
-  T va[IPT][E], vx[IPT][E];
-  Tw t[IPT][E - 1];
-  Item it[IPT];
-#pragma unroll
-  for (int u = 0; u < IPT; ++u) {
-    it[u] = item_at(tid + u * nt, A.logr, A.logc, l0, K);
-    load_tw<Ring, K>(t[u], tw, A.d0, P.blk, l0, it[u].sb);
-  }
-#pragma unroll
-  for (int u = 0; u < IPT; ++u)
-#pragma unroll
-    for (int i = 0; i < E; ++i) {
-      const uint32_t row = it[u].row0 + ((uint32_t)i << it[u].sh);
-      if constexpr (FIRST)
-        va[u][i] = srca(R, P.inst, gidx(P.base, P.rs, it[u], i));
-      else
-        va[u][i] = lda[(row << A.logc) + it[u].col];
-    }
-  __builtin_amdgcn_sched_barrier(0);  // row loads first, then the vector's
-#pragma unroll
-  for (int u = 0; u < IPT; ++u)
-#pragma unroll
-    for (int i = 0; i < E; ++i) {
-      const uint32_t row = it[u].row0 + ((uint32_t)i << it[u].sh);
-      if constexpr (FIRST)
-        vx[u][i] = srcx(R, P.inst, gidx(P.base, P.rs, it[u], i));
-      else
-        vx[u][i] = ldx[(row << A.logc) + it[u].col];
-    }
-  __builtin_amdgcn_sched_barrier(0);  // all loads in flight before the row's arithmetic
-#pragma unroll
-  for (int u = 0; u < IPT; ++u) split_levels<Ring, K, true, false>(R, va[u], va[u], t[u]);
-#pragma unroll
-  for (int u = 0; u < IPT; ++u)
-#pragma unroll
-    for (int i = 0; i < E; ++i) {
-      const uint32_t row = it[u].row0 + ((uint32_t)i << it[u].sh);
-      if constexpr (LAST)
-        dsta(P.inst, gidx(P.base, P.rs, it[u], i), va[u][i]);
-      else
-        lda[(row << A.logc) + it[u].col] = va[u][i];
-    }
-#pragma unroll
-  for (int u = 0; u < IPT; ++u) split_levels<Ring, K, false, true>(R, vx[u], vx[u], t[u]);
-#pragma unroll
-  for (int u = 0; u < IPT; ++u)
-#pragma unroll
-    for (int i = 0; i < E; ++i) {
-      const uint32_t row = it[u].row0 + ((uint32_t)i << it[u].sh);
-      if constexpr (LAST)
-        dstx(P.inst, gidx(P.base, P.rs, it[u], i), vx[u][i]);
-      else
-        ldx[(row << A.logc) + it[u].col] = vx[u][i];
-    }
+template <class Ring, int R>
+constexpr size_t split_ax_lds_bytes(size_t tile) {
+  return 2 * tile * sizeof(typename Ring::T) + (((size_t)1 << R) - 1) * sizeof(typename Ring::Tw);
 }
 
 template <class Ring, int R, class SrcA, class SrcX, class Dst>
@@ -415,18 +406,52 @@ __global__ void __launch_bounds__(TopThreads<Ring>::value) k_split_ax(PassArgs<R
                                                   typename Ring::Params rp2, SrcA srca, SrcX srcx, Dst dsta, Dst dstx) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   using T = typename Ring::T;
+  using Tw = typename Ring::Tw;
   using SP = StagePlan<R>;
+  constexpr int K0 = SP::K0;
   const TilePos P = tile_pos(A, A.xcd ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x);
   uint32_t rsel;
   const Ring Rg = make_ring(A, P.inst, rp0, rp1, rp2, &rsel);
+  const size_t tile = (size_t)1 << (A.logr + A.logc);
   T* lda = reinterpret_cast<T*>(smem_raw);
-  T* ldx = lda + ((size_t)1 << (A.logr + A.logc));
-  const typename Ring::Tw* tw = A.tw[rsel];
+  T* ldx = lda + tile;
+  Tw* stw = reinterpret_cast<Tw*>(ldx + tile);
+  const Tw* tw = A.tw[rsel];
+  const uint32_t nt = blockDim.x, tid = threadIdx.x;
+  StagePre<Ring, K0> pa, px;
+  stage_prefetch<Ring, K0>(A, P, Rg, nt, tid, srca, pa);
+  __builtin_amdgcn_sched_barrier(0);  // the row's loads first
+  // level l of the tile is the contiguous heap range [2^(d0+l) + blk 2^l, + 2^l)
+  for (uint32_t e = tid; e < (1u << R) - 1; e += nt) {
+    const uint32_t l = 31u - __clz(e + 1);
+    stw[e] = tw[(1u << (A.d0 + l)) + (P.blk << l) + (e + 1 - (1u << l))];
+  }
+  __syncthreads();
+  const auto prefetch_x = [&] {
+    __builtin_amdgcn_sched_barrier(0);
+    stage_prefetch<Ring, K0>(A, P, Rg, nt, tid, srcx, px);
+    __builtin_amdgcn_sched_barrier(0);
+  };
   static_for<SP::NST>([&](auto sc) {
     constexpr int s = decltype(sc)::value;
     constexpr bool first = s == 0, last = s + 1 == SP::NST;
-    split_stage_ax<Ring, SP::k(s), first, last>(A, P, Rg, tw, lda, ldx, SP::l0(s), blockDim.x, threadIdx.x, srca, srcx,
-                                                dsta, dstx);
+    if constexpr (first)
+      split_stage<Ring, SP::k(s), first, last, false, true, true>(A, P, Rg, tw, lda, SP::l0(s), nt, tid, srca, dsta, &pa,
+                                                                  prefetch_x, stw);
+    else
+      split_stage<Ring, SP::k(s), first, last, false, false, true>(A, P, Rg, tw, lda, SP::l0(s), nt, tid, srca, dsta,
+                                                                   nullptr, NoHook{}, stw);
+    if constexpr (!last) __syncthreads();
+  });
+  static_for<SP::NST>([&](auto sc) {
+    constexpr int s = decltype(sc)::value;
+    constexpr bool first = s == 0, last = s + 1 == SP::NST;
+    if constexpr (first)
+      split_stage<Ring, SP::k(s), first, last, true, true, true>(A, P, Rg, tw, ldx, SP::l0(s), nt, tid, srcx, dstx, &px,
+                                                                 NoHook{}, stw);
+    else
+      split_stage<Ring, SP::k(s), first, last, true, false, true>(A, P, Rg, tw, ldx, SP::l0(s), nt, tid, srcx, dstx,
+                                                                  nullptr, NoHook{}, stw);
     if constexpr (!last) __syncthreads();
   });
 }
@@ -594,17 +619,6 @@ __device__ __forceinline__ void load_deep_tw(DeepTw<Ring>& D, const Ring& R, con
     }
   } else {
     load_deep_heap<Ring>(D, R, tw, twi, A.d0, P.blk, l0, it.sb);
-  }
-}
-
-// The 2^K - 1 twiddles of an item from the LDS copy (levels l0 .. l0 + K - 1).
-template <class Ring, int K>
-__device__ __forceinline__ void lds_tw(typename Ring::Tw* t, const typename Ring::Tw* stw, uint32_t l0, uint32_t sb) {
-#pragma unroll
-  for (int j = 0; j < K; ++j) {
-    const uint32_t ib = (1u << (l0 + j)) - 1 + (sb << j);
-#pragma unroll
-    for (int g = 0; g < (1 << j); ++g) t[(1 << j) - 1 + g] = stw[ib + g];
   }
 }
 
