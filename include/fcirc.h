@@ -313,15 +313,20 @@ int fcirc_get_split(fcirc_ctx *ctx, uint64_t n, fcirc_ring ring);
  * Set the schedule for (ring, n) explicitly, as fcirc_tune would: top_levels (-1 default),
  * tile_log = log2 elements of a top-pass tile (-1 default, at most 14 for Z/p and 13 for the
  * complex rings), flags = a bitwise
- * OR of FCIRC_SCHED_* (0..3; the default is FCIRC_SCHED_XCD). fcirc_get_schedule reports
+ * OR of FCIRC_SCHED_* (0..7; the default is FCIRC_SCHED_XCD). fcirc_get_schedule reports
  * the schedule in use and returns the number of top passes.
  *   FCIRC_SCHED_XCD       top-pass tiles in XCD-aware order (neighbouring column tiles on
  *                         one XCD, so they share its L2)
  *   FCIRC_SCHED_SEPARATE  the split passes take the row and the vector in separate
  *                         workgroups (default: one workgroup splits the same tile of both)
+ *   FCIRC_SCHED_SMALL     a product with no top pass and 2^6 <= n <= 2^12 runs as one
+ *                         workgroup of several waves per instance (radix-4 register
+ *                         stages, every twiddle in LDS) instead of the single-wave block
+ *                         pass; ignored for other sizes
  */
 #define FCIRC_SCHED_XCD 1
 #define FCIRC_SCHED_SEPARATE 2
+#define FCIRC_SCHED_SMALL 4
 fcirc_status fcirc_set_schedule(fcirc_ctx *ctx, fcirc_ring ring, uint64_t n, int top_levels, int tile_log, int flags);
 int fcirc_get_schedule(fcirc_ctx *ctx, fcirc_ring ring, uint64_t n, int *top_levels, int *tile_log, int *flags);
 

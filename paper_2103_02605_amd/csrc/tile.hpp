@@ -824,6 +824,161 @@ __device__ __forceinline__ void block_pass(const PassArgs<Ring>& A, uint32_t vwg
 }
 
 // ---------------------------------------------------------------------------------------
+// Small product in one workgroup: the whole tree of an instance of 2^LOGR elements
+// (LOGR <= 12, no top pass) by 2^(LOGR - K) threads, radix-2^K register stages (the first
+// takes the remainder), every twiddle of the tree staged in LDS, a barrier between
+// stages. A lone small product then runs on 2^(LOGR - K - 6) waves instead of the block
+// pass's single wave, whose 16 elements per thread make it one long dependent stream.
+// One workgroup per instance.
+// ---------------------------------------------------------------------------------------
+template <int LOGR, int K>
+struct SmallShape {
+  static constexpr int NST = (LOGR + K - 1) / K;
+  static constexpr int K0 = LOGR - K * (NST - 1);  // levels of the first stage
+  static constexpr int NT = 1 << (LOGR - K);       // threads; 2^K elements each per stage
+  static constexpr int NTW = (1 << LOGR) - 1;      // twiddles per direction
+};
+
+template <class Ring, int LOGR, int K>
+constexpr size_t small_lds_bytes() {
+  return 2 * (sizeof(typename Ring::T) << LOGR) + 2 * (size_t)SmallShape<LOGR, K>::NTW * sizeof(typename Ring::Tw);
+}
+
+// One split stage of KS levels (the deepest also forms the leaves and merges back).
+template <class Ring, int LOGR, int K, int KS, bool FIRST, bool DEEPEST, class SrcA, class SrcX, class Dst>
+__device__ __forceinline__ void small_split_stage(const PassArgs<Ring>& A, const TilePos& P, const Ring& R,
+                                                  const typename Ring::Tw* stw, const typename Ring::Tw* stwi,
+                                                  typename Ring::T* sa, typename Ring::T* sx, uint32_t l0, uint32_t tid,
+                                                  const SrcA& srca, const SrcX& srcx, const Dst& dst) {
+  using T = typename Ring::T;
+  using Tw = typename Ring::Tw;
+  constexpr int E = 1 << KS;
+  constexpr int IPT = (1 << K) / E;
+  constexpr uint32_t NT = SmallShape<LOGR, K>::NT;
+  T va[IPT][E], vx[IPT][E];
+  Tw t[IPT][E - 1];
+  Tw ti[DEEPEST ? IPT : 1][E - 1];
+  Item it[IPT];
+#pragma unroll
+  for (int u = 0; u < IPT; ++u) {
+    it[u] = item_at(tid + u * NT, LOGR, 0, l0, KS);
+    lds_tw<Ring, KS>(t[u], stw, l0, it[u].sb);
+    if constexpr (DEEPEST) lds_tw<Ring, KS>(ti[u], stwi, l0, it[u].sb);
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      const uint32_t row = it[u].row0 + ((uint32_t)i << it[u].sh);
+      if constexpr (FIRST) {
+        va[u][i] = srca(R, P.inst, P.base + row);
+        vx[u][i] = srcx(R, P.inst, P.base + row);
+      } else {
+        va[u][i] = sa[row];
+        vx[u][i] = sx[row];
+      }
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < IPT; ++u) {
+    split_levels<Ring, KS, true, true>(R, va[u], vx[u], t[u]);
+    if constexpr (DEEPEST) {
+#pragma unroll
+      for (int i = 0; i < E; ++i) va[u][i] = R.leaf(va[u][i], vx[u][i]);
+      merge_levels<Ring, KS>(R, va[u], ti[u]);
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < IPT; ++u)
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      const uint32_t row = it[u].row0 + ((uint32_t)i << it[u].sh);
+      if constexpr (DEEPEST && FIRST) {
+        dst(P.inst, P.base + row, A.final_store ? R.canon(va[u][i]) : va[u][i]);
+      } else {
+        sa[row] = va[u][i];
+        if constexpr (!DEEPEST) sx[row] = vx[u][i];
+      }
+    }
+}
+
+// One merge stage of KS levels. LAST: write dst.
+template <class Ring, int LOGR, int K, int KS, bool LAST, class Dst>
+__device__ __forceinline__ void small_merge_stage(const PassArgs<Ring>& A, const TilePos& P, const Ring& R,
+                                                  const typename Ring::Tw* stwi, typename Ring::T* sa, uint32_t l0,
+                                                  uint32_t tid, const Dst& dst) {
+  using T = typename Ring::T;
+  using Tw = typename Ring::Tw;
+  constexpr int E = 1 << KS;
+  constexpr int IPT = (1 << K) / E;
+  constexpr uint32_t NT = SmallShape<LOGR, K>::NT;
+  T v[IPT][E];
+  Tw t[IPT][E - 1];
+  Item it[IPT];
+#pragma unroll
+  for (int u = 0; u < IPT; ++u) {
+    it[u] = item_at(tid + u * NT, LOGR, 0, l0, KS);
+    lds_tw<Ring, KS>(t[u], stwi, l0, it[u].sb);
+#pragma unroll
+    for (int i = 0; i < E; ++i) v[u][i] = sa[it[u].row0 + ((uint32_t)i << it[u].sh)];
+  }
+#pragma unroll
+  for (int u = 0; u < IPT; ++u) merge_levels<Ring, KS>(R, v[u], t[u]);
+#pragma unroll
+  for (int u = 0; u < IPT; ++u)
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      const uint32_t row = it[u].row0 + ((uint32_t)i << it[u].sh);
+      if constexpr (LAST)
+        dst(P.inst, P.base + row, A.final_store ? R.canon(v[u][i]) : v[u][i]);
+      else
+        sa[row] = v[u][i];
+    }
+}
+
+template <class Ring, int LOGR, int K, class SrcA, class SrcX, class Dst>
+__global__ void __launch_bounds__((SmallShape<LOGR, K>::NT)) k_small(PassArgs<Ring> A, typename Ring::Params rp0,
+                                                                   typename Ring::Params rp1, typename Ring::Params rp2,
+                                                                   SrcA srca, SrcX srcx, Dst dst) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  using T = typename Ring::T;
+  using Tw = typename Ring::Tw;
+  using S = SmallShape<LOGR, K>;
+  static_assert(S::NST >= 2, "at least two stages");
+  const uint32_t tid = threadIdx.x;
+  T* sa = reinterpret_cast<T*>(smem_raw);
+  T* sx = sa + (1u << LOGR);
+  Tw* stw = reinterpret_cast<Tw*>(sx + (1u << LOGR));
+  Tw* stwi = stw + S::NTW;
+  const TilePos P = tile_pos(A, blockIdx.x);
+  uint32_t rsel;
+  const Ring R = make_ring(A, P.inst, rp0, rp1, rp2, &rsel);
+  // the tree of one instance (d0 = 0, block 0): level l is heap range [2^l, 2^(l+1)),
+  // local index 2^l - 1 + g, so the copy is contiguous
+  const Tw* tw = A.tw[rsel] + 1;
+  const Tw* twi = A.twi[rsel] + 1;
+  for (uint32_t e = tid; e < (uint32_t)S::NTW; e += S::NT) {
+    stw[e] = tw[e];
+    stwi[e] = twi[e];
+  }
+  __syncthreads();
+  small_split_stage<Ring, LOGR, K, S::K0, true, false>(A, P, R, stw, stwi, sa, sx, 0, tid, srca, srcx, dst);
+  __syncthreads();
+#pragma unroll
+  for (int s = 1; s < S::NST; ++s) {
+    const uint32_t l0 = S::K0 + K * (s - 1);
+    if (s + 1 == S::NST)
+      small_split_stage<Ring, LOGR, K, K, false, true>(A, P, R, stw, stwi, sa, sx, l0, tid, srca, srcx, dst);
+    else
+      small_split_stage<Ring, LOGR, K, K, false, false>(A, P, R, stw, stwi, sa, sx, l0, tid, srca, srcx, dst);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int s = S::NST - 2; s >= 1; --s) {
+    small_merge_stage<Ring, LOGR, K, K, false>(A, P, R, stwi, sa, S::K0 + K * (s - 1), tid, dst);
+    __syncthreads();
+  }
+  small_merge_stage<Ring, LOGR, K, S::K0, true>(A, P, R, stwi, sa, 0, tid, dst);
+}
+
+// ---------------------------------------------------------------------------------------
 // Leaf-domain block pass: the row's leaves are given (the row transform of the whole
 // product, shared by every instance), so a block only splits the vector, multiplies each
 // leaf by the row's leaf (conjugated if CONJ) and 1/n, and merges back up. Same stage plan

@@ -139,7 +139,7 @@ fcirc_status load_schedules(Ctx& c, const char* path) {
     }
     const bool zp = ring >= FCIRC_ZP_998244353 && ring <= FCIRC_ZP_167772161;
     if (ring < FCIRC_ZP_998244353 || ring > FCIRC_GFP2 || L < 0 || L > 26 || top < -1 || top > 26 || tile < -1 ||
-        tile > (zp ? 14 : 13) || flags < 0 || flags > 3) {
+        tile > (zp ? 14 : 13) || flags < 0 || flags > 7) {
       ok = false;
       break;
     }
@@ -189,7 +189,7 @@ fcirc_status fcirc_load_schedules(fcirc_ctx* ctx, const char* path) {
 
 fcirc_status fcirc_set_schedule(fcirc_ctx* ctx, fcirc_ring ring, uint64_t n, int top_levels, int tile_log, int flags) {
   if (!ctx || n == 0 || (n & (n - 1)) || ring < FCIRC_ZP_998244353 || ring > FCIRC_GFP2) return FCIRC_EINVAL;
-  if (top_levels < -1 || top_levels > 26 || tile_log < -1 || tile_log > (ring <= FCIRC_ZP_167772161 ? 14 : 13) || flags < 0 || flags > 3) return FCIRC_EINVAL;
+  if (top_levels < -1 || top_levels > 26 || tile_log < -1 || tile_log > (ring <= FCIRC_ZP_167772161 ? 14 : 13) || flags < 0 || flags > 7) return FCIRC_EINVAL;
   TuneVal v;
   v.top = top_levels;
   v.tile_log = tile_log;
@@ -225,7 +225,12 @@ fcirc_status fcirc_tune(fcirc_ctx* ctx, uint64_t n, fcirc_ring ring, void* strea
     if (top == 0) {
       TuneVal v;
       v.top = 0;
+      v.flags = FCIRC_SCHED_XCD;
       cands.push_back(v);
+      if (L >= 6 && L <= 12) {  // the several-wave small-product kernel
+        v.flags = FCIRC_SCHED_XCD | FCIRC_SCHED_SMALL;
+        cands.push_back(v);
+      }
       continue;
     }
     for (int tl = 10; tl <= (zp ? 14 : 13); ++tl)

@@ -336,6 +336,7 @@ def tune(n: int, ring: int, device=None):
 
 SCHED_XCD = 1       # XCD-aware tile order in the top passes
 SCHED_SEPARATE = 2  # split passes take the row and the vector in separate workgroups
+SCHED_SMALL = 4     # 2^6..2^12 with no top pass: one several-wave workgroup per instance
 
 
 def set_schedule(n: int, ring: int, top_levels: int = -1, tile_log: int = -1, flags: int = SCHED_XCD, device=None):

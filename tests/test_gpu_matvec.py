@@ -72,6 +72,39 @@ def test_all_sizes_bit_exact(F, p, L):
         np.testing.assert_array_equal(host_u32(y), oracle_modp(a, x, f, p), err_msg=f"p={p} n={n} f={f}")
 
 
+@pytest.mark.parametrize("ring", ["p1", "p2", "p3", "c64"])
+@pytest.mark.parametrize("L", list(range(6, 13)))
+def test_small_kernel_and_block_pass(F, ring, L):
+    """Products of 2^6..2^12 with no top pass run as the several-wave small-product kernel
+    by default (FCIRC_SCHED_SMALL) and as the single-wave block pass otherwise; both
+    against the oracle (bit-exact over Z/p for f = 1, p - 1 and a random f; complex within
+    1e-5 of the FP64 definition), alone and as a batch of 3."""
+    import torch
+    n = 1 << L
+    ring_id = {"p1": 0, "p2": 1, "p3": 2, "c64": 3}[ring]
+    try:
+        for flags in (F.SCHED_XCD | F.SCHED_SMALL, F.SCHED_XCD):
+            F.set_schedule(n, ring_id, 0, -1, flags)
+            if ring == "c64":
+                a, x = W.complex_pair(n, seed=300 + L)
+                y = F.matvec(torch.from_numpy(a).cuda(), torch.from_numpy(x).cuda()).cpu().numpy()
+                want = O.dense_matvec_c128(a.astype(np.complex128), x.astype(np.complex128), 1.0)
+                assert np.linalg.norm(y - want) / np.linalg.norm(want) < 1e-5, (L, flags)
+                continue
+            p = PRIMES[ring_id]
+            a, x = W.modp_pair(n, p, seed=200 + L)
+            for f in (1, p - 1, rand_f(n, p, 7 * L)):
+                y = F.matvec(dev(a), dev(x), f=f, p=p)
+                np.testing.assert_array_equal(host_u32(y), oracle_modp(a, x, f, p), err_msg=f"p={p} n={n} f={f} flags={flags}")
+            am = np.stack([W.modp_pair(n, p, seed=400 + 10 * L + k)[0] for k in range(3)])
+            xm = np.stack([W.modp_pair(n, p, seed=400 + 10 * L + k)[1] for k in range(3)])
+            ym = F.matvec_many(dev(am), dev(xm), f=1, p=p).cpu().numpy().view(np.uint32).astype(np.int64)
+            for k in range(3):
+                np.testing.assert_array_equal(ym[k], oracle_modp(am[k], xm[k], 1, p), err_msg=f"batch row {k} flags={flags}")
+    finally:
+        F.set_schedule(n, ring_id, -1, -1, F.SCHED_XCD | F.SCHED_SMALL)
+
+
 def test_zero_sizes(F):
     """Empty inputs through the C-ABI: n = 0 is ESIZE; an empty batch (count 0) enqueues
     nothing and returns OK; an empty factor (na = 0) or an empty layer batch is EINVAL."""
