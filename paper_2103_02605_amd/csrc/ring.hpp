@@ -32,6 +32,8 @@ struct ZpTw {
 struct ZpParams {
   uint32_t p;
   uint32_t pinv;   // p^-1 mod 2^32
+  uint32_t npinv;  // -p^-1 mod 2^32, from the host: formed on the device, t * (0 - pinv)
+                   // is rewritten by the compiler as -(t * pinv), one instruction more
   ZpTw leaf;       // 2^32 / n mod p: undoes the Montgomery factor and applies 1/n
   ZpTw one;        // {1, floor(2^32 / p)}: reduces any 32-bit value to [0, 2p)
   uint32_t two31;  // 2^31 mod p
@@ -42,13 +44,13 @@ struct Zp {
   using T = uint32_t;
   using Tw = ZpTw;
   using Params = ZpParams;
-  uint32_t p, p2, pinv;
+  uint32_t p, p2, pinv, npinv;
   ZpTw leafs, one;
   uint32_t two31;
   ZpTw r32;
 
   __device__ __forceinline__ explicit Zp(const ZpParams& q)
-      : p(q.p), p2(2u * q.p), pinv(q.pinv), leafs(q.leaf), one(q.one), two31(q.two31), r32(q.r32) {}
+      : p(q.p), p2(2u * q.p), pinv(q.pinv), npinv(q.npinv), leafs(q.leaf), one(q.one), two31(q.two31), r32(q.r32) {}
 
   __device__ __forceinline__ uint32_t shoup(uint32_t v, ZpTw t) const {
     const uint32_t q = __umulhi(v, t.wp);
@@ -110,7 +112,7 @@ struct Zp {
   using DeepW = uint32_t;
   __device__ __forceinline__ uint32_t mont(uint32_t v, uint32_t wM) const {
     const uint64_t t = (uint64_t)v * wM;
-    const uint32_t m = (uint32_t)t * (0u - pinv);          // -p^-1 mod 2^32
+    const uint32_t m = (uint32_t)t * npinv;
     return (uint32_t)(((uint64_t)m * p + t) >> 32);        // (t + m p) / 2^32, exact
   }
   __device__ __forceinline__ uint32_t canon1(uint32_t v) const { return min(v, v - p); }  // [0,2p) -> [0,p)

@@ -149,8 +149,8 @@ __device__ __forceinline__ void load_tw_first(typename Ring::Tw* t, typename Rin
 
 // The 2^K - 1 twiddles of an item from the LDS copy (levels l0 .. l0 + K - 1; level l of
 // the copy, node b at 2^l - 1 + b).
-template <class Ring, int K>
-__device__ __forceinline__ void lds_tw(typename Ring::Tw* t, const typename Ring::Tw* stw, uint32_t l0, uint32_t sb) {
+template <class Ring, int K, class W>
+__device__ __forceinline__ void lds_tw(W* t, const W* stw, uint32_t l0, uint32_t sb) {
 #pragma unroll
   for (int j = 0; j < K; ++j) {
     const uint32_t ib = (1u << (l0 + j)) - 1 + (sb << j);
@@ -172,13 +172,11 @@ __device__ __forceinline__ void deep_twiddles(const Ring& R, typename Ring::Deep
   }
 }
 
-// K split levels from the first twiddle per level and the uniform factors tu, on the row
-// (DA) and/or the vector (DX).
+// K split levels with twiddles in the ring's deepest-stage form (Montgomery form for Z/p,
+// which needs no per-twiddle companion), on the row (DA) and/or the vector (DX).
 template <class Ring, int K, bool DA = true, bool DX = true>
-__device__ __forceinline__ void split_levels_first(const Ring& R, typename Ring::T* va, typename Ring::T* vx,
-                                                   const typename Ring::DeepW* c, const typename Ring::DeepW* tu) {
-  typename Ring::DeepW w[(1 << K) - 1];
-  deep_twiddles<Ring, K>(R, w, c, tu);
+__device__ __forceinline__ void split_levels_d(const Ring& R, typename Ring::T* va, typename Ring::T* vx,
+                                               const typename Ring::DeepW* w) {
 #pragma unroll
   for (int j = 0; j < K; ++j) {
     const int h = 1 << (K - 1 - j);
@@ -194,12 +192,9 @@ __device__ __forceinline__ void split_levels_first(const Ring& R, typename Ring:
   }
 }
 
-// K merge levels (deepest first) from the first twiddle per level and the factors tui.
+// K merge levels (deepest first) with twiddles in deepest-stage form.
 template <class Ring, int K>
-__device__ __forceinline__ void merge_levels_first(const Ring& R, typename Ring::T* vy, const typename Ring::DeepW* c,
-                                                   const typename Ring::DeepW* tui) {
-  typename Ring::DeepW w[(1 << K) - 1];
-  deep_twiddles<Ring, K>(R, w, c, tui);
+__device__ __forceinline__ void merge_levels_d(const Ring& R, typename Ring::T* vy, const typename Ring::DeepW* w) {
 #pragma unroll
   for (int j = K - 1; j >= 0; --j) {
     const int h = 1 << (K - 1 - j);
@@ -212,6 +207,25 @@ __device__ __forceinline__ void merge_levels_first(const Ring& R, typename Ring:
       }
     }
   }
+}
+
+// K split levels from the first twiddle per level and the uniform factors tu, on the row
+// (DA) and/or the vector (DX).
+template <class Ring, int K, bool DA = true, bool DX = true>
+__device__ __forceinline__ void split_levels_first(const Ring& R, typename Ring::T* va, typename Ring::T* vx,
+                                                   const typename Ring::DeepW* c, const typename Ring::DeepW* tu) {
+  typename Ring::DeepW w[(1 << K) - 1];
+  deep_twiddles<Ring, K>(R, w, c, tu);
+  split_levels_d<Ring, K, DA, DX>(R, va, vx, w);
+}
+
+// K merge levels (deepest first) from the first twiddle per level and the factors tui.
+template <class Ring, int K>
+__device__ __forceinline__ void merge_levels_first(const Ring& R, typename Ring::T* vy, const typename Ring::DeepW* c,
+                                                   const typename Ring::DeepW* tui) {
+  typename Ring::DeepW w[(1 << K) - 1];
+  deep_twiddles<Ring, K>(R, w, c, tui);
+  merge_levels_d<Ring, K>(R, vy, w);
 }
 
 // K split levels on the registers of one item, for the row (a) and/or the vector (x).
@@ -262,8 +276,8 @@ __device__ __forceinline__ Ring make_ring(const PassArgs<Ring>& A, uint32_t inst
 // ---------------------------------------------------------------------------------------
 // One split stage of a top pass (one array). FIRST: read from global; LAST: write global.
 // PRE: the stage's elements were loaded ahead (pre); TWL: the twiddles come from the tile's
-// LDS copy stw (local heap order: level l of the tile, node b at 2^l - 1 + b); hook runs
-// between the stage's arithmetic and its stores.
+// LDS copy stw, in the ring's deepest-stage form (local heap order: level l of the tile,
+// node b at 2^l - 1 + b); hook runs between the stage's arithmetic and its stores.
 // ---------------------------------------------------------------------------------------
 template <class Ring, int K>
 struct StagePre {
@@ -280,14 +294,15 @@ __device__ __forceinline__ void split_stage(const PassArgs<Ring>& A, const TileP
                                             typename Ring::Tw const* tw, typename Ring::T* lds, uint32_t l0,
                                             uint32_t nt, uint32_t tid, const Src& src, const Dst& dst,
                                             const StagePre<Ring, K>* pre = nullptr, const Hook& hook = Hook{},
-                                            const typename Ring::Tw* stw = nullptr) {
+                                            const typename Ring::DeepW* stw = nullptr) {
   using T = typename Ring::T;
   using Tw = typename Ring::Tw;
   constexpr int IPT = 1 << (EPT_LOG - K);
   constexpr int E = 1 << K;
   static_assert(!PRE || FIRST, "only a first stage takes preloaded elements");
   T v[IPT][E];
-  Tw t[IPT][E - 1];
+  using TwS = std::conditional_t<TWL, typename Ring::DeepW, Tw>;  // LDS copy or heap tables
+  TwS t[IPT][E - 1];
   Item it[IPT];
 #pragma unroll
   for (int u = 0; u < IPT; ++u) {
@@ -310,7 +325,12 @@ __device__ __forceinline__ void split_stage(const PassArgs<Ring>& A, const TileP
         v[u][i] = lds[(row << A.logc) + it[u].col];
     }
 #pragma unroll
-  for (int u = 0; u < IPT; ++u) split_levels<Ring, K, !IS_X, IS_X>(R, v[u], v[u], t[u]);
+  for (int u = 0; u < IPT; ++u) {
+    if constexpr (TWL)
+      split_levels_d<Ring, K, !IS_X, IS_X>(R, v[u], v[u], t[u]);
+    else
+      split_levels<Ring, K, !IS_X, IS_X>(R, v[u], v[u], t[u]);
+  }
   hook();
 #pragma unroll
   for (int u = 0; u < IPT; ++u)
@@ -393,12 +413,13 @@ __global__ void __launch_bounds__(TopThreads<Ring>::value) k_split(PassArgs<Ring
 // tile's reads of one array overlap the writes of the other (the outputs are streamed out
 // with non-temporal stores, not held in L2 until the kernel ends). Every stage takes its
 // twiddles from an LDS copy of the tile's 2^R - 1 (the row and the vector split of a node
-// share g), loaded behind the row's elements so that no global load waits behind the
-// vector's. LDS holds two tiles and the twiddles.
+// share g), converted to the ring's deepest-stage form (Montgomery form for Z/p, one
+// instruction less per vector butterfly) and loaded behind the row's elements so that no
+// global load waits behind the vector's. LDS holds two tiles and the twiddles.
 // ---------------------------------------------------------------------------------------
 template <class Ring, int R>
 constexpr size_t split_ax_lds_bytes(size_t tile) {
-  return 2 * tile * sizeof(typename Ring::T) + (((size_t)1 << R) - 1) * sizeof(typename Ring::Tw);
+  return 2 * tile * sizeof(typename Ring::T) + (((size_t)1 << R) - 1) * sizeof(typename Ring::DeepW);
 }
 
 template <class Ring, int R, class SrcA, class SrcX, class Dst>
@@ -415,7 +436,7 @@ __global__ void __launch_bounds__(TopThreads<Ring>::value) k_split_ax(PassArgs<R
   const size_t tile = (size_t)1 << (A.logr + A.logc);
   T* lda = reinterpret_cast<T*>(smem_raw);
   T* ldx = lda + tile;
-  Tw* stw = reinterpret_cast<Tw*>(ldx + tile);
+  typename Ring::DeepW* stw = reinterpret_cast<typename Ring::DeepW*>(ldx + tile);
   const Tw* tw = A.tw[rsel];
   const uint32_t nt = blockDim.x, tid = threadIdx.x;
   StagePre<Ring, K0> pa, px;
@@ -424,7 +445,7 @@ __global__ void __launch_bounds__(TopThreads<Ring>::value) k_split_ax(PassArgs<R
   // level l of the tile is the contiguous heap range [2^(d0+l) + blk 2^l, + 2^l)
   for (uint32_t e = tid; e < (1u << R) - 1; e += nt) {
     const uint32_t l = 31u - __clz(e + 1);
-    stw[e] = tw[(1u << (A.d0 + l)) + (P.blk << l) + (e + 1 - (1u << l))];
+    stw[e] = Rg.to_deep(tw[(1u << (A.d0 + l)) + (P.blk << l) + (e + 1 - (1u << l))]);
   }
   __syncthreads();
   const auto prefetch_x = [&] {
@@ -577,7 +598,7 @@ struct BlockShape {
 template <class Ring, int LOGR, int NT = 0>
 constexpr size_t block_lds_bytes() {
   using S = BlockShape<LOGR, NT>;
-  return (size_t)S::GROUPS * (2 * (sizeof(typename Ring::T) << LOGR) + 2 * (size_t)S::NTW * sizeof(typename Ring::Tw));
+  return (size_t)S::GROUPS * (2 * (sizeof(typename Ring::T) << LOGR) + 2 * (size_t)S::NTW * sizeof(typename Ring::DeepW));
 }
 
 // First twiddles of the deepest radix-16 stage (one item per thread), split and merge,
@@ -628,7 +649,7 @@ __device__ __forceinline__ void load_deep_tw(DeepTw<Ring>& D, const Ring& R, con
 template <class Ring, int LOGR, int K, bool FIRST, bool DEEPEST, class SrcA, class SrcX, class Dst>
 __device__ __forceinline__ void block_split_stage(const PassArgs<Ring>& A, const TilePos& P, const Ring& R, uint32_t rsel,
                                                   typename Ring::Tw const* tw, typename Ring::Tw const* twi,
-                                                  const typename Ring::Tw* stw, const DeepTw<Ring>& D,
+                                                  const typename Ring::DeepW* stw, const DeepTw<Ring>& D,
                                                   typename Ring::T* sa, typename Ring::T* sx, uint32_t l0, uint32_t ltid,
                                                   const SrcA& srca, const SrcX& srcx, const Dst& dst) {
   using T = typename Ring::T;
@@ -642,7 +663,10 @@ __device__ __forceinline__ void block_split_stage(const PassArgs<Ring>& A, const
   constexpr bool FIRSTS = DEEPEST && K == EPT_LOG;
   static_assert(!FROM_D || K == EPT_LOG, "deepest stage of a multi-stage block pass is radix 16");
   T va[IPT][E], vx[IPT][E];
-  Tw t[(FROM_D || FIRSTS) ? 1 : IPT][E - 1];
+  // a first stage loads its twiddles from the heap tables (Shoup form), later stages from
+  // the LDS copy (deepest-stage form)
+  using TwS = std::conditional_t<FIRST, Tw, typename Ring::DeepW>;
+  TwS t[(FROM_D || FIRSTS) ? 1 : IPT][E - 1];
   Tw ti[(DEEPEST && !FROM_D && !FIRSTS) ? IPT : 1][E - 1];
   DeepTw<Ring> Dl[FIRSTS && !FROM_D ? IPT : 1];  // single-stage radix-16 block: from the heap
   Item it[IPT];
@@ -679,8 +703,10 @@ __device__ __forceinline__ void block_split_stage(const PassArgs<Ring>& A, const
       split_levels_first<Ring, K>(R, va[u], vx[u], D.t, A.tu[rsel]);
     else if constexpr (FIRSTS)
       split_levels_first<Ring, K>(R, va[u], vx[u], Dl[u].t, A.tu[rsel]);
-    else
+    else if constexpr (FIRST)
       split_levels<Ring, K, true, true>(R, va[u], vx[u], t[u]);
+    else
+      split_levels_d<Ring, K, true, true>(R, va[u], vx[u], t[u]);
   }
   if constexpr (DEEPEST) {
 #pragma unroll
@@ -714,15 +740,14 @@ __device__ __forceinline__ void block_split_stage(const PassArgs<Ring>& A, const
 // One radix-2^K merge stage of the block pass (twiddles from the LDS copy). LAST: write dst.
 template <class Ring, int LOGR, int K, bool LAST, class Dst>
 __device__ __forceinline__ void block_merge_stage(const PassArgs<Ring>& A, const TilePos& P, const Ring& R,
-                                                  const typename Ring::Tw* stwi, typename Ring::T* sa, uint32_t l0,
+                                                  const typename Ring::DeepW* stwi, typename Ring::T* sa, uint32_t l0,
                                                   uint32_t ltid, const Dst& dst) {
   using T = typename Ring::T;
-  using Tw = typename Ring::Tw;
   using S = BlockShape<LOGR>;
   constexpr int E = 1 << K;
   constexpr int IPT = S::EPT / E;
   constexpr uint32_t ACTIVE = 1u << S::ACTIVE_LOG;
-  Tw t[IPT][E - 1];
+  typename Ring::DeepW t[IPT][E - 1];
   T v[IPT][E];
   Item it[IPT];
 #pragma unroll
@@ -735,7 +760,7 @@ __device__ __forceinline__ void block_merge_stage(const PassArgs<Ring>& A, const
 #pragma unroll
     for (int i = 0; i < E; ++i) v[u][i] = sa[it[u].row0 + ((uint32_t)i << it[u].sh)];
 #pragma unroll
-  for (int u = 0; u < IPT; ++u) merge_levels<Ring, K>(R, v[u], t[u]);
+  for (int u = 0; u < IPT; ++u) merge_levels_d<Ring, K>(R, v[u], t[u]);
 #pragma unroll
   for (int u = 0; u < IPT; ++u)
 #pragma unroll
@@ -765,8 +790,9 @@ __device__ __forceinline__ void block_pass(const PassArgs<Ring>& A, uint32_t vwg
   const bool active = group < S::GROUPS && vwg < A.tiles * A.ninst;
   T* sa = reinterpret_cast<T*>(smem_raw) + ((size_t)group << (LOGR + 1));
   T* sx = sa + ((size_t)1 << LOGR);
-  Tw* stw = reinterpret_cast<Tw*>(smem_raw + (size_t)S::GROUPS * 2 * (sizeof(T) << LOGR)) + (size_t)group * 2 * S::NTW;
-  Tw* stwi = stw + S::NTW;
+  using DW = typename Ring::DeepW;
+  DW* stw = reinterpret_cast<DW*>(smem_raw + (size_t)S::GROUPS * 2 * (sizeof(T) << LOGR)) + (size_t)group * 2 * S::NTW;
+  DW* stwi = stw + S::NTW;
   const TilePos P = tile_pos(A, active ? vwg : 0);
   uint32_t rsel;
   const Ring R = make_ring(A, P.inst, rp0, rp1, rp2, &rsel);
@@ -783,13 +809,15 @@ __device__ __forceinline__ void block_pass(const PassArgs<Ring>& A, uint32_t vwg
     DeepTw<Ring> D;
     if constexpr (NST > 1) {
       if (active) {
-        // LDS copy of the twiddles above the deepest stage: level l of the block is the
+        // LDS copy of the twiddles above the deepest stage, in the ring's deepest-stage form
+        // (Montgomery form for Z/p: the vector split and the merge then take one instruction
+        // less per butterfly, and the copy is half the size): level l of the block is the
         // contiguous heap range [2^(d0+l) + blk 2^l, + 2^l)
         for (uint32_t e = ltid; e < (uint32_t)S::NTW; e += 1u << S::ACTIVE_LOG) {
           const uint32_t l = 31u - __clz(e + 1);
           const uint32_t gi = (1u << (A.d0 + l)) + (P.blk << l) + (e + 1 - (1u << l));
-          stw[e] = tw[gi];
-          stwi[e] = twi[gi];
+          stw[e] = R.to_deep(tw[gi]);
+          stwi[e] = R.to_deep(twi[gi]);
         }
         load_deep_tw<Ring, LOGR>(D, R, A, P, rsel, tw, twi, ltid);
       }
@@ -987,13 +1015,13 @@ __global__ void __launch_bounds__((SmallShape<LOGR, K>::NT)) k_small(PassArgs<Ri
 template <class Ring, int LOGR, int NT = 0>
 constexpr size_t lf_block_lds_bytes() {
   using S = BlockShape<LOGR, NT>;
-  return (size_t)S::GROUPS * ((sizeof(typename Ring::T) << LOGR) + 2 * (size_t)S::NTW * sizeof(typename Ring::Tw));
+  return (size_t)S::GROUPS * ((sizeof(typename Ring::T) << LOGR) + 2 * (size_t)S::NTW * sizeof(typename Ring::DeepW));
 }
 
 template <class Ring, int LOGR, int K, bool FIRST, bool DEEPEST, bool CONJ, class SrcX, class Lv, class Dst>
 __device__ __forceinline__ void lf_split_stage(const PassArgs<Ring>& A, const TilePos& P, const Ring& R, uint32_t rsel,
                                                typename Ring::Tw const* tw, typename Ring::Tw const* twi,
-                                               const typename Ring::Tw* stw, const DeepTw<Ring>& D, typename Ring::T* sx,
+                                               const typename Ring::DeepW* stw, const DeepTw<Ring>& D, typename Ring::T* sx,
                                                uint32_t l0, uint32_t ltid, const SrcX& srcx, const Lv& leaves,
                                                const Dst& dst) {
   using T = typename Ring::T;
@@ -1006,7 +1034,8 @@ __device__ __forceinline__ void lf_split_stage(const PassArgs<Ring>& A, const Ti
   constexpr bool FIRSTS = DEEPEST && K == EPT_LOG;
   static_assert(!FROM_D || K == EPT_LOG, "deepest stage of a multi-stage block pass is radix 16");
   T vx[IPT][E];
-  Tw t[(FROM_D || FIRSTS) ? 1 : IPT][E - 1];
+  using TwS = std::conditional_t<FIRST, Tw, typename Ring::DeepW>;  // heap (Shoup) or LDS copy
+  TwS t[(FROM_D || FIRSTS) ? 1 : IPT][E - 1];
   Tw ti[(DEEPEST && !FROM_D && !FIRSTS) ? IPT : 1][E - 1];
   DeepTw<Ring> Dl[FIRSTS && !FROM_D ? IPT : 1];  // single-stage radix-16 block: from the heap
   Item it[IPT];
@@ -1040,8 +1069,10 @@ __device__ __forceinline__ void lf_split_stage(const PassArgs<Ring>& A, const Ti
       split_levels_first<Ring, K, false, true>(R, vx[u], vx[u], D.t, A.tu[rsel]);
     else if constexpr (FIRSTS)
       split_levels_first<Ring, K, false, true>(R, vx[u], vx[u], Dl[u].t, A.tu[rsel]);
-    else
+    else if constexpr (FIRST)
       split_levels<Ring, K, false, true>(R, vx[u], vx[u], t[u]);
+    else
+      split_levels_d<Ring, K, false, true>(R, vx[u], vx[u], t[u]);
   }
   if constexpr (DEEPEST) {
 #pragma unroll
@@ -1086,8 +1117,9 @@ __device__ __forceinline__ void lf_block_pass(const PassArgs<Ring>& A, uint32_t 
   const uint32_t vwg = vwg0 + group;
   const bool active = group < S::GROUPS && vwg < A.tiles * A.ninst;
   T* sx = reinterpret_cast<T*>(smem_raw) + ((size_t)group << LOGR);
-  Tw* stw = reinterpret_cast<Tw*>(smem_raw + (size_t)S::GROUPS * (sizeof(T) << LOGR)) + (size_t)group * 2 * S::NTW;
-  Tw* stwi = stw + S::NTW;
+  using DW = typename Ring::DeepW;
+  DW* stw = reinterpret_cast<DW*>(smem_raw + (size_t)S::GROUPS * (sizeof(T) << LOGR)) + (size_t)group * 2 * S::NTW;
+  DW* stwi = stw + S::NTW;
   const TilePos P = tile_pos(A, active ? vwg : 0);
   const uint32_t rsel = 0;
   const Ring R(rp);
@@ -1100,8 +1132,8 @@ __device__ __forceinline__ void lf_block_pass(const PassArgs<Ring>& A, uint32_t 
       for (uint32_t e = ltid; e < (uint32_t)S::NTW; e += 1u << S::ACTIVE_LOG) {
         const uint32_t l = 31u - __clz(e + 1);
         const uint32_t gi = (1u << (A.d0 + l)) + (P.blk << l) + (e + 1 - (1u << l));
-        stw[e] = tw[gi];
-        stwi[e] = twi[gi];
+        stw[e] = R.to_deep(tw[gi]);
+        stwi[e] = R.to_deep(twi[gi]);
       }
       load_deep_tw<Ring, LOGR>(D, R, A, P, rsel, tw, twi, ltid);
     }
@@ -1159,8 +1191,9 @@ __device__ __forceinline__ void acc_block_pass(const PassArgs<Ring>& A, uint32_t
   const uint32_t ltid = tid;
   T* sa = reinterpret_cast<T*>(smem_raw);
   T* sx = sa + ((size_t)1 << LOGR);
-  Tw* stw = reinterpret_cast<Tw*>(smem_raw + 2 * (sizeof(T) << LOGR));
-  Tw* stwi = stw + S::NTW;
+  using DW = typename Ring::DeepW;
+  DW* stw = reinterpret_cast<DW*>(smem_raw + 2 * (sizeof(T) << LOGR));
+  DW* stwi = stw + S::NTW;
   const Ring R(rp);
   const Tw* tw = A.tw[0];
   const Tw* twi = A.twi[0];
@@ -1168,8 +1201,8 @@ __device__ __forceinline__ void acc_block_pass(const PassArgs<Ring>& A, uint32_t
   for (uint32_t e = ltid; e < (uint32_t)S::NTW; e += 1u << S::ACTIVE_LOG) {
     const uint32_t l = 31u - __clz(e + 1);
     const uint32_t gi = (1u << (A.d0 + l)) + (P0.blk << l) + (e + 1 - (1u << l));
-    stw[e] = tw[gi];
-    stwi[e] = twi[gi];
+    stw[e] = R.to_deep(tw[gi]);
+    stwi[e] = R.to_deep(twi[gi]);
   }
   DeepTw<Ring> D;
   load_deep_tw<Ring, LOGR>(D, R, A, P0, 0, tw, twi, ltid);

@@ -108,6 +108,7 @@ ZpParams zp_params(uint32_t p, int L) {
   uint32_t inv = p;  // Newton iteration for p^-1 mod 2^32 (p odd)
   for (int i = 0; i < 5; ++i) inv *= 2u - p * inv;
   q.pinv = inv;
+  q.npinv = 0u - inv;
   const uint32_t two32 = (uint32_t)(((uint64_t)1 << 32) % p);
   const uint32_t ninv = invmod(powmod(2, (uint64_t)L, p), p);
   q.leaf = shoup_tw(mulmod(two32, ninv, p), p);
