@@ -286,10 +286,19 @@ def circulant_vs_fft(torch, F, W, quick: bool):
 
     def classic(i):
         return torch.fft.ifft(torch.fft.fft(tb) * torch.fft.fft(tx))
+    torch.cuda.synchronize()
+    yh = ty.cpu().numpy()  # the circulant product, copied out before the FFT side runs
     ms_f = time_steps(torch, classic, 20 if quick else 200, 10)
-    yc = classic(0)
-    rel = float(torch.linalg.vector_norm(ty - yc) / torch.linalg.vector_norm(yc))
-    return {"circulant_ms": ms_c, "fft_ms": ms_f, "fft_over_circulant": ms_f / ms_c, "rel_l2_between": rel,
+    yc = classic(0).cpu().numpy()
+    # both results against the FP64 evaluation of the definition (cyclic correlation by a
+    # host FFT), and against each other, on host copies
+    yd = np.fft.ifft(np.fft.fft(a.astype(np.complex128)[(-np.arange(n)) % n]) * np.fft.fft(x.astype(np.complex128)))
+    nd = np.linalg.norm(yd)
+    return {"circulant_ms": ms_c, "fft_ms": ms_f, "fft_over_circulant": ms_f / ms_c,
+            "rel_l2_between": float(np.linalg.norm(yh - yc) / np.linalg.norm(yc)),
+            "rel_l2_circulant_vs_fp64": float(np.linalg.norm(yh - yd) / nd),
+            "rel_l2_fft_vs_fp64": float(np.linalg.norm(yc - yd) / nd),
+            "output_changed_after": bool(not np.array_equal(ty.cpu().numpy(), yh)),
             **fractions(24 * n, 3 * FP32_OPS_PER_COEF_LEVEL_TRANSFORM * 21 * n, ms_c)}
 
 
