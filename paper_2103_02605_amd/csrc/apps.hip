@@ -22,15 +22,25 @@ namespace {
 
 constexpr uint32_t Q1 = 998244353u, Q2 = 469762049u, Q3 = 167772161u;
 
+// Both loaders read unconditionally (element 0 when the index is past the data: na and nb
+// are at least 1) and select zero afterwards, so the loads of a stage are all issued before
+// the first wait instead of one branch, load and wait per element.
+template <class V>
+__device__ __forceinline__ uint32_t residue_of(const Zp& R, V v) {
+  if constexpr (sizeof(V) == 4)
+    return R.from_i32((int32_t)v);
+  else
+    return (uint32_t)v;
+}
 template <class V>
 struct LdRowRev {  // r_k = a_((N - k) mod N), zero beyond na
   const V* a;
   uint64_t na, N;
   __device__ __forceinline__ uint32_t operator()(const Zp& R, uint32_t, uint32_t k) const {
     const uint64_t j = k == 0 ? 0 : N - k;
-    if (j >= na) return 0u;
-    if constexpr (sizeof(V) == 4) return R.from_i32((int32_t)a[j]);
-    else return (uint32_t)a[j];
+    const bool in = j < na;
+    const uint32_t r = residue_of(R, a[in ? j : 0]);
+    return in ? r : 0u;
   }
 };
 template <class V>
@@ -38,9 +48,9 @@ struct LdVecPad {  // b_k, zero beyond nb
   const V* b;
   uint64_t nb;
   __device__ __forceinline__ uint32_t operator()(const Zp& R, uint32_t, uint32_t k) const {
-    if (k >= nb) return 0u;
-    if constexpr (sizeof(V) == 4) return R.from_i32((int32_t)b[k]);
-    else return (uint32_t)b[k];
+    const bool in = k < nb;
+    const uint32_t r = residue_of(R, b[in ? k : 0]);
+    return in ? r : 0u;
   }
 };
 

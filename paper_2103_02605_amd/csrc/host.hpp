@@ -369,8 +369,21 @@ inline hipError_t launch_block_l(Ctx& c, const PassArgs<Ring>& A, const typename
   using S = BlockShape<LOGR>;
   const uint64_t vwgs = (uint64_t)A.tiles * A.ninst;
   const uint32_t grid = (uint32_t)((vwgs + S::GROUPS - 1) / S::GROUPS);
-  const size_t lds = block_lds_bytes<Ring, LOGR>();
-  auto k = k_block<Ring, LOGR, SrcA, SrcX, Dst>;
+  // Up to one workgroup per CU: Montgomery-form staged twiddles (fewer instructions). More:
+  // Shoup pairs, whose kernel needs fewer registers, so that two 2^13-element blocks fit a
+  // CU (measured: three 2^21 products over Z/p, block pass 52.9 -> 46.6 us; one, 19.4 ->
+  // 18.3 us the other way).
+  // (Rings whose deepest-stage form is the heap form compile one kernel.)
+  constexpr bool same = std::is_same_v<typename Ring::Tw, typename Ring::DeepW>;
+  const bool mont = same || grid <= (uint32_t)c.prop.multiProcessorCount;
+  size_t lds = block_lds_bytes<Ring, LOGR, 0, true>();
+  auto k = k_block<Ring, LOGR, SrcA, SrcX, Dst, true>;
+  if constexpr (!same) {
+    if (!mont) {
+      lds = block_lds_bytes<Ring, LOGR, 0, false>();
+      k = k_block<Ring, LOGR, SrcA, SrcX, Dst, false>;
+    }
+  }
   allow_lds(k, lds);
   return launch(c, "fcirc_block", s, [&](hipEvent_t e0_, hipEvent_t e1_) { FCIRC_LAUNCH(e0_, e1_, k, dim3(grid), dim3(S::NT), lds, s, A, rp[0], rp[1], rp[2], sa, sx, d); });
 }

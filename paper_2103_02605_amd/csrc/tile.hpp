@@ -228,6 +228,19 @@ __device__ __forceinline__ void merge_levels_first(const Ring& R, typename Ring:
   merge_levels_d<Ring, K>(R, vy, w);
 }
 
+// Form of the twiddles a block pass stages in LDS. MONT: the ring's deepest-stage form
+// (Montgomery words for Z/p: fewer instructions per butterfly and half the LDS, but more
+// registers); otherwise its heap form (Shoup pairs).
+template <class Ring, bool MONT>
+using BlockTw = std::conditional_t<MONT, typename Ring::DeepW, typename Ring::Tw>;
+template <class Ring, bool MONT>
+__device__ __forceinline__ BlockTw<Ring, MONT> to_block_tw(const Ring& R, typename Ring::Tw t) {
+  if constexpr (std::is_same_v<BlockTw<Ring, MONT>, typename Ring::Tw>)
+    return t;
+  else
+    return R.to_deep(t);
+}
+
 // K split levels on the registers of one item, for the row (a) and/or the vector (x).
 template <class Ring, int K, bool DA, bool DX>
 __device__ __forceinline__ void split_levels(const Ring& R, typename Ring::T* va, typename Ring::T* vx,
@@ -262,6 +275,23 @@ __device__ __forceinline__ void merge_levels(const Ring& R, typename Ring::T* vy
       }
     }
   }
+}
+
+// K split (merge) levels with twiddles of either form: the heap form (Shoup pair) or the
+// deepest-stage form.
+template <class Ring, int K, bool DA, bool DX, class W>
+__device__ __forceinline__ void split_levels_w(const Ring& R, typename Ring::T* va, typename Ring::T* vx, const W* t) {
+  if constexpr (std::is_same_v<W, typename Ring::Tw>)
+    split_levels<Ring, K, DA, DX>(R, va, vx, t);
+  else
+    split_levels_d<Ring, K, DA, DX>(R, va, vx, t);
+}
+template <class Ring, int K, class W>
+__device__ __forceinline__ void merge_levels_w(const Ring& R, typename Ring::T* vy, const W* t) {
+  if constexpr (std::is_same_v<W, typename Ring::Tw>)
+    merge_levels<Ring, K>(R, vy, t);
+  else
+    merge_levels_d<Ring, K>(R, vy, t);
 }
 
 template <class Ring>
@@ -595,10 +625,10 @@ struct BlockShape {
 
 // LDS of a block pass: [GROUPS][row, vector][2^LOGR] elements, then [GROUPS][split, merge][NTW]
 // twiddles (local heap order: level l, node b at 2^l - 1 + b).
-template <class Ring, int LOGR, int NT = 0>
+template <class Ring, int LOGR, int NT = 0, bool MONT = true>
 constexpr size_t block_lds_bytes() {
   using S = BlockShape<LOGR, NT>;
-  return (size_t)S::GROUPS * (2 * (sizeof(typename Ring::T) << LOGR) + 2 * (size_t)S::NTW * sizeof(typename Ring::DeepW));
+  return (size_t)S::GROUPS * (2 * (sizeof(typename Ring::T) << LOGR) + 2 * (size_t)S::NTW * sizeof(BlockTw<Ring, MONT>));
 }
 
 // First twiddles of the deepest radix-16 stage (one item per thread), split and merge,
@@ -646,10 +676,10 @@ __device__ __forceinline__ void load_deep_tw(DeepTw<Ring>& D, const Ring& R, con
 // One split stage of the block pass on row and vector. FIRST: elements come from global
 // memory (twiddles too); otherwise from LDS. DEEPEST: the stage also forms the leaf
 // products and runs its merge levels, leaving y in sa (or writing dst if also FIRST).
-template <class Ring, int LOGR, int K, bool FIRST, bool DEEPEST, class SrcA, class SrcX, class Dst>
+template <class Ring, int LOGR, int K, bool FIRST, bool DEEPEST, class W, class SrcA, class SrcX, class Dst>
 __device__ __forceinline__ void block_split_stage(const PassArgs<Ring>& A, const TilePos& P, const Ring& R, uint32_t rsel,
                                                   typename Ring::Tw const* tw, typename Ring::Tw const* twi,
-                                                  const typename Ring::DeepW* stw, const DeepTw<Ring>& D,
+                                                  const W* stw, const DeepTw<Ring>& D,
                                                   typename Ring::T* sa, typename Ring::T* sx, uint32_t l0, uint32_t ltid,
                                                   const SrcA& srca, const SrcX& srcx, const Dst& dst) {
   using T = typename Ring::T;
@@ -665,7 +695,7 @@ __device__ __forceinline__ void block_split_stage(const PassArgs<Ring>& A, const
   T va[IPT][E], vx[IPT][E];
   // a first stage loads its twiddles from the heap tables (Shoup form), later stages from
   // the LDS copy (deepest-stage form)
-  using TwS = std::conditional_t<FIRST, Tw, typename Ring::DeepW>;
+  using TwS = std::conditional_t<FIRST, Tw, W>;
   TwS t[(FROM_D || FIRSTS) ? 1 : IPT][E - 1];
   Tw ti[(DEEPEST && !FROM_D && !FIRSTS) ? IPT : 1][E - 1];
   DeepTw<Ring> Dl[FIRSTS && !FROM_D ? IPT : 1];  // single-stage radix-16 block: from the heap
@@ -703,10 +733,8 @@ __device__ __forceinline__ void block_split_stage(const PassArgs<Ring>& A, const
       split_levels_first<Ring, K>(R, va[u], vx[u], D.t, A.tu[rsel]);
     else if constexpr (FIRSTS)
       split_levels_first<Ring, K>(R, va[u], vx[u], Dl[u].t, A.tu[rsel]);
-    else if constexpr (FIRST)
-      split_levels<Ring, K, true, true>(R, va[u], vx[u], t[u]);
     else
-      split_levels_d<Ring, K, true, true>(R, va[u], vx[u], t[u]);
+      split_levels_w<Ring, K, true, true>(R, va[u], vx[u], t[u]);
   }
   if constexpr (DEEPEST) {
 #pragma unroll
@@ -738,16 +766,16 @@ __device__ __forceinline__ void block_split_stage(const PassArgs<Ring>& A, const
 }
 
 // One radix-2^K merge stage of the block pass (twiddles from the LDS copy). LAST: write dst.
-template <class Ring, int LOGR, int K, bool LAST, class Dst>
+template <class Ring, int LOGR, int K, bool LAST, class W, class Dst>
 __device__ __forceinline__ void block_merge_stage(const PassArgs<Ring>& A, const TilePos& P, const Ring& R,
-                                                  const typename Ring::DeepW* stwi, typename Ring::T* sa, uint32_t l0,
+                                                  const W* stwi, typename Ring::T* sa, uint32_t l0,
                                                   uint32_t ltid, const Dst& dst) {
   using T = typename Ring::T;
   using S = BlockShape<LOGR>;
   constexpr int E = 1 << K;
   constexpr int IPT = S::EPT / E;
   constexpr uint32_t ACTIVE = 1u << S::ACTIVE_LOG;
-  typename Ring::DeepW t[IPT][E - 1];
+  W t[IPT][E - 1];
   T v[IPT][E];
   Item it[IPT];
 #pragma unroll
@@ -760,7 +788,7 @@ __device__ __forceinline__ void block_merge_stage(const PassArgs<Ring>& A, const
 #pragma unroll
     for (int i = 0; i < E; ++i) v[u][i] = sa[it[u].row0 + ((uint32_t)i << it[u].sh)];
 #pragma unroll
-  for (int u = 0; u < IPT; ++u) merge_levels_d<Ring, K>(R, v[u], t[u]);
+  for (int u = 0; u < IPT; ++u) merge_levels_w<Ring, K>(R, v[u], t[u]);
 #pragma unroll
   for (int u = 0; u < IPT; ++u)
 #pragma unroll
@@ -776,7 +804,7 @@ __device__ __forceinline__ void block_merge_stage(const PassArgs<Ring>& A, const
 // The block pass for workgroup-local virtual workgroups vwg0 .. vwg0 + GROUPS - 1 (NT threads;
 // each group of 2^(LOGR-4) threads owns one block). smem_raw holds block_lds_bytes<Ring,
 // LOGR, NT>() bytes. tid is the thread's index in the workgroup.
-template <class Ring, int LOGR, int NT, class SrcA, class SrcX, class Dst>
+template <class Ring, int LOGR, int NT, bool MONT = true, class SrcA, class SrcX, class Dst>
 __device__ __forceinline__ void block_pass(const PassArgs<Ring>& A, uint32_t vwg0, uint32_t tid, unsigned char* smem_raw,
                                            const typename Ring::Params& rp0, const typename Ring::Params& rp1,
                                            const typename Ring::Params& rp2, const SrcA& srca, const SrcX& srcx,
@@ -790,7 +818,7 @@ __device__ __forceinline__ void block_pass(const PassArgs<Ring>& A, uint32_t vwg
   const bool active = group < S::GROUPS && vwg < A.tiles * A.ninst;
   T* sa = reinterpret_cast<T*>(smem_raw) + ((size_t)group << (LOGR + 1));
   T* sx = sa + ((size_t)1 << LOGR);
-  using DW = typename Ring::DeepW;
+  using DW = BlockTw<Ring, MONT>;
   DW* stw = reinterpret_cast<DW*>(smem_raw + (size_t)S::GROUPS * 2 * (sizeof(T) << LOGR)) + (size_t)group * 2 * S::NTW;
   DW* stwi = stw + S::NTW;
   const TilePos P = tile_pos(A, active ? vwg : 0);
@@ -816,8 +844,8 @@ __device__ __forceinline__ void block_pass(const PassArgs<Ring>& A, uint32_t vwg
         for (uint32_t e = ltid; e < (uint32_t)S::NTW; e += 1u << S::ACTIVE_LOG) {
           const uint32_t l = 31u - __clz(e + 1);
           const uint32_t gi = (1u << (A.d0 + l)) + (P.blk << l) + (e + 1 - (1u << l));
-          stw[e] = R.to_deep(tw[gi]);
-          stwi[e] = R.to_deep(twi[gi]);
+          stw[e] = to_block_tw<Ring, MONT>(R, tw[gi]);
+          stwi[e] = to_block_tw<Ring, MONT>(R, twi[gi]);
         }
         load_deep_tw<Ring, LOGR>(D, R, A, P, rsel, tw, twi, ltid);
       }
@@ -1015,13 +1043,13 @@ __global__ void __launch_bounds__((SmallShape<LOGR, K>::NT)) k_small(PassArgs<Ri
 template <class Ring, int LOGR, int NT = 0>
 constexpr size_t lf_block_lds_bytes() {
   using S = BlockShape<LOGR, NT>;
-  return (size_t)S::GROUPS * ((sizeof(typename Ring::T) << LOGR) + 2 * (size_t)S::NTW * sizeof(typename Ring::DeepW));
+  return (size_t)S::GROUPS * ((sizeof(typename Ring::T) << LOGR) + 2 * (size_t)S::NTW * sizeof(BlockTw<Ring, true>));
 }
 
 template <class Ring, int LOGR, int K, bool FIRST, bool DEEPEST, bool CONJ, class SrcX, class Lv, class Dst>
 __device__ __forceinline__ void lf_split_stage(const PassArgs<Ring>& A, const TilePos& P, const Ring& R, uint32_t rsel,
                                                typename Ring::Tw const* tw, typename Ring::Tw const* twi,
-                                               const typename Ring::DeepW* stw, const DeepTw<Ring>& D, typename Ring::T* sx,
+                                               const BlockTw<Ring, true>* stw, const DeepTw<Ring>& D, typename Ring::T* sx,
                                                uint32_t l0, uint32_t ltid, const SrcX& srcx, const Lv& leaves,
                                                const Dst& dst) {
   using T = typename Ring::T;
@@ -1034,7 +1062,7 @@ __device__ __forceinline__ void lf_split_stage(const PassArgs<Ring>& A, const Ti
   constexpr bool FIRSTS = DEEPEST && K == EPT_LOG;
   static_assert(!FROM_D || K == EPT_LOG, "deepest stage of a multi-stage block pass is radix 16");
   T vx[IPT][E];
-  using TwS = std::conditional_t<FIRST, Tw, typename Ring::DeepW>;  // heap (Shoup) or LDS copy
+  using TwS = std::conditional_t<FIRST, Tw, BlockTw<Ring, true>>;  // heap (Shoup) or LDS copy
   TwS t[(FROM_D || FIRSTS) ? 1 : IPT][E - 1];
   Tw ti[(DEEPEST && !FROM_D && !FIRSTS) ? IPT : 1][E - 1];
   DeepTw<Ring> Dl[FIRSTS && !FROM_D ? IPT : 1];  // single-stage radix-16 block: from the heap
@@ -1069,10 +1097,8 @@ __device__ __forceinline__ void lf_split_stage(const PassArgs<Ring>& A, const Ti
       split_levels_first<Ring, K, false, true>(R, vx[u], vx[u], D.t, A.tu[rsel]);
     else if constexpr (FIRSTS)
       split_levels_first<Ring, K, false, true>(R, vx[u], vx[u], Dl[u].t, A.tu[rsel]);
-    else if constexpr (FIRST)
-      split_levels<Ring, K, false, true>(R, vx[u], vx[u], t[u]);
     else
-      split_levels_d<Ring, K, false, true>(R, vx[u], vx[u], t[u]);
+      split_levels_w<Ring, K, false, true>(R, vx[u], vx[u], t[u]);
   }
   if constexpr (DEEPEST) {
 #pragma unroll
@@ -1117,7 +1143,7 @@ __device__ __forceinline__ void lf_block_pass(const PassArgs<Ring>& A, uint32_t 
   const uint32_t vwg = vwg0 + group;
   const bool active = group < S::GROUPS && vwg < A.tiles * A.ninst;
   T* sx = reinterpret_cast<T*>(smem_raw) + ((size_t)group << LOGR);
-  using DW = typename Ring::DeepW;
+  using DW = BlockTw<Ring, true>;
   DW* stw = reinterpret_cast<DW*>(smem_raw + (size_t)S::GROUPS * (sizeof(T) << LOGR)) + (size_t)group * 2 * S::NTW;
   DW* stwi = stw + S::NTW;
   const TilePos P = tile_pos(A, active ? vwg : 0);
@@ -1132,8 +1158,8 @@ __device__ __forceinline__ void lf_block_pass(const PassArgs<Ring>& A, uint32_t 
       for (uint32_t e = ltid; e < (uint32_t)S::NTW; e += 1u << S::ACTIVE_LOG) {
         const uint32_t l = 31u - __clz(e + 1);
         const uint32_t gi = (1u << (A.d0 + l)) + (P.blk << l) + (e + 1 - (1u << l));
-        stw[e] = R.to_deep(tw[gi]);
-        stwi[e] = R.to_deep(twi[gi]);
+        stw[e] = to_block_tw<Ring, true>(R, tw[gi]);
+        stwi[e] = to_block_tw<Ring, true>(R, twi[gi]);
       }
       load_deep_tw<Ring, LOGR>(D, R, A, P, rsel, tw, twi, ltid);
     }
@@ -1191,7 +1217,7 @@ __device__ __forceinline__ void acc_block_pass(const PassArgs<Ring>& A, uint32_t
   const uint32_t ltid = tid;
   T* sa = reinterpret_cast<T*>(smem_raw);
   T* sx = sa + ((size_t)1 << LOGR);
-  using DW = typename Ring::DeepW;
+  using DW = BlockTw<Ring, true>;
   DW* stw = reinterpret_cast<DW*>(smem_raw + 2 * (sizeof(T) << LOGR));
   DW* stwi = stw + S::NTW;
   const Ring R(rp);
@@ -1201,8 +1227,8 @@ __device__ __forceinline__ void acc_block_pass(const PassArgs<Ring>& A, uint32_t
   for (uint32_t e = ltid; e < (uint32_t)S::NTW; e += 1u << S::ACTIVE_LOG) {
     const uint32_t l = 31u - __clz(e + 1);
     const uint32_t gi = (1u << (A.d0 + l)) + (P0.blk << l) + (e + 1 - (1u << l));
-    stw[e] = R.to_deep(tw[gi]);
-    stwi[e] = R.to_deep(twi[gi]);
+    stw[e] = to_block_tw<Ring, true>(R, tw[gi]);
+    stwi[e] = to_block_tw<Ring, true>(R, twi[gi]);
   }
   DeepTw<Ring> D;
   load_deep_tw<Ring, LOGR>(D, R, A, P0, 0, tw, twi, ltid);
@@ -1248,13 +1274,13 @@ __global__ void __launch_bounds__(BlockShape<LOGR>::NT) k_acc_block(PassArgs<Rin
   acc_block_pass<Ring, LOGR>(A, blk, b0, b1, chunk, threadIdx.x, smem_raw, rp, srca, srcx, out);
 }
 
-template <class Ring, int LOGR, class SrcA, class SrcX, class Dst>
+template <class Ring, int LOGR, class SrcA, class SrcX, class Dst, bool MONT = true>
 __global__ void __launch_bounds__(BlockShape<LOGR>::NT) k_block(PassArgs<Ring> A, typename Ring::Params rp0,
                                                                  typename Ring::Params rp1, typename Ring::Params rp2,
                                                                  SrcA srca, SrcX srcx, Dst dst) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   using S = BlockShape<LOGR>;
-  block_pass<Ring, LOGR, S::NT>(A, blockIdx.x * S::GROUPS, threadIdx.x, smem_raw, rp0, rp1, rp2, srca, srcx, dst);
+  block_pass<Ring, LOGR, S::NT, MONT>(A, blockIdx.x * S::GROUPS, threadIdx.x, smem_raw, rp0, rp1, rp2, srca, srcx, dst);
 }
 
 }  // namespace fcirc
