@@ -3,15 +3,17 @@
 // instance). The queue built for an item list is kept and reused when the same list comes
 // again, so a repeated batch costs two launches (counter reset, persistent kernel).
 //
-// Work items, issued from one queue in this order:
+// Work items, issued from one queue:
 //   SPLIT  one top-split tile (row or vector) of a large instance
 //   FULL   a group of small instances of one size, each a whole product (split, leaf
 //          products, merge) by one group of threads of the workgroup
 //   BLOCK  LDS-resident blocks of a large instance (waits for all of its SPLIT tiles)
 //   MERGE  one top-merge tile of a large instance (waits for all of its BLOCK items)
-// Large instances are ordered largest first. Every item waits only for items that sit
-// earlier in the queue, which some running workgroup has already taken, so waits end;
-// each wait is also bounded and reports an error instead of spinning forever.
+// Large instances are ordered largest first and taken in groups; the queue is pipelined
+// over the groups (SPLITs of one group, BLOCKs of the previous, MERGEs of the one before,
+// FULL items spread between). Every item waits only for items that sit earlier in the
+// queue, which some running workgroup has already taken, so waits end; each wait is also
+// bounded and reports an error instead of spinning forever.
 //
 // Parameters by size. The workgroup size of a launch (256 or 512 threads, 16 elements per
 // thread per stage) fixes the largest FULL instance and the top-pass tile (2^12 or 2^13
@@ -35,6 +37,12 @@ namespace fcirc {
 namespace {
 
 constexpr uint32_t SPIN_LIMIT = 1u << 24;
+// Split outputs per group of large instances in the pipelined queue (see build_and_launch).
+// Measured for 4096 complex instances of 2^6..2^16 on MI355X: 2, 4, 8, 16, 32, 64 MiB and one
+// group gave 1344, 1089, 922, 795, 809, 856 and 851 us per batch. Smaller groups leave the
+// BLOCK items of a group waiting for its SPLIT tiles; larger ones let the intermediates
+// leave the last-level cache before they are read back.
+constexpr size_t GROUP_WS_BYTES = (size_t)16 << 20;
 
 enum : uint32_t { IT_SPLIT = 0, IT_FULL = 1, IT_BLOCK = 2, IT_MERGE = 3 };
 
@@ -477,11 +485,6 @@ fcirc_status build_and_launch(Ctx& c, const std::vector<uint64_t>& key, fcirc_ri
     }
     insts[k] = b;
   }
-  std::vector<BItem> q;
-  // SPLIT tiles of the large instances (row and vector of each), largest first
-  for (uint32_t k = 0; k < count; ++k)
-    if (insts[k].big != ~0u)
-      for (uint32_t v = 0; v < insts[k].nsplit; ++v) q.push_back(BItem{IT_SPLIT, insts[k].L, k, v});
   // FULL items: consecutive instances of equal size, as many as one workgroup holds
   std::vector<BItem> full;
   for (uint32_t k = 0; k < count;) {
@@ -496,17 +499,46 @@ fcirc_status build_and_launch(Ctx& c, const std::vector<uint64_t>& key, fcirc_ri
     full.push_back(BItem{IT_FULL, L, k, m});
     k += m;
   }
-  const size_t half = full.size() / 2;
-  q.insert(q.end(), full.begin(), full.begin() + half);
-  for (uint32_t k = 0; k < count; ++k)
-    if (insts[k].big != ~0u) {
-      const uint32_t groups = (uint32_t)BT >> (insts[k].blog - EPT_LOG);
-      for (uint32_t b = 0; b < insts[k].nblock; ++b) q.push_back(BItem{IT_BLOCK, insts[k].L, k, b * groups});
+  // Large instances (largest first) in groups of about GROUP_WS_BYTES of split outputs. The
+  // queue is pipelined over the groups: the SPLIT tiles of group g + 1, then the BLOCK
+  // items of group g, then the MERGE tiles of group g - 1, with a share of the FULL items
+  // after each step. A group's intermediates are then read back soon after they are
+  // written, while they are still in the last-level cache, instead of after every large
+  // instance has been split. Every item still waits only for items earlier in the queue.
+  std::vector<std::pair<uint32_t, uint32_t>> groups;  // [first, last) instance ranges
+  for (uint32_t k = 0; k < count;) {
+    if (insts[k].big == ~0u) {
+      ++k;
+      continue;
     }
-  q.insert(q.end(), full.begin() + half, full.end());
-  for (uint32_t k = 0; k < count; ++k)
-    if (insts[k].big != ~0u)
-      for (uint32_t v = 0; v < insts[k].nsplit / 2; ++v) q.push_back(BItem{IT_MERGE, insts[k].L, k, v});
+    uint32_t e = k;
+    size_t bytes = 0;
+    while (e < count && insts[e].big != ~0u && (e == k || bytes + (sizeof(T) << (insts[e].L + 1)) <= GROUP_WS_BYTES)) {
+      bytes += sizeof(T) << (insts[e].L + 1);
+      ++e;
+    }
+    groups.emplace_back(k, e);
+    k = e;
+  }
+  const size_t ng = groups.size(), nsteps = ng + 2;
+  std::vector<BItem> q;
+  size_t fi = 0;
+  for (size_t step = 0; step < nsteps; ++step) {
+    if (step < ng)
+      for (uint32_t k = groups[step].first; k < groups[step].second; ++k)
+        for (uint32_t v = 0; v < insts[k].nsplit; ++v) q.push_back(BItem{IT_SPLIT, insts[k].L, k, v});
+    if (step >= 1 && step - 1 < ng)
+      for (uint32_t k = groups[step - 1].first; k < groups[step - 1].second; ++k) {
+        const uint32_t gpb = (uint32_t)BT >> (insts[k].blog - EPT_LOG);
+        for (uint32_t b = 0; b < insts[k].nblock; ++b) q.push_back(BItem{IT_BLOCK, insts[k].L, k, b * gpb});
+      }
+    if (step >= 2)
+      for (uint32_t k = groups[step - 2].first; k < groups[step - 2].second; ++k)
+        for (uint32_t v = 0; v < insts[k].nsplit / 2; ++v) q.push_back(BItem{IT_MERGE, insts[k].L, k, v});
+    const size_t fe = full.size() * (step + 1) / nsteps;
+    q.insert(q.end(), full.begin() + fi, full.begin() + fe);
+    fi = fe;
+  }
 
   BatchEntry* g = new BatchEntry;
   g->key = key;
