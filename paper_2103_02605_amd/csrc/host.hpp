@@ -373,8 +373,9 @@ inline hipError_t launch_block_l(Ctx& c, const PassArgs<Ring>& A, const typename
   // Shoup pairs, whose kernel needs fewer registers, so that two 2^13-element blocks fit a
   // CU (measured: three 2^21 products over Z/p, block pass 52.9 -> 46.6 us; one, 19.4 ->
   // 18.3 us the other way).
-  // (Rings whose deepest-stage form is the heap form compile one kernel.)
-  constexpr bool same = std::is_same_v<typename Ring::Tw, typename Ring::DeepW>;
+  // Only 2^13-element blocks have both forms: at 2^12 and 2^10 the two compile to the same
+  // register count, and rings whose deepest-stage form is the heap form have one kernel.
+  constexpr bool same = std::is_same_v<typename Ring::Tw, typename Ring::DeepW> || LOGR != 13;
   const bool mont = same || grid <= (uint32_t)c.prop.multiProcessorCount;
   size_t lds = block_lds_bytes<Ring, LOGR, 0, true>();
   auto k = k_block<Ring, LOGR, SrcA, SrcX, Dst, true>;

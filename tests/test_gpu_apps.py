@@ -40,6 +40,23 @@ def test_polymul_small(F, na, nb):
     F.check()
 
 
+@pytest.mark.parametrize("L", list(range(1, 15)))
+def test_polymul_bigint_every_size(F, L):
+    """Factors of 2^(L-1) coefficients (limbs), so that the three-prime products have
+    exactly 2^L elements: every schedule form of the product (small-product kernel, block
+    pass, top passes) meets the row-reversing and padding loaders."""
+    m = 1 << (L - 1)
+    rng = np.random.default_rng(1000 + L)
+    a = rng.integers(-(1 << 15), 1 << 15, m).astype(np.int32)
+    b = rng.integers(-(1 << 15), 1 << 15, m).astype(np.int32)
+    want = OP.poly_kronecker(a, b) if m * m > 10**6 else np.array(OP.poly_schoolbook(a, b), dtype=np.int64)
+    np.testing.assert_array_equal(F.polymul_i64(d(a), d(b)).cpu().numpy(), want)
+    ua = rng.integers(0, 1 << 16, m).astype(np.uint16)
+    ub = rng.integers(0, 1 << 16, m).astype(np.uint16)
+    np.testing.assert_array_equal(F.bigint_mul(d(ua), d(ub)).cpu().numpy().view(np.uint16), OB.bigint_mul_pyint(ua, ub))
+    F.check()
+
+
 def test_polymul_full_config(F):
     """2 x 2^20 int32 coefficients in [-2^15, 2^15) (seed 4): every coefficient against the
     oracle's three circulant products and textbook CRT."""

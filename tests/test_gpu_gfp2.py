@@ -30,7 +30,7 @@ def rand(n, seed):
     return np.random.default_rng(seed).integers(0, P, (n, 2)).astype(np.uint64)
 
 
-@pytest.mark.parametrize("L", [0, 1, 2, 4, 5, 8, 10, 12, 13, 16])
+@pytest.mark.parametrize("L", [0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 16])
 def test_gfp2_sizes_bit_exact(F, L):
     n = 1 << L
     a, x = rand(n, 100 + L), rand(n, 200 + L)

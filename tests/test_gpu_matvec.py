@@ -9,7 +9,11 @@ import numpy as np
 import pytest
 
 from oracle import fcirc as O
+from oracle import gfp2 as OG
+from paper_2103_02605_amd import _lib
 from paper_2103_02605_amd import workloads as W
+
+GP = OG.P  # 2^31 - 1, the ring of section 3.1
 
 pytestmark = pytest.mark.gpu
 
@@ -26,6 +30,12 @@ def F():
     fcirc.set_split(-1)
     yield fcirc
     fcirc.set_split(-1)
+
+
+def dev64(arr):
+    """(n, 2) residues of Z/p[sqrt 3] as the int32 pairs the binding takes."""
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(arr.astype(np.int32))).cuda()
 
 
 def dev(arr):
@@ -72,7 +82,7 @@ def test_all_sizes_bit_exact(F, p, L):
         np.testing.assert_array_equal(host_u32(y), oracle_modp(a, x, f, p), err_msg=f"p={p} n={n} f={f}")
 
 
-@pytest.mark.parametrize("ring", ["p1", "p2", "p3", "c64"])
+@pytest.mark.parametrize("ring", ["p1", "p2", "p3", "c64", "r32", "gfp2"])
 @pytest.mark.parametrize("L", list(range(6, 13)))
 def test_small_kernel_and_block_pass(F, ring, L):
     """Products of 2^6..2^12 with no top pass run as the several-wave small-product kernel
@@ -81,10 +91,24 @@ def test_small_kernel_and_block_pass(F, ring, L):
     1e-5 of the FP64 definition), alone and as a batch of 3."""
     import torch
     n = 1 << L
-    ring_id = {"p1": 0, "p2": 1, "p3": 2, "c64": 3}[ring]
+    ring_id = {"p1": 0, "p2": 1, "p3": 2, "c64": 3, "r32": _lib.FCIRC_R32, "gfp2": _lib.FCIRC_GFP2}[ring]
     try:
         for flags in (F.SCHED_XCD | F.SCHED_SMALL, F.SCHED_XCD):
             F.set_schedule(n, ring_id, 0, -1, flags)
+            if ring == "r32":
+                rng = np.random.default_rng(600 + L)
+                a = rng.standard_normal(n).astype(np.float32)
+                x = rng.standard_normal(n).astype(np.float32)
+                y = F.matvec(torch.from_numpy(a).cuda(), torch.from_numpy(x).cuda()).cpu().numpy()
+                want = O.dense_matvec_c128(a.astype(np.complex128), x.astype(np.complex128), 1.0).real
+                assert np.linalg.norm(y - want) / np.linalg.norm(want) < 1e-5, (L, flags)
+                continue
+            if ring == "gfp2":
+                a = np.random.default_rng(700 + L).integers(0, GP, (n, 2)).astype(np.uint64)
+                x = np.random.default_rng(800 + L).integers(0, GP, (n, 2)).astype(np.uint64)
+                y = F.matvec(dev64(a), dev64(x), f=1, p=GP).cpu().numpy().astype(np.uint64)
+                np.testing.assert_array_equal(y, OG.levels_matvec(a, x, OG.ONE), err_msg=f"L={L} flags={flags}")
+                continue
             if ring == "c64":
                 a, x = W.complex_pair(n, seed=300 + L)
                 y = F.matvec(torch.from_numpy(a).cuda(), torch.from_numpy(x).cuda()).cpu().numpy()
@@ -103,6 +127,26 @@ def test_small_kernel_and_block_pass(F, ring, L):
                 np.testing.assert_array_equal(ym[k], oracle_modp(am[k], xm[k], 1, p), err_msg=f"batch row {k} flags={flags}")
     finally:
         F.set_schedule(n, ring_id, -1, -1, F.SCHED_XCD | F.SCHED_SMALL)
+
+
+@pytest.mark.parametrize("count", [2, 300])
+def test_block_twiddle_forms(F, count):
+    """2^13-element blocks stage their twiddles as Montgomery words when the grid has at
+    most one workgroup per CU and as Shoup pairs otherwise (300 blocks on 256 CUs): both
+    forms bit-exact, on a batch of 2^13 products forced to one block pass."""
+    L = 13
+    n = 1 << L
+    p = P1
+    rows = [W.modp_pair(n, p, seed=500 + k) for k in range(count)]
+    am = np.stack([r[0] for r in rows])
+    xm = np.stack([r[1] for r in rows])
+    F.set_schedule(n, 0, 0, -1, F.SCHED_XCD)
+    try:
+        ym = F.matvec_many(dev(am), dev(xm), f=p - 1, p=p).cpu().numpy().view(np.uint32).astype(np.int64)
+    finally:
+        F.set_schedule(n, 0, -1, -1, F.SCHED_XCD | F.SCHED_SMALL)
+    for k in sorted({0, count // 2, count - 1}):
+        np.testing.assert_array_equal(ym[k], O.levels_matvec_modp(am[k], xm[k], p - 1, p), err_msg=f"row {k}")
 
 
 def test_zero_sizes(F):
@@ -250,7 +294,7 @@ def test_complex_non_unit_f(F, f):
         assert rel_l2(got, want) <= TOL, (L, f, rel_l2(got, want))
 
 
-@pytest.mark.parametrize("L", [0, 1, 5, 11, 12, 14, 16])
+@pytest.mark.parametrize("L", [0, 1, 5, 6, 7, 8, 9, 10, 11, 12, 14, 16])
 def test_real_ring(F, L):
     n = 1 << L
     rng = np.random.default_rng(L)
