@@ -583,13 +583,13 @@ __global__ void __launch_bounds__(TopThreads<Ring>::value) k_merge(PassArgs<Ring
 // the same rows in every deeper stage: an exchange between such stages stays inside the
 // wave, and only the wave's own LDS operations have to complete. A block of at most 2^10
 // elements (at most 64 threads) lies in one wave altogether.
-template <int LOGR>
+template <int LOGR, int EL = EPT_LOG>
 constexpr bool block_in_one_wave() {
-  return LOGR - EPT_LOG <= 6;
+  return LOGR - EL <= 6;
 }
-template <int LOGR>
-constexpr bool wave_region(int l0) {  // radix-16 stage at level l0
-  return block_in_one_wave<LOGR>() || LOGR - l0 - EPT_LOG <= 6;
+template <int LOGR, int EL = EPT_LOG>
+constexpr bool wave_region(int l0) {  // radix-2^EL stage at level l0
+  return block_in_one_wave<LOGR, EL>() || LOGR - l0 - EL <= 6;
 }
 __device__ __forceinline__ void stage_sync(bool wave_local) {
   if (wave_local) {
@@ -612,100 +612,105 @@ __device__ __forceinline__ void stage_sync(bool wave_local) {
 // stage are loaded into registers at the start too; all of these loads overlap the
 // element loads of the first stage.
 // ---------------------------------------------------------------------------------------
-template <int LOGR, int NT_ = 0>
+// EL: log2 elements per thread (radix of the register stages).
+template <int LOGR, int NT_ = 0, int EL = EPT_LOG>
 struct BlockShape {
-  static constexpr int ACTIVE_LOG = LOGR > EPT_LOG ? LOGR - EPT_LOG : 0;  // threads per block
+  static constexpr int ACTIVE_LOG = LOGR > EL ? LOGR - EL : 0;  // threads per block
   static constexpr int NT = NT_ ? NT_ : ((1 << ACTIVE_LOG) < 64 ? 64 : (1 << ACTIVE_LOG));
-  static constexpr int GROUPS = NT >> ACTIVE_LOG;                        // blocks per workgroup
-  static constexpr int NST = LOGR == 0 ? 0 : (LOGR + EPT_LOG - 1) / EPT_LOG;
-  static constexpr int K0 = LOGR - EPT_LOG * (NST > 0 ? NST - 1 : 0);   // levels of the first stage
-  static constexpr int EPT = LOGR < EPT_LOG ? (1 << LOGR) : (1 << EPT_LOG);
-  static constexpr int NTW = LOGR > EPT_LOG ? (1 << (LOGR - EPT_LOG)) - 1 : 0;  // LDS twiddles per direction
+  static constexpr int GROUPS = NT >> ACTIVE_LOG;              // blocks per workgroup
+  static constexpr int NST = LOGR == 0 ? 0 : (LOGR + EL - 1) / EL;
+  static constexpr int K0 = LOGR - EL * (NST > 0 ? NST - 1 : 0);  // levels of the first stage
+  static constexpr int EPT = LOGR < EL ? (1 << LOGR) : (1 << EL);
+  static constexpr int NTW = LOGR > EL ? (1 << (LOGR - EL)) - 1 : 0;  // LDS twiddles per direction
 };
 
 // LDS of a block pass: [GROUPS][row, vector][2^LOGR] elements, then [GROUPS][split, merge][NTW]
 // twiddles (local heap order: level l, node b at 2^l - 1 + b).
-template <class Ring, int LOGR, int NT = 0, bool MONT = true>
+template <class Ring, int LOGR, int NT = 0, bool MONT = true, int EL = EPT_LOG>
 constexpr size_t block_lds_bytes() {
-  using S = BlockShape<LOGR, NT>;
+  using S = BlockShape<LOGR, NT, EL>;
   return (size_t)S::GROUPS * (2 * (sizeof(typename Ring::T) << LOGR) + 2 * (size_t)S::NTW * sizeof(BlockTw<Ring, MONT>));
 }
 
 // First twiddles of the deepest radix-16 stage (one item per thread), split and merge,
 // in deepest-stage form.
-template <class Ring>
+template <class Ring, int EL = EPT_LOG>
 struct DeepTw {
-  typename Ring::DeepW t[EPT_LOG], ti[EPT_LOG];
+  typename Ring::DeepW t[EL], ti[EL];
 };
 
 // From the heap tables (any block at depth d0, levels l0 .. l0 + 3, item sub-block sb).
-template <class Ring>
-__device__ __forceinline__ void load_deep_heap(DeepTw<Ring>& D, const Ring& R, typename Ring::Tw const* tw,
+template <class Ring, int EL>
+__device__ __forceinline__ void load_deep_heap(DeepTw<Ring, EL>& D, const Ring& R, typename Ring::Tw const* tw,
                                                typename Ring::Tw const* twi, uint32_t d0, uint32_t blk, uint32_t l0,
                                                uint32_t sb) {
-  typename Ring::Tw c[EPT_LOG], ci[EPT_LOG];
-  load_tw_first<Ring, EPT_LOG>(c, tw, d0, blk, l0, sb);
-  load_tw_first<Ring, EPT_LOG>(ci, twi, d0, blk, l0, sb);
+  typename Ring::Tw c[EL], ci[EL];
+  load_tw_first<Ring, EL>(c, tw, d0, blk, l0, sb);
+  load_tw_first<Ring, EL>(ci, twi, d0, blk, l0, sb);
 #pragma unroll
-  for (int j = 0; j < EPT_LOG; ++j) {
+  for (int j = 0; j < EL; ++j) {
     D.t[j] = R.to_deep(c[j]);
     D.ti[j] = R.to_deep(ci[j]);
   }
 }
 
-template <class Ring, int LOGR>
-__device__ __forceinline__ void load_deep_tw(DeepTw<Ring>& D, const Ring& R, const PassArgs<Ring>& A, const TilePos& P,
+// The packed first-twiddle table ft serves radix-16 deepest stages only.
+template <class Ring, int LOGR, int EL = EPT_LOG>
+__device__ __forceinline__ void load_deep_tw(DeepTw<Ring, EL>& D, const Ring& R, const PassArgs<Ring>& A, const TilePos& P,
                                              uint32_t rsel, typename Ring::Tw const* tw, typename Ring::Tw const* twi,
                                              uint32_t ltid) {
-  constexpr uint32_t l0 = LOGR - EPT_LOG;
-  const Item it = item_at(ltid, LOGR, 0, l0, EPT_LOG);
-  if (A.ft[rsel] != nullptr && A.d0 + (uint32_t)LOGR == A.logn) {
-    const uint32_t b0 = (P.blk << l0) + it.sb;  // node at depth logn - 4
-    D.t[EPT_LOG - 1] = A.ft[rsel][b0];
-    D.ti[EPT_LOG - 1] = A.fti[rsel][b0];
+  constexpr uint32_t l0 = LOGR - EL;
+  const Item it = item_at(ltid, LOGR, 0, l0, EL);
+  if constexpr (EL == EPT_LOG) {
+    if (A.ft[rsel] != nullptr && A.d0 + (uint32_t)LOGR == A.logn) {
+      const uint32_t b0 = (P.blk << l0) + it.sb;  // node at depth logn - 4
+      D.t[EL - 1] = A.ft[rsel][b0];
+      D.ti[EL - 1] = A.fti[rsel][b0];
 #pragma unroll
-    for (int j = EPT_LOG - 2; j >= 0; --j) {
-      D.t[j] = R.deep_sq(D.t[j + 1]);
-      D.ti[j] = R.deep_sq(D.ti[j + 1]);
+      for (int j = EL - 2; j >= 0; --j) {
+        D.t[j] = R.deep_sq(D.t[j + 1]);
+        D.ti[j] = R.deep_sq(D.ti[j + 1]);
+      }
+      return;
     }
-  } else {
-    load_deep_heap<Ring>(D, R, tw, twi, A.d0, P.blk, l0, it.sb);
   }
+  load_deep_heap<Ring, EL>(D, R, tw, twi, A.d0, P.blk, l0, it.sb);
 }
 
 // One split stage of the block pass on row and vector. FIRST: elements come from global
 // memory (twiddles too); otherwise from LDS. DEEPEST: the stage also forms the leaf
 // products and runs its merge levels, leaving y in sa (or writing dst if also FIRST).
-template <class Ring, int LOGR, int K, bool FIRST, bool DEEPEST, class W, class SrcA, class SrcX, class Dst>
+template <class Ring, int LOGR, int K, bool FIRST, bool DEEPEST, int EL = EPT_LOG, class W, class SrcA, class SrcX,
+          class Dst>
 __device__ __forceinline__ void block_split_stage(const PassArgs<Ring>& A, const TilePos& P, const Ring& R, uint32_t rsel,
                                                   typename Ring::Tw const* tw, typename Ring::Tw const* twi,
-                                                  const W* stw, const DeepTw<Ring>& D,
+                                                  const W* stw, const DeepTw<Ring, EL>& D,
                                                   typename Ring::T* sa, typename Ring::T* sx, uint32_t l0, uint32_t ltid,
                                                   const SrcA& srca, const SrcX& srcx, const Dst& dst) {
   using T = typename Ring::T;
   using Tw = typename Ring::Tw;
-  using S = BlockShape<LOGR>;
+  using S = BlockShape<LOGR, 0, EL>;
   constexpr int E = 1 << K;
   constexpr int IPT = S::EPT / E;
   constexpr uint32_t ACTIVE = 1u << S::ACTIVE_LOG;
   // the deepest stage of a multi-stage pass takes its first twiddles from D (radix 16)
   constexpr bool FROM_D = DEEPEST && !FIRST;
-  constexpr bool FIRSTS = DEEPEST && K == EPT_LOG;
-  static_assert(!FROM_D || K == EPT_LOG, "deepest stage of a multi-stage block pass is radix 16");
+  constexpr bool FIRSTS = DEEPEST && K == EL;
+  static_assert(!FROM_D || K == EL, "deepest stage of a multi-stage block pass is a full radix-2^EL stage");
   T va[IPT][E], vx[IPT][E];
   // a first stage loads its twiddles from the heap tables (Shoup form), later stages from
   // the LDS copy (deepest-stage form)
   using TwS = std::conditional_t<FIRST, Tw, W>;
   TwS t[(FROM_D || FIRSTS) ? 1 : IPT][E - 1];
   Tw ti[(DEEPEST && !FROM_D && !FIRSTS) ? IPT : 1][E - 1];
-  DeepTw<Ring> Dl[FIRSTS && !FROM_D ? IPT : 1];  // single-stage radix-16 block: from the heap
+  DeepTw<Ring, EL> Dl[FIRSTS && !FROM_D ? IPT : 1];  // single-stage radix-16 block: from the heap
   Item it[IPT];
 #pragma unroll
   for (int u = 0; u < IPT; ++u) {
     it[u] = item_at(ltid + u * ACTIVE, LOGR, 0, l0, K);
     if constexpr (FIRST) {
       if constexpr (FIRSTS) {
-        load_deep_heap<Ring>(Dl[u], R, tw, twi, A.d0, P.blk, l0, it[u].sb);
+        load_deep_heap<Ring, EL>(Dl[u], R, tw, twi, A.d0, P.blk, l0, it[u].sb);
       } else {
         load_tw<Ring, K>(t[u], tw, A.d0, P.blk, l0, it[u].sb);
         if constexpr (DEEPEST) load_tw<Ring, K>(ti[u], twi, A.d0, P.blk, l0, it[u].sb);
@@ -766,12 +771,12 @@ __device__ __forceinline__ void block_split_stage(const PassArgs<Ring>& A, const
 }
 
 // One radix-2^K merge stage of the block pass (twiddles from the LDS copy). LAST: write dst.
-template <class Ring, int LOGR, int K, bool LAST, class W, class Dst>
+template <class Ring, int LOGR, int K, bool LAST, int EL = EPT_LOG, class W, class Dst>
 __device__ __forceinline__ void block_merge_stage(const PassArgs<Ring>& A, const TilePos& P, const Ring& R,
                                                   const W* stwi, typename Ring::T* sa, uint32_t l0,
                                                   uint32_t ltid, const Dst& dst) {
   using T = typename Ring::T;
-  using S = BlockShape<LOGR>;
+  using S = BlockShape<LOGR, 0, EL>;
   constexpr int E = 1 << K;
   constexpr int IPT = S::EPT / E;
   constexpr uint32_t ACTIVE = 1u << S::ACTIVE_LOG;
@@ -804,14 +809,14 @@ __device__ __forceinline__ void block_merge_stage(const PassArgs<Ring>& A, const
 // The block pass for workgroup-local virtual workgroups vwg0 .. vwg0 + GROUPS - 1 (NT threads;
 // each group of 2^(LOGR-4) threads owns one block). smem_raw holds block_lds_bytes<Ring,
 // LOGR, NT>() bytes. tid is the thread's index in the workgroup.
-template <class Ring, int LOGR, int NT, bool MONT = true, class SrcA, class SrcX, class Dst>
+template <class Ring, int LOGR, int NT, bool MONT = true, int EL = EPT_LOG, class SrcA, class SrcX, class Dst>
 __device__ __forceinline__ void block_pass(const PassArgs<Ring>& A, uint32_t vwg0, uint32_t tid, unsigned char* smem_raw,
                                            const typename Ring::Params& rp0, const typename Ring::Params& rp1,
                                            const typename Ring::Params& rp2, const SrcA& srca, const SrcX& srcx,
                                            const Dst& dst) {
   using T = typename Ring::T;
   using Tw = typename Ring::Tw;
-  using S = BlockShape<LOGR, NT>;
+  using S = BlockShape<LOGR, NT, EL>;
   const uint32_t group = tid >> S::ACTIVE_LOG;
   const uint32_t ltid = tid & ((1u << S::ACTIVE_LOG) - 1);
   const uint32_t vwg = vwg0 + group;
@@ -834,7 +839,7 @@ __device__ __forceinline__ void block_pass(const PassArgs<Ring>& A, uint32_t vwg
     }
   } else {
     constexpr int NST = S::NST, K0 = S::K0;
-    DeepTw<Ring> D;
+    DeepTw<Ring, EL> D;
     if constexpr (NST > 1) {
       if (active) {
         // LDS copy of the twiddles above the deepest stage, in the ring's deepest-stage form
@@ -847,34 +852,34 @@ __device__ __forceinline__ void block_pass(const PassArgs<Ring>& A, uint32_t vwg
           stw[e] = to_block_tw<Ring, MONT>(R, tw[gi]);
           stwi[e] = to_block_tw<Ring, MONT>(R, twi[gi]);
         }
-        load_deep_tw<Ring, LOGR>(D, R, A, P, rsel, tw, twi, ltid);
+        load_deep_tw<Ring, LOGR, EL>(D, R, A, P, rsel, tw, twi, ltid);
       }
     }
     // split stages (first takes K0 levels), the deepest also runs leaf + its merge levels
-    if (active) block_split_stage<Ring, LOGR, K0, true, NST == 1>(A, P, R, rsel, tw, twi, stw, D, sa, sx, 0, ltid, srca, srcx, dst);
+    if (active) block_split_stage<Ring, LOGR, K0, true, NST == 1, EL>(A, P, R, rsel, tw, twi, stw, D, sa, sx, 0, ltid, srca, srcx, dst);
     if constexpr (NST > 1) {
-      stage_sync(block_in_one_wave<LOGR>());  // also publishes the LDS twiddles
+      stage_sync(block_in_one_wave<LOGR, EL>());  // also publishes the LDS twiddles
 #pragma unroll
       for (int s = 1; s < NST; ++s) {
-        const uint32_t l0 = K0 + EPT_LOG * (s - 1);
+        const uint32_t l0 = K0 + EL * (s - 1);
         if (active) {
           if (s + 1 == NST)
-            block_split_stage<Ring, LOGR, EPT_LOG, false, true>(A, P, R, rsel, tw, twi, stw, D, sa, sx, l0, ltid, srca, srcx, dst);
+            block_split_stage<Ring, LOGR, EL, false, true, EL>(A, P, R, rsel, tw, twi, stw, D, sa, sx, l0, ltid, srca, srcx, dst);
           else
-            block_split_stage<Ring, LOGR, EPT_LOG, false, false>(A, P, R, rsel, tw, twi, stw, D, sa, sx, l0, ltid, srca, srcx, dst);
+            block_split_stage<Ring, LOGR, EL, false, false, EL>(A, P, R, rsel, tw, twi, stw, D, sa, sx, l0, ltid, srca, srcx, dst);
         }
         // next: split stage s + 1, or (after the deepest) merge stage NST - 2 in its layout
         const int nxt = s + 1 < NST ? s : NST - 2;
-        stage_sync(nxt >= 1 && wave_region<LOGR>(K0 + EPT_LOG * (nxt - 1)) ? true : block_in_one_wave<LOGR>());
+        stage_sync(nxt >= 1 && wave_region<LOGR, EL>(K0 + EL * (nxt - 1)) ? true : block_in_one_wave<LOGR, EL>());
       }
       // merge stages above the deepest one, then the first stage's K0 levels to dst
 #pragma unroll
       for (int s = NST - 2; s >= 1; --s) {
-        const uint32_t l0 = K0 + EPT_LOG * (s - 1);
-        if (active) block_merge_stage<Ring, LOGR, EPT_LOG, false>(A, P, R, stwi, sa, l0, ltid, dst);
-        stage_sync(s - 1 >= 1 && wave_region<LOGR>(K0 + EPT_LOG * (s - 2)) ? true : block_in_one_wave<LOGR>());
+        const uint32_t l0 = K0 + EL * (s - 1);
+        if (active) block_merge_stage<Ring, LOGR, EL, false, EL>(A, P, R, stwi, sa, l0, ltid, dst);
+        stage_sync(s - 1 >= 1 && wave_region<LOGR, EL>(K0 + EL * (s - 2)) ? true : block_in_one_wave<LOGR, EL>());
       }
-      if (active) block_merge_stage<Ring, LOGR, K0, true>(A, P, R, stwi, sa, 0, ltid, dst);
+      if (active) block_merge_stage<Ring, LOGR, K0, true, EL>(A, P, R, stwi, sa, 0, ltid, dst);
     }
   }
 }
@@ -1274,13 +1279,13 @@ __global__ void __launch_bounds__(BlockShape<LOGR>::NT) k_acc_block(PassArgs<Rin
   acc_block_pass<Ring, LOGR>(A, blk, b0, b1, chunk, threadIdx.x, smem_raw, rp, srca, srcx, out);
 }
 
-template <class Ring, int LOGR, class SrcA, class SrcX, class Dst, bool MONT = true>
-__global__ void __launch_bounds__(BlockShape<LOGR>::NT) k_block(PassArgs<Ring> A, typename Ring::Params rp0,
+template <class Ring, int LOGR, class SrcA, class SrcX, class Dst, bool MONT = true, int EL = EPT_LOG>
+__global__ void __launch_bounds__((BlockShape<LOGR, 0, EL>::NT)) k_block(PassArgs<Ring> A, typename Ring::Params rp0,
                                                                  typename Ring::Params rp1, typename Ring::Params rp2,
                                                                  SrcA srca, SrcX srcx, Dst dst) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  using S = BlockShape<LOGR>;
-  block_pass<Ring, LOGR, S::NT, MONT>(A, blockIdx.x * S::GROUPS, threadIdx.x, smem_raw, rp0, rp1, rp2, srca, srcx, dst);
+  using S = BlockShape<LOGR, 0, EL>;
+  block_pass<Ring, LOGR, S::NT, MONT, EL>(A, blockIdx.x * S::GROUPS, threadIdx.x, smem_raw, rp0, rp1, rp2, srca, srcx, dst);
 }
 
 }  // namespace fcirc
