@@ -509,11 +509,14 @@ __global__ void __launch_bounds__(TopThreads<Ring>::value) k_split_ax(PassArgs<R
 
 // ---------------------------------------------------------------------------------------
 // One merge stage of a top pass. FIRST: read global (the deepest stage runs first).
+// tpre: the stage's twiddles, loaded ahead (a stage at tile level 0, whose items all use
+// sub-block 0), or null.
 // ---------------------------------------------------------------------------------------
 template <class Ring, int K, bool FIRST, bool LAST, class Src, class Dst>
 __device__ __forceinline__ void merge_stage(const PassArgs<Ring>& A, const TilePos& P, const Ring& R,
                                             typename Ring::Tw const* twi, typename Ring::T* lds, uint32_t l0,
-                                            uint32_t nt, uint32_t tid, const Src& src, const Dst& dst) {
+                                            uint32_t nt, uint32_t tid, const Src& src, const Dst& dst,
+                                            const typename Ring::Tw* tpre = nullptr) {
   using T = typename Ring::T;
   using Tw = typename Ring::Tw;
   constexpr int IPT = 1 << (EPT_LOG - K);
@@ -524,7 +527,12 @@ __device__ __forceinline__ void merge_stage(const PassArgs<Ring>& A, const TileP
 #pragma unroll
   for (int u = 0; u < IPT; ++u) {
     it[u] = item_at(tid + u * nt, A.logr, A.logc, l0, K);
-    load_tw<Ring, K>(t[u], twi, A.d0, P.blk, l0, it[u].sb);
+    if (tpre != nullptr) {
+#pragma unroll
+      for (int j = 0; j < E - 1; ++j) t[u][j] = tpre[j];
+    } else {
+      load_tw<Ring, K>(t[u], twi, A.d0, P.blk, l0, it[u].sb);
+    }
   }
 #pragma unroll
   for (int u = 0; u < IPT; ++u)
@@ -559,10 +567,15 @@ __device__ __forceinline__ void merge_pass(const PassArgs<Ring>& A, const TilePo
                                            uint32_t nt, uint32_t tid, typename Ring::T* lds, const Src& src, const Dst& dst) {
   using SP = StagePlan<R>;
   const typename Ring::Tw* twi = A.twi[rsel];
+  // The last stage (tile levels 0 .. K0-1) uses the same twiddles in every item: loaded at
+  // the start from addresses uniform over the workgroup, so that they do not wait behind
+  // the stage barriers.
+  typename Ring::Tw t0[(1 << SP::K0) - 1];
+  load_tw<Ring, SP::K0>(t0, twi, A.d0, P.blk, 0, 0);
   static_for<SP::NST>([&](auto sc) {
     constexpr int s = SP::NST - 1 - decltype(sc)::value;  // deepest stage first
     constexpr bool first = s + 1 == SP::NST, last = s == 0;
-    merge_stage<Ring, SP::k(s), first, last>(A, P, Rg, twi, lds, SP::l0(s), nt, tid, src, dst);
+    merge_stage<Ring, SP::k(s), first, last>(A, P, Rg, twi, lds, SP::l0(s), nt, tid, src, dst, last ? t0 : nullptr);
     if constexpr (!last) __syncthreads();
   });
 }
