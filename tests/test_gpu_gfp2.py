@@ -72,6 +72,21 @@ def test_gfp2_many_and_forced_splits(F):
     del torch
 
 
+def test_gfp2_two_top_passes(F):
+    """Forced schedules of 16, 18 and 20 top levels at 2^20: two top passes of 8, 9 and 10
+    levels each way (inner merges write the workspace), blocks of 2^4, 2^2 and 2^0."""
+    n = 1 << 20
+    a, x = rand(n, 61), rand(n, 62)
+    want = G.levels_matvec(a, x, G.ONE)
+    try:
+        for top in (16, 18, 20):
+            F.set_split(top)
+            got = F.matvec(dev(a), dev(x), f=1, p=P).cpu().numpy().astype(np.uint64)
+            np.testing.assert_array_equal(got, want, err_msg=f"top={top}")
+    finally:
+        F.set_split(-1)
+
+
 def test_gfp2_errors(F):
     from paper_2103_02605_amd._lib import FcircError
     a = dev(rand(16, 1))

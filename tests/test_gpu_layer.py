@@ -46,7 +46,9 @@ def test_real_n64_against_dense_autograd_and_finite_differences(F):
 @pytest.mark.parametrize("n,batch", [(16, 1), (64, 3), (1024, 7), (1 << 13, 4), (1 << 14, 33), (1 << 14, 64), (1 << 16, 2), (1 << 21, 1),
                                      # grad_a by 13-level accumulating blocks: no top split at 2^13
                                      # (512 complex instances), one top level at 2^14 (256)
-                                     (1 << 13, 512), (1 << 14, 256)])
+                                     (1 << 13, 512), (1 << 14, 256),
+                                     # 11 top levels: two top passes (5 + 6 levels) in every product
+                                     (1 << 24, 1)])
 def test_complex_layer(F, n, batch):
     import torch
     rng = np.random.default_rng(n + batch)

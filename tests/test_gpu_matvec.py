@@ -305,7 +305,9 @@ def test_real_ring(F, L):
     assert rel_l2(got, want) <= TOL
 
 
-@pytest.mark.parametrize("L,top", [(12, 3), (14, 10), (16, 13)])
+# (20, 16..20): two top passes of 8, 9 and 10 levels each way, so the inner merge passes
+# (workspace to workspace, agent-scope stores) of 8..10 levels run; blocks of 2^4 .. 2^0
+@pytest.mark.parametrize("L,top", [(12, 3), (14, 10), (16, 13), (20, 16), (20, 18), (20, 20)])
 def test_complex_forced_splits(F, L, top):
     n = 1 << L
     a, x = W.complex_pair(n, seed=3)
