@@ -329,6 +329,14 @@ inline Schedule make_schedule(int L, int elem_log, int top_levels, int tile_log_
   const int top_max = 10;
   int T = top_levels;
   if (T < 0) T = L <= 12 ? 0 : std::max(L - block_max, std::min(8, L - 10));
+  // Z/p above 2^21 (every top-level count from L - 13 to L - 8 and tiles of 2^12..2^14
+  // timed on MI355X at 2^22..2^26): 2^22 and 2^23 take 10 top levels in one pass over
+  // 2^14-element tiles (2^23: 135 against 182 us with 2^13 tiles); from 2^24 on, two top
+  // passes over blocks of 2^10 (2^25: 523 against 564 us; 2^26: 1.02 against 1.16 ms).
+  if (elem_log == 2 && L >= 22) {
+    if (tile_log_in < 0) tile_log = L <= 23 ? 14 : 13;
+    if (top_levels < 0) T = L <= 23 ? 10 : L - 10;
+  }
   if (T > L) T = L;
   if (L < 5) T = 0;                                // too small for a column tile of 16 elements
   if (L - T > 13 - (elem_log - 2)) T = L - (13 - (elem_log - 2));  // block must fit LDS
