@@ -101,20 +101,6 @@ __global__ void k_crt_i64(const uint32_t* __restrict__ res, uint64_t N, uint64_t
   out[k] = v;
 }
 
-// Unsigned coefficients (bigint): v3 must be 0.
-__global__ void k_crt_u64(const uint32_t* __restrict__ res, uint64_t N, uint64_t nc, CrtConsts K, uint64_t* __restrict__ out,
-                          uint32_t* status) {
-  const uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= nc) return;
-  uint64_t c;
-  const uint32_t v3 = garner(res[k], res[N + k], res[2 * N + k], K, &c);
-  if (v3 != 0) {
-    c = 0;
-    atomicOr(status, FCIRC_STATUS_RANGE);
-  }
-  out[k] = c;
-}
-
 // Carries. The value is sum_k c_k 2^(16k) with c_k < 2^52. With digit_t(c) = 16-bit digit t,
 // s_j = sum_{t<4} digit_t(c_(j-t)) < 2^18 and u_j = (s_j mod 2^16) + floor(s_(j-1) / 2^16)
 // <= 2^16 + 2 keep the same value; then one carry-lookahead pass over u finishes it:
@@ -161,20 +147,70 @@ __device__ __forceinline__ GP block_scan_gp(GP v, uint32_t* sh, GP* total) {
 __device__ __forceinline__ uint32_t padk(uint32_t k) { return k + (k >> 4); }
 constexpr int CARRY_PAD = CARRY_BLOCK + CARRY_BLOCK / 16;
 
+// Coefficient sources of the first carry pass: c_k from memory, or formed from the three
+// residues by Garner's method (the large-integer product: no coefficient array at all).
+// Each has load(k), which reads unconditionally (coefficient 0 past the end: nc >= 1), and
+// value(k, raw, bad), which selects zero past the end; a thread issues all its loads before
+// the first value. A coefficient out of range is noted in `bad` and reported once per
+// thread (report).
+struct CoefU64 {
+  const uint64_t* c;
+  uint64_t nc;
+  using Raw = uint64_t;
+  __device__ __forceinline__ Raw load(uint64_t k) const { return c[k < nc ? k : 0]; }
+  __device__ __forceinline__ uint64_t value(uint64_t k, Raw v, uint32_t&) const { return k < nc ? v : 0ull; }
+  __device__ __forceinline__ void report(uint32_t) const {}
+};
+struct CoefCrt {  // unsigned coefficients: v3 must be 0, else the range flag is raised
+  const uint32_t* res;
+  uint64_t N, nc;
+  CrtConsts K;
+  uint32_t* status;
+  struct Raw {
+    uint32_t r1, r2, r3;
+  };
+  __device__ __forceinline__ Raw load(uint64_t k) const {
+    const uint64_t kk = k < nc ? k : 0;
+    return Raw{res[kk], res[N + kk], res[2 * N + kk]};
+  }
+  __device__ __forceinline__ uint64_t value(uint64_t k, Raw r, uint32_t& bad) const {
+    uint64_t c;
+    const uint32_t v3 = garner(r.r1, r.r2, r.r3, K, &c);
+    const bool in = k < nc;
+    bad |= (in && v3 != 0) ? 1u : 0u;
+    return in && v3 == 0 ? c : 0ull;
+  }
+  __device__ __forceinline__ void report(uint32_t bad) const {
+    if (bad) atomicOr(status, FCIRC_STATUS_RANGE);
+  }
+};
+
 // Pass 1: u_j into `u`, and each workgroup's (G, P) summary. The block's coefficients
 // (plus 4 before it) are staged in LDS with coalesced loads; thread t computes u for limbs
 // t + 256 i (consecutive lanes, consecutive words), then takes the GP summary of its own
 // contiguous run of 16.
-__global__ void __launch_bounds__(CARRY_NT) k_carry_scan1(const uint64_t* __restrict__ c, uint64_t nc, uint64_t nl,
-                                                          uint32_t* __restrict__ u, uint32_t* __restrict__ summ) {
+template <class Coef>
+__global__ void __launch_bounds__(CARRY_NT) k_carry_scan1(Coef coef, uint64_t nl, uint32_t* __restrict__ u,
+                                                          uint32_t* __restrict__ summ) {
   __shared__ uint64_t sc[CARRY_BLOCK + 4];
   __shared__ uint32_t su[CARRY_PAD];
   __shared__ uint32_t sh[CARRY_NT / 64];
   const uint64_t jb = (uint64_t)blockIdx.x * CARRY_BLOCK;
-  for (uint32_t k = threadIdx.x; k < CARRY_BLOCK + 4; k += CARRY_NT) {
-    const int64_t idx = (int64_t)jb + (int64_t)k - 4;
-    sc[k] = (idx >= 0 && (uint64_t)idx < nc) ? c[idx] : 0ull;
+  // sc[k] = c_(jb + k - 4): the block's coefficients, then the 4 before it
+  // thread t < 4 also stages c_(jb + t - 4) (zero before the first limb)
+  const uint64_t kx = jb + threadIdx.x >= 4 ? jb + threadIdx.x - 4 : coef.nc;
+  typename Coef::Raw raw[CARRY_PER_THREAD], rx;
+#pragma unroll
+  for (int i = 0; i < CARRY_PER_THREAD; ++i) raw[i] = coef.load(jb + threadIdx.x + (uint32_t)i * CARRY_NT);
+  if (threadIdx.x < 4) rx = coef.load(kx);
+  uint32_t bad = 0;
+#pragma unroll
+  for (int i = 0; i < CARRY_PER_THREAD; ++i) {
+    const uint64_t k = jb + threadIdx.x + (uint32_t)i * CARRY_NT;
+    sc[threadIdx.x + (uint32_t)i * CARRY_NT + 4] = coef.value(k, raw[i], bad);
   }
+  if (threadIdx.x < 4) sc[threadIdx.x] = coef.value(kx, rx, bad);
+  coef.report(bad);
   __syncthreads();
 #pragma unroll
   for (int i = 0; i < CARRY_PER_THREAD; ++i) {
@@ -209,13 +245,36 @@ __global__ void __launch_bounds__(CARRY_NT) k_carry_scan2(const uint32_t* __rest
   __shared__ uint32_t su[CARRY_PAD];
   __shared__ uint32_t sh[CARRY_NT / 64];
   const uint64_t jb = (uint64_t)blockIdx.x * CARRY_BLOCK;
-  for (uint32_t k = threadIdx.x; k < CARRY_BLOCK; k += CARRY_NT) su[padk(k)] = jb + k < nl ? u[jb + k] : 0u;
-  // summaries of blocks [0, blockIdx.x): thread t composes its contiguous share in order
+  // Summaries of blocks [0, blockIdx.x): thread t composes its contiguous share in order.
+  // All loads are issued before the first wait: the block's limbs (unconditional: limb
+  // nl - 1 past the end) and the first two summaries of the share (a share has at most two
+  // below 513 blocks; the rest, if any, follow in a loop).
   const uint32_t nb = blockIdx.x;
   const uint32_t per = (nb + CARRY_NT - 1) / CARRY_NT;
+  const uint32_t b0 = threadIdx.x * per, b1 = min(b0 + per, nb);
+  uint32_t lv[CARRY_PER_THREAD];
+#pragma unroll
+  for (int i = 0; i < CARRY_PER_THREAD; ++i) {
+    const uint64_t j = jb + threadIdx.x + (uint32_t)i * CARRY_NT;
+    lv[i] = u[j < nl ? j : nl - 1];
+  }
+  uint32_t sv[4];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const uint32_t b = b0 + q < b1 ? b0 + q : 0;  // summary 0 exists whenever nb > 0
+    sv[2 * q] = summ[2 * b];
+    sv[2 * q + 1] = summ[2 * b + 1];
+  }
+#pragma unroll
+  for (int i = 0; i < CARRY_PER_THREAD; ++i) {
+    const uint32_t k = threadIdx.x + (uint32_t)i * CARRY_NT;
+    su[padk(k)] = jb + k < nl ? lv[i] : 0u;
+  }
   GP part{0u, 1u};
-  for (uint32_t b = threadIdx.x * per; b < (threadIdx.x + 1) * per && b < nb; ++b)
-    part = gp_combine(part, GP{summ[2 * b], summ[2 * b + 1]});
+#pragma unroll
+  for (int q = 0; q < 2; ++q)
+    if (b0 + q < b1) part = gp_combine(part, GP{sv[2 * q], sv[2 * q + 1]});
+  for (uint32_t b = b0 + 2; b < b1; ++b) part = gp_combine(part, GP{summ[2 * b], summ[2 * b + 1]});
   GP before;
   (void)block_scan_gp(part, sh, &before);
   const uint32_t cin_blk = before.g;  // carry out of all earlier limbs (initial carry 0)
@@ -308,6 +367,19 @@ fcirc_status three_prime_products(Ctx& c, const V* a, uint64_t na, const V* b, u
                                     StPlain<uint32_t, ST_AGENT>{res, N}, res, ws, s));
 }
 
+// The two carry passes over nl limbs, coefficients from `coef`.
+template <class Coef>
+fcirc_status carry_passes(Ctx& c, Coef coef, uint64_t nl, uint32_t* u, uint32_t* summ, uint16_t* out, hipStream_t s) {
+  const uint64_t nblk = (nl + CARRY_BLOCK - 1) / CARRY_BLOCK;
+  hipError_t e = launch(c, "fcirc_carry", s, [&](hipEvent_t e0_, hipEvent_t e1_) {
+    FCIRC_LAUNCH(e0_, e1_, k_carry_scan1<Coef>, dim3((uint32_t)nblk), dim3(CARRY_NT), 0, s, coef, nl, u, summ);
+  });
+  if (e != hipSuccess) return hip_status(e);
+  return hip_status(launch(c, "fcirc_carry", s, [&](hipEvent_t e0_, hipEvent_t e1_) {
+    FCIRC_LAUNCH(e0_, e1_, k_carry_scan2, dim3((uint32_t)nblk), dim3(CARRY_NT), 0, s, u, nl, summ, out);
+  }));
+}
+
 }  // namespace
 
 fcirc_status polymul_i64(Ctx& c, const int32_t* a, uint64_t na, const int32_t* b, uint64_t nb, int64_t* out, hipStream_t s) {
@@ -332,34 +404,28 @@ fcirc_status bigint_mul(Ctx& c, const uint16_t* a, uint64_t na, const uint16_t* 
   const uint64_t N = (uint64_t)1 << L;
   const Schedule S = schedule_for(c, FCIRC_ZP_998244353, L);
   const uint64_t nblk = (nl + CARRY_BLOCK - 1) / CARRY_BLOCK;
-  // layout (uint32 units): res[3N] | coeffs u64[nc] | u[nl] | summaries[2 nblk] | product workspace
-  const uint64_t off_c = 3 * N, off_u = off_c + 2 * nc, off_s = off_u + nl, off_w = (off_s + 2 * nblk + 63) & ~63ull;
+  // layout (uint32 units): res[3N] | u[nl] | summaries[2 nblk] | product workspace
+  const uint64_t off_u = 3 * N, off_s = off_u + nl, off_w = (off_s + 2 * nblk + 63) & ~63ull;
   const uint64_t wse = off_w + product_ws_elems(S, 3, false);
   fcirc_status st = ws_reserve(c, wse * sizeof(uint32_t));
   if (st != FCIRC_OK) return st;
   uint32_t* base = (uint32_t*)c.ws;
   uint32_t* res = base;
-  uint64_t* coef = (uint64_t*)(base + off_c);
   uint32_t* u = base + off_u;
   uint32_t* summ = base + off_s;
   st = three_prime_products<uint16_t>(c, a, na, b, nb, L, res, base + off_w, s);
   if (st != FCIRC_OK) return st;
-  const CrtConsts K = crt_consts();
-  hipError_t e = launch(c, "fcirc_crt", s, [&](hipEvent_t e0_, hipEvent_t e1_) {
-    FCIRC_LAUNCH(e0_, e1_, k_crt_u64, dim3((uint32_t)((nc + 255) / 256)), dim3(256), 0, s, res, N, nc, K, coef, c.d_status);
-  });
-  if (e != hipSuccess) return hip_status(e);
-  return carry_to_limbs(c, coef, nc, nl, u, summ, out, s);
+  // Garner's CRT runs inside the first carry pass, on the coefficients each workgroup
+  // stages: the 8-byte coefficients never reach memory (measured on MI355X for 2 x 2^24
+  // bits: a separate CRT kernel and pass took 9.1 + 12.3 us).
+  return carry_passes(c, CoefCrt{res, N, nc, crt_consts(), c.d_status}, nl, u, summ, out, s);
 }
 
 uint64_t carry_blocks(uint64_t nl) { return (nl + CARRY_BLOCK - 1) / CARRY_BLOCK; }
 
 fcirc_status carry_to_limbs(Ctx& c, const uint64_t* coef, uint64_t nc, uint64_t nl, uint32_t* u, uint32_t* summ,
                             uint16_t* out, hipStream_t s) {
-  const uint64_t nblk = carry_blocks(nl);
-  hipError_t e = launch(c, "fcirc_carry", s, [&](hipEvent_t e0_, hipEvent_t e1_) { FCIRC_LAUNCH(e0_, e1_, k_carry_scan1, dim3((uint32_t)nblk), dim3(CARRY_NT), 0, s, coef, nc, nl, u, summ); });
-  if (e != hipSuccess) return hip_status(e);
-  return hip_status(launch(c, "fcirc_carry", s, [&](hipEvent_t e0_, hipEvent_t e1_) { FCIRC_LAUNCH(e0_, e1_, k_carry_scan2, dim3((uint32_t)nblk), dim3(CARRY_NT), 0, s, u, nl, summ, out); }));
+  return carry_passes(c, CoefU64{coef, nc}, nl, u, summ, out, s);
 }
 
 }  // namespace fcirc
