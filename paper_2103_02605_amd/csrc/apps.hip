@@ -25,12 +25,19 @@ constexpr uint32_t Q1 = 998244353u, Q2 = 469762049u, Q3 = 167772161u;
 // Both loaders read unconditionally (element 0 when the index is past the data: na and nb
 // are at least 1) and select zero afterwards, so the loads of a stage are all issued before
 // the first wait instead of one branch, load and wait per element.
+// A signed 32-bit input enters as a residue in (0, 3p), not reduced further: every first
+// operation of the product (split butterfly, or the leaf product of a one-element block)
+// takes operands below 4p. v + 2^31 is brought to [0, 2p) by Shoup's method with w = 1,
+// then 2^31 mod p is subtracted as p - (2^31 mod p) added.
 template <class V>
 __device__ __forceinline__ uint32_t residue_of(const Zp& R, V v) {
-  if constexpr (sizeof(V) == 4)
-    return R.from_i32((int32_t)v);
-  else
+  if constexpr (sizeof(V) == 4) {
+    const uint32_t u = (uint32_t)(int32_t)v ^ 0x80000000u;
+    const uint32_t r = u - __umulhi(u, R.one.wp) * R.p;
+    return r + (R.p - R.two31);
+  } else {
     return (uint32_t)v;
+  }
 }
 template <class V>
 struct LdRowRev {  // r_k = a_((N - k) mod N), zero beyond na
