@@ -431,6 +431,49 @@ __global__ void __launch_bounds__(64 * FM_WAVES) k_fm_split(const uint32_t* a_in
   fm_split_levels<Q, R, true>(x_in, wx, k, q, b, d, f_shift);
 }
 
+// Four levels d .. d + 3 in one pass, exchanged through LDS: a workgroup of four waves
+// takes the 16 elements k + j q (j < 16, q = n / 2^(d+4)) of one depth-d block b. For
+// levels d and d + 1, wave w holds elements w + 4i (i < 4): a two-level pass over block b.
+// For levels d + 2 and d + 3 it holds elements 4w + i: a two-level pass over the
+// depth-(d+2) block 4b + w. Every element is read from memory and written back once per
+// four levels (twice per two-level pass).
+static_assert(FM_WAVES == 4, "a four-level pass takes one wave per quarter of its 16 elements");
+
+template <int Q, bool IS_X>
+__device__ __forceinline__ void fm_split4_array(const uint32_t* src, uint32_t* dst, uint32_t* sm, uint32_t k, uint32_t q,
+                                                uint32_t b, uint32_t d, uint32_t f_shift, uint32_t w) {
+  constexpr uint32_t S = 64u * Q + 1;
+  FE<Q> v[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) v[i] = fload<Q>(src + (size_t)(k + (w + 4u * i) * q) * S);
+  fm_split_from<Q, 2, 0, IS_X>(v, b, d, f_shift);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) fstore<Q>(sm + (w + 4u * i) * S, v[i]);
+  __syncthreads();  // also: every element of the group has been read before any is written
+#pragma unroll
+  for (int i = 0; i < 4; ++i) v[i] = fload<Q>(sm + (4u * w + i) * S);
+  fm_split_from<Q, 2, 0, IS_X>(v, 4u * b + w, d + 2, f_shift);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) fstore<Q>(dst + (size_t)(k + (4u * w + i) * q) * S, v[i]);
+}
+
+// grid: 2 n / 16 workgroups of 4 waves, the row's groups then the vector's.
+template <int Q>
+__global__ void __launch_bounds__(64 * FM_WAVES) k_fm_split4(const uint32_t* a_in, const uint32_t* x_in, uint32_t* wa,
+                                                             uint32_t* wx, uint32_t n, uint32_t d, uint32_t f_shift) {
+  constexpr uint32_t S = 64u * Q + 1;
+  __shared__ uint32_t sm[16 * S];
+  const uint32_t groups = n >> 4;
+  const bool is_x = blockIdx.x >= groups;
+  const uint32_t t = is_x ? blockIdx.x - groups : blockIdx.x;
+  const uint32_t w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint32_t q = n >> (d + 4), b = t / q, k = b * 16u * q + (t - b * q);
+  if (is_x)
+    fm_split4_array<Q, true>(x_in, wx, sm, k, q, b, d, f_shift, w);
+  else
+    fm_split4_array<Q, false>(a_in, wa, sm, k, q, b, d, f_shift, w);
+}
+
 // Leaves: y_k = a_k x_k / n (1/n = 2^(2K - L)), one wave per element.
 template <int Q>
 __global__ void __launch_bounds__(64 * FM_WAVES) k_fm_leaf(const uint32_t* a, const uint32_t* x, uint32_t* y, uint32_t n,
@@ -480,6 +523,29 @@ __global__ void __launch_bounds__(64 * FM_WAVES) k_fm_merge(uint32_t* y, uint32_
   fm_merge_from<Q, R, R - 1>(v, b, d, f_shift);
 #pragma unroll
   for (int j = 0; j < E; ++j) fstore<Q>(y + (size_t)(k + j * q) * S, v[j]);
+}
+
+// Four merge levels d + 3 .. d in one pass (the inverse of k_fm_split4), in place.
+// grid: n / 16 workgroups of 4 waves.
+template <int Q>
+__global__ void __launch_bounds__(64 * FM_WAVES) k_fm_merge4(uint32_t* y, uint32_t n, uint32_t d, uint32_t f_shift) {
+  constexpr uint32_t S = 64u * Q + 1;
+  __shared__ uint32_t sm[16 * S];
+  const uint32_t t = blockIdx.x;
+  const uint32_t w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint32_t q = n >> (d + 4), b = t / q, k = b * 16u * q + (t - b * q);
+  FE<Q> v[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) v[i] = fload<Q>(y + (size_t)(k + (4u * w + i) * q) * S);
+  fm_merge_from<Q, 2, 1>(v, 4u * b + w, d + 2, f_shift);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) fstore<Q>(sm + (4u * w + i) * S, v[i]);
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < 4; ++i) v[i] = fload<Q>(sm + (w + 4u * i) * S);
+  fm_merge_from<Q, 2, 1>(v, b, d, f_shift);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) fstore<Q>(y + (size_t)(k + (w + 4u * i) * q) * S, v[i]);
 }
 
 // Canonical form of n elements (the input check): the top word is 0 or 1, and 1 only
@@ -535,12 +601,12 @@ __global__ void k_fm_coef(const uint32_t* __restrict__ y, uint32_t n, uint32_t W
   coef[k] = s;
 }
 
-// Levels per split or merge pass (the pass holds 2^R elements of Q words per lane). Two:
-// measured on MI355X for the 2 x 2^24-bit product (K = 8192, 2^14 pieces), passes of 3 and
-// 4 levels took 545 and 720 us against 499 us, their registers (200 and 256 per lane in
-// the split) cutting occupancy more than the fewer passes save.
-constexpr int fm_pass_levels(int) { return 2; }
-
+// Levels per split or merge pass. A register pass holds 2^R elements of Q words per lane:
+// measured on MI355X for the 2 x 2^24-bit product (K = 8192, 2^14 pieces), register passes
+// of 3 and 4 levels took 545 and 720 us against 499 us with 2 levels, their registers (200
+// and 256 per lane in the split) cutting occupancy more than the fewer passes save. Four
+// levels go through LDS instead (k_fm_split4, k_fm_merge4: two 2-level steps per pass, the
+// registers of a 2-level pass); the 1..3 levels left take register passes of 2 and 1.
 template <int Q, int R>
 hipError_t fm_split_pass(Ctx& c, const uint32_t* sa, const uint32_t* sx, uint32_t* wa, uint32_t* wx, uint32_t n, uint32_t d,
                          uint32_t f_shift, hipStream_t s) {
@@ -559,25 +625,41 @@ hipError_t fm_merge_pass(Ctx& c, uint32_t* y, uint32_t n, uint32_t d, uint32_t f
 }
 
 template <int Q>
+hipError_t fm_split4_pass(Ctx& c, const uint32_t* sa, const uint32_t* sx, uint32_t* wa, uint32_t* wx, uint32_t n, uint32_t d,
+                          uint32_t f_shift, hipStream_t s) {
+  return launch(c, "fcirc_fermat_split", s, [&](hipEvent_t e0_, hipEvent_t e1_) {
+    FCIRC_LAUNCH(e0_, e1_, k_fm_split4<Q>, dim3(2 * (n >> 4)), dim3(64 * FM_WAVES), 0, s, sa, sx, wa, wx, n, d, f_shift);
+  });
+}
+
+template <int Q>
+hipError_t fm_merge4_pass(Ctx& c, uint32_t* y, uint32_t n, uint32_t d, uint32_t f_shift, hipStream_t s) {
+  return launch(c, "fcirc_fermat_merge", s, [&](hipEvent_t e0_, hipEvent_t e1_) {
+    FCIRC_LAUNCH(e0_, e1_, k_fm_merge4<Q>, dim3(n >> 4), dim3(64 * FM_WAVES), 0, s, y, n, d, f_shift);
+  });
+}
+
+template <int Q>
 hipError_t fm_product_q(Ctx& c, const uint32_t* a, const uint32_t* x, uint32_t* y, int L, uint32_t f_shift, uint32_t* wa,
                         uint32_t* wx, hipStream_t s) {
-  constexpr int RM = fm_pass_levels(Q);
   const uint32_t n = 1u << L;
+  // passes from the top: 4 levels while at least 4 are left, then 2, then 1
+  int pd[32], pr[32], np = 0;
+  for (int d = 0; d < L;) {
+    const int r = L - d >= 4 ? 4 : std::min(2, L - d);
+    pd[np] = d;
+    pr[np] = r;
+    ++np;
+    d += r;
+  }
   hipError_t e = hipSuccess;
   const uint32_t* sa = a;
   const uint32_t* sx = x;
-  // levels in passes of RM from the top; the last pass takes what is left
-  for (int d = 0; d < L && e == hipSuccess; d += RM) {
-    const int r = std::min(RM, L - d);
-    const uint32_t dd = (uint32_t)d;
-    if (r == 1) e = fm_split_pass<Q, 1>(c, sa, sx, wa, wx, n, dd, f_shift, s);
-    else if (r == 2) e = fm_split_pass<Q, 2>(c, sa, sx, wa, wx, n, dd, f_shift, s);
-    else if constexpr (RM >= 3) {
-      if (r == 3) e = fm_split_pass<Q, 3>(c, sa, sx, wa, wx, n, dd, f_shift, s);
-      else if constexpr (RM >= 4) {
-        if (r == 4) e = fm_split_pass<Q, 4>(c, sa, sx, wa, wx, n, dd, f_shift, s);
-      }
-    }
+  for (int i = 0; i < np && e == hipSuccess; ++i) {
+    const uint32_t dd = (uint32_t)pd[i];
+    if (pr[i] == 4) e = fm_split4_pass<Q>(c, sa, sx, wa, wx, n, dd, f_shift, s);
+    else if (pr[i] == 2) e = fm_split_pass<Q, 2>(c, sa, sx, wa, wx, n, dd, f_shift, s);
+    else e = fm_split_pass<Q, 1>(c, sa, sx, wa, wx, n, dd, f_shift, s);
     sa = wa;
     sx = wx;
   }
@@ -587,17 +669,11 @@ hipError_t fm_product_q(Ctx& c, const uint32_t* a, const uint32_t* x, uint32_t* 
     FCIRC_LAUNCH(e0_, e1_, k_fm_leaf<Q>, dim3(gl), dim3(64 * FM_WAVES), 0, s, sa, sx, y, n, LL);
   });
   // the same passes in reverse order (none when n = 1)
-  for (int d = L > 0 ? ((L - 1) / RM) * RM : -1; d >= 0 && e == hipSuccess; d -= RM) {
-    const int r = std::min(RM, L - d);
-    const uint32_t dd = (uint32_t)d;
-    if (r == 1) e = fm_merge_pass<Q, 1>(c, y, n, dd, f_shift, s);
-    else if (r == 2) e = fm_merge_pass<Q, 2>(c, y, n, dd, f_shift, s);
-    else if constexpr (RM >= 3) {
-      if (r == 3) e = fm_merge_pass<Q, 3>(c, y, n, dd, f_shift, s);
-      else if constexpr (RM >= 4) {
-        if (r == 4) e = fm_merge_pass<Q, 4>(c, y, n, dd, f_shift, s);
-      }
-    }
+  for (int i = np - 1; i >= 0 && e == hipSuccess; --i) {
+    const uint32_t dd = (uint32_t)pd[i];
+    if (pr[i] == 4) e = fm_merge4_pass<Q>(c, y, n, dd, f_shift, s);
+    else if (pr[i] == 2) e = fm_merge_pass<Q, 2>(c, y, n, dd, f_shift, s);
+    else e = fm_merge_pass<Q, 1>(c, y, n, dd, f_shift, s);
   }
   return e;
 }
