@@ -22,9 +22,6 @@ namespace {
 
 constexpr uint32_t Q1 = 998244353u, Q2 = 469762049u, Q3 = 167772161u;
 
-// Both loaders read unconditionally (element 0 when the index is past the data: na and nb
-// are at least 1) and select zero afterwards, so the loads of a stage are all issued before
-// the first wait instead of one branch, load and wait per element.
 // A signed 32-bit input enters as a residue in (0, 3p), not reduced further: every first
 // operation of the product (split butterfly, or the leaf product of a one-element block)
 // takes operands below 4p. v + 2^31 is brought to [0, 2p) by Shoup's method with w = 1,
@@ -39,6 +36,9 @@ __device__ __forceinline__ uint32_t residue_of(const Zp& R, V v) {
     return (uint32_t)v;
   }
 }
+// Both loaders read unconditionally (element 0 when the index is past the data: na and nb
+// are at least 1) and select zero afterwards, so the loads of a stage are all issued before
+// the first wait instead of one branch, load and wait per element.
 template <class V>
 struct LdRowRev {  // r_k = a_((N - k) mod N), zero beyond na
   const V* a;
@@ -203,7 +203,7 @@ __global__ void __launch_bounds__(CARRY_NT) k_carry_scan1(Coef coef, uint64_t nl
   __shared__ uint32_t su[CARRY_PAD];
   __shared__ uint32_t sh[CARRY_NT / 64];
   const uint64_t jb = (uint64_t)blockIdx.x * CARRY_BLOCK;
-  // sc[k] = c_(jb + k - 4): the block's coefficients, then the 4 before it
+  // sc[k] = c_(jb + k - 4), k < 4100: the 4 coefficients before the block, then its 4096;
   // thread t < 4 also stages c_(jb + t - 4) (zero before the first limb)
   const uint64_t kx = jb + threadIdx.x >= 4 ? jb + threadIdx.x - 4 : coef.nc;
   typename Coef::Raw raw[CARRY_PER_THREAD], rx;
@@ -268,7 +268,7 @@ __global__ void __launch_bounds__(CARRY_NT) k_carry_scan2(const uint32_t* __rest
   uint32_t sv[4];
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
-    const uint32_t b = b0 + q < b1 ? b0 + q : 0;  // summary 0 exists whenever nb > 0
+    const uint32_t b = b0 + q < b1 ? b0 + q : 0;  // summary 0 always exists
     sv[2 * q] = summ[2 * b];
     sv[2 * q + 1] = summ[2 * b + 1];
   }
