@@ -386,22 +386,13 @@ inline hipError_t launch_block_l(Ctx& c, const PassArgs<Ring>& A, const typename
   using S = BlockShape<LOGR, 0, EL>;
   const uint64_t vwgs = (uint64_t)A.tiles * A.ninst;
   const uint32_t grid = (uint32_t)((vwgs + S::GROUPS - 1) / S::GROUPS);
-  // Up to one workgroup per CU: Montgomery-form staged twiddles (fewer instructions). More:
-  // Shoup pairs, whose kernel needs fewer registers, so that two 2^13-element blocks fit a
-  // CU (measured: three 2^21 products over Z/p, block pass 52.9 -> 46.6 us; one, 19.4 ->
-  // 18.3 us the other way).
-  // Only 2^13-element blocks have both forms: at 2^12 and 2^10 the two compile to the same
-  // register count, and rings whose deepest-stage form is the heap form have one kernel.
-  constexpr bool same = std::is_same_v<typename Ring::Tw, typename Ring::DeepW> || LOGR != 13;
-  const bool mont = same || grid <= (uint32_t)c.prop.multiProcessorCount;
-  size_t lds = block_lds_bytes<Ring, LOGR, 0, true, EL>();
-  auto k = k_block<Ring, LOGR, SrcA, SrcX, Dst, true, EL>;
-  if constexpr (!same) {
-    if (!mont) {
-      lds = block_lds_bytes<Ring, LOGR, 0, false, EL>();
-      k = k_block<Ring, LOGR, SrcA, SrcX, Dst, false, EL>;
-    }
-  }
+  // Montgomery-form staged twiddles (fewer instructions than Shoup pairs). With the deepest
+  // stage's twiddles pinned as 32-bit values the kernel needs 98 registers at 2^13 (148
+  // before), so two 2^13-element blocks fit a CU in this form too; measured on MI355X for
+  // three 2^21 products (polymul, bigint) against the Shoup-pair kernel then picked for
+  // launches of more blocks than CUs: 95.9 against 96.6-97.5 us, and 103.5 against 104.5 us.
+  const size_t lds = block_lds_bytes<Ring, LOGR, 0, true, EL>();
+  const auto k = k_block<Ring, LOGR, SrcA, SrcX, Dst, true, EL>;
   allow_lds(k, lds);
   return launch(c, "fcirc_block", s, [&](hipEvent_t e0_, hipEvent_t e1_) { FCIRC_LAUNCH(e0_, e1_, k, dim3(grid), dim3(S::NT), lds, s, A, rp[0], rp[1], rp[2], sa, sx, d); });
 }

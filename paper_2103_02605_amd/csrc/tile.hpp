@@ -652,6 +652,21 @@ struct DeepTw {
   typename Ring::DeepW t[EL], ti[EL];
 };
 
+// A copy of D whose 32-bit twiddles are pinned as 32-bit registers where the deepest stage
+// uses them. D is formed in one of two branches (the packed first-twiddle table or the heap
+// tables); without the pin the compiler merges the two as zero-extended 64-bit values, and
+// every Montgomery product with one of them becomes a 64 x 32-bit multiply (two multiplies
+// and a move instead of one multiply).
+template <class Ring, int EL>
+__device__ __forceinline__ DeepTw<Ring, EL> pinned(const DeepTw<Ring, EL>& D) {
+  DeepTw<Ring, EL> P = D;
+  if constexpr (std::is_same_v<typename Ring::DeepW, uint32_t>) {
+#pragma unroll
+    for (int j = 0; j < EL; ++j) asm volatile("" : "+v"(P.t[j]), "+v"(P.ti[j]));
+  }
+  return P;
+}
+
 // From the heap tables (any block at depth d0, levels l0 .. l0 + 3, item sub-block sb).
 template <class Ring, int EL>
 __device__ __forceinline__ void load_deep_heap(DeepTw<Ring, EL>& D, const Ring& R, typename Ring::Tw const* tw,
@@ -745,10 +760,11 @@ __device__ __forceinline__ void block_split_stage(const PassArgs<Ring>& A, const
         vx[u][i] = sx[row];
       }
     }
+  [[maybe_unused]] const DeepTw<Ring, EL> Dp = FROM_D ? pinned<Ring, EL>(D) : D;
 #pragma unroll
   for (int u = 0; u < IPT; ++u) {
     if constexpr (FROM_D)
-      split_levels_first<Ring, K>(R, va[u], vx[u], D.t, A.tu[rsel]);
+      split_levels_first<Ring, K>(R, va[u], vx[u], Dp.t, A.tu[rsel]);
     else if constexpr (FIRSTS)
       split_levels_first<Ring, K>(R, va[u], vx[u], Dl[u].t, A.tu[rsel]);
     else
@@ -762,7 +778,7 @@ __device__ __forceinline__ void block_split_stage(const PassArgs<Ring>& A, const
 #pragma unroll
     for (int u = 0; u < IPT; ++u) {
       if constexpr (FROM_D)
-        merge_levels_first<Ring, K>(R, va[u], D.ti, A.tui[rsel]);
+        merge_levels_first<Ring, K>(R, va[u], Dp.ti, A.tui[rsel]);
       else if constexpr (FIRSTS)
         merge_levels_first<Ring, K>(R, va[u], Dl[u].ti, A.tui[rsel]);
       else

@@ -131,9 +131,9 @@ def test_small_kernel_and_block_pass(F, ring, L):
 
 @pytest.mark.parametrize("count", [2, 300])
 def test_block_twiddle_forms(F, count):
-    """2^13-element blocks stage their twiddles as Montgomery words when the grid has at
-    most one workgroup per CU and as Shoup pairs otherwise (300 blocks on 256 CUs): both
-    forms bit-exact, on a batch of 2^13 products forced to one block pass."""
+    """2^13-element block passes with at most one workgroup per CU and with more (300
+    blocks on 256 CUs, two blocks resident per CU) bit-exact, on a batch of 2^13 products
+    forced to one block pass."""
     L = 13
     n = 1 << L
     p = P1
