@@ -85,12 +85,18 @@ struct Uniform16 {
   typename Ring::Tw tu[15], tui[15];
 };
 
+// Levels of the Z/p block factors (see PassArgs::ub): every block pass of at most 2^13.
+constexpr int ZP_UB_LEVELS = 13;
+constexpr size_t ZP_UB = ((size_t)1 << ZP_UB_LEVELS) - 1;
+
 struct ZpTables {
   uint32_t p = 0, f = 0;
   int levels = 0;  // covers depths d < levels
   ZpTw* tw = nullptr;
   ZpTw* twi = nullptr;
-  uint32_t* dU = nullptr;  // uniform factors in Montgomery form (device): tu[15] then tui[15]
+  // uniform factors in Montgomery form (device): tu[15], tui[15], then the block factors
+  // ub[ZP_UB] and ubi[ZP_UB]
+  uint32_t* dU = nullptr;
   // last first-twiddle of the deepest radix-16 stage per item, Montgomery form, per log2 n
   // (see PassArgs::ft)
   uint32_t* ft[27] = {nullptr};
@@ -512,6 +518,10 @@ inline PassArgs<Ring> product_pass_args(const Schedule& S, uint32_t count, typen
     A.tui[r] = U[r] + 15;
     A.ft[r] = FT ? FT[r] : nullptr;
     A.fti[r] = FTI ? FTI[r] : nullptr;
+    if constexpr (std::is_same_v<Ring, Zp>) {
+      A.ub[r] = U[r] + 30;
+      A.ubi[r] = U[r] + 30 + ZP_UB;
+    }
   }
   for (int i = 0; i < 3; ++i) {
     A.tw[i] = tw[i];

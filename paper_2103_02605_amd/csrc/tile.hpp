@@ -66,6 +66,13 @@ struct PassArgs {
   // first child's root is a square root of its parent's.
   typename Ring::DeepW const* ft[3];
   typename Ring::DeepW const* fti[3];
+  // Block factors (may be null): the twiddle of node (local level l, index g) of any block
+  // at depth d0 is the twiddle of the block's first node of level l times
+  // ub[2^l - 1 + g] = rho_l^brev_l(g) (a root of unity that depends on neither f, d0 nor
+  // the block; ubi the inverses), l < 13, in deepest-stage form. With them a block pass
+  // reads one heap twiddle per level instead of 2^l, and no first-twiddle table.
+  typename Ring::DeepW const* ub[3];
+  typename Ring::DeepW const* ubi[3];
 };
 
 // Workgroups are dispatched round-robin over the 8 XCDs (workgroup i runs on XCD i mod 8),
@@ -689,6 +696,21 @@ __device__ __forceinline__ void load_deep_tw(DeepTw<Ring, EL>& D, const Ring& R,
                                              uint32_t ltid) {
   constexpr uint32_t l0 = LOGR - EL;
   const Item it = item_at(ltid, LOGR, 0, l0, EL);
+  if constexpr (LOGR <= 13 && std::is_same_v<typename Ring::DeepW, uint32_t>) {
+    if (A.ub[rsel] != nullptr) {  // c_(EL-1): node (LOGR - 1, sb 2^(EL-1)) from the block factors
+      constexpr uint32_t l = LOGR - 1;
+      const uint32_t g0 = (1u << (A.d0 + l)) + (P.blk << l);
+      const uint32_t ge = (1u << l) - 1 + (it.sb << (EL - 1));
+      D.t[EL - 1] = R.deep_derive(R.to_deep(tw[g0]), A.ub[rsel][ge]);
+      D.ti[EL - 1] = R.deep_derive(R.to_deep(twi[g0]), A.ubi[rsel][ge]);
+#pragma unroll
+      for (int j = EL - 2; j >= 0; --j) {
+        D.t[j] = R.deep_sq(D.t[j + 1]);
+        D.ti[j] = R.deep_sq(D.ti[j + 1]);
+      }
+      return;
+    }
+  }
   if constexpr (EL == EPT_LOG) {
     if (A.ft[rsel] != nullptr && A.d0 + (uint32_t)LOGR == A.logn) {
       const uint32_t b0 = (P.blk << l0) + it.sb;  // node at depth logn - 4
@@ -875,11 +897,26 @@ __device__ __forceinline__ void block_pass(const PassArgs<Ring>& A, uint32_t vwg
         // (Montgomery form for Z/p: the vector split and the merge then take one instruction
         // less per butterfly, and the copy is half the size): level l of the block is the
         // contiguous heap range [2^(d0+l) + blk 2^l, + 2^l)
-        for (uint32_t e = ltid; e < (uint32_t)S::NTW; e += 1u << S::ACTIVE_LOG) {
-          const uint32_t l = 31u - __clz(e + 1);
-          const uint32_t gi = (1u << (A.d0 + l)) + (P.blk << l) + (e + 1 - (1u << l));
-          stw[e] = to_block_tw<Ring, MONT>(R, tw[gi]);
-          stwi[e] = to_block_tw<Ring, MONT>(R, twi[gi]);
+        bool staged = false;
+        if constexpr (MONT && LOGR <= 13 && std::is_same_v<typename Ring::DeepW, uint32_t>) {
+          if (A.ub[rsel] != nullptr) {
+            // from the block factors: one heap twiddle per level (the level's first node)
+            for (uint32_t e = ltid; e < (uint32_t)S::NTW; e += 1u << S::ACTIVE_LOG) {
+              const uint32_t l = 31u - __clz(e + 1);
+              const uint32_t g0 = (1u << (A.d0 + l)) + (P.blk << l);
+              stw[e] = R.deep_derive(R.to_deep(tw[g0]), A.ub[rsel][e]);
+              stwi[e] = R.deep_derive(R.to_deep(twi[g0]), A.ubi[rsel][e]);
+            }
+            staged = true;
+          }
+        }
+        if (!staged) {
+          for (uint32_t e = ltid; e < (uint32_t)S::NTW; e += 1u << S::ACTIVE_LOG) {
+            const uint32_t l = 31u - __clz(e + 1);
+            const uint32_t gi = (1u << (A.d0 + l)) + (P.blk << l) + (e + 1 - (1u << l));
+            stw[e] = to_block_tw<Ring, MONT>(R, tw[gi]);
+            stwi[e] = to_block_tw<Ring, MONT>(R, twi[gi]);
+          }
         }
         load_deep_tw<Ring, LOGR, EL>(D, R, A, P, rsel, tw, twi, ltid);
       }

@@ -118,20 +118,27 @@ ZpParams zp_params(uint32_t p, int L) {
   return q;
 }
 
-// Uniform radix-16 factors rho_j^brev_j(g) (j < 4) and their inverses, in Montgomery form
-// (w 2^32 mod p): out[0..15) split, out[15..30) merge.
-void zp_uniform16_mont(uint32_t p, uint32_t* out) {
+// Uniform factors rho_j^brev_j(g) and their inverses, in Montgomery form (w 2^32 mod p):
+// out[0..15) split and out[15..30) merge for the radix-16 items (j < 4), then the block
+// factors of j < ZP_UB_LEVELS: out[30 .. 30 + ZP_UB) split, the next ZP_UB merge.
+void zp_uniform_mont(uint32_t p, uint32_t* out) {
   // rho_j = gen^((p-1)/2^(j+1)), the same roots the tables are built from
   const uint32_t gen = generator(p);
   const uint32_t two32 = (uint32_t)(((uint64_t)1 << 32) % p);
-  for (int j = 0; j < 4; ++j) {
+  uint32_t* ub = out + 30;
+  uint32_t* ubi = ub + ZP_UB;
+  for (int j = 0; j < ZP_UB_LEVELS; ++j) {
     const uint32_t rho = powmod(gen, (uint64_t)(p - 1) >> (j + 1), p);
     for (uint32_t g = 0; g < (1u << j); ++g) {
       const uint32_t e = brev(g, j);
       const uint32_t w = powmod(rho, e, p), wi = invmod(w, p);
-      out[(1 << j) - 1 + g] = mulmod(w, two32, p);
-      out[15 + (1 << j) - 1 + g] = mulmod(wi, two32, p);
+      ub[(1 << j) - 1 + g] = mulmod(w, two32, p);
+      ubi[(1 << j) - 1 + g] = mulmod(wi, two32, p);
     }
+  }
+  for (int k = 0; k < 15; ++k) {
+    out[k] = ub[k];
+    out[15 + k] = ubi[k];
   }
 }
 
@@ -196,9 +203,10 @@ fcirc_status zp_tables(Ctx& c, uint32_t p, uint32_t f, int L, const ZpTables** o
   if (hipMemcpy(t.tw, tw.data(), ne * sizeof(ZpTw), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(t.twi, twi.data(), ne * sizeof(ZpTw), hipMemcpyHostToDevice) != hipSuccess)
     return FCIRC_EDEVICE;
-  uint32_t um[30];
-  zp_uniform16_mont(p, um);
-  if (hipMalloc(&t.dU, sizeof um) != hipSuccess || hipMemcpy(t.dU, um, sizeof um, hipMemcpyHostToDevice) != hipSuccess)
+  std::vector<uint32_t> um(30 + 2 * ZP_UB);
+  zp_uniform_mont(p, um.data());
+  const size_t ub_bytes = um.size() * sizeof(uint32_t);
+  if (hipMalloc(&t.dU, ub_bytes) != hipSuccess || hipMemcpy(t.dU, um.data(), ub_bytes, hipMemcpyHostToDevice) != hipSuccess)
     return FCIRC_ENOMEM;
   // Replace a smaller table for the same (p, f) only after the device is idle.
   for (auto& old : c.zp)
