@@ -88,7 +88,7 @@ class _Enqueue:
             ctx.lock.release()
             raise
         self.handle = h
-        return C.c_void_p(h)
+        return h  # ctypes passes an int as the stream's void*
 
     def __exit__(self, *exc):
         self.ctx._last_stream = self.handle  # raw handle of the stream of this call
@@ -101,7 +101,10 @@ _contexts_lock = threading.Lock()
 
 
 def context(device=None) -> Context:
-    idx = torch.cuda.current_device() if device is None else torch.device(device).index or 0
+    if isinstance(device, int):  # a device index (Tensor.get_device(); -1 for host tensors)
+        idx = max(device, 0)
+    else:
+        idx = torch.cuda.current_device() if device is None else torch.device(device).index or 0
     c = _contexts.get(idx)
     if c is not None:
         return c
@@ -111,8 +114,8 @@ def context(device=None) -> Context:
         return _contexts[idx]
 
 
-def _ptr(t: torch.Tensor) -> C.c_void_p:
-    return C.c_void_p(t.data_ptr())
+def _ptr(t: torch.Tensor) -> int:
+    return t.data_ptr()  # ctypes passes an int as void*
 
 
 def _need(t: torch.Tensor, name: str):
@@ -158,7 +161,7 @@ def matvec(a: torch.Tensor, x: torch.Tensor, f=None, p: int | None = None, out: 
         raise ValueError("a and x must be tensors of the same shape and dtype, one vector each")
     y = torch.empty_like(a) if out is None else out
     _need(y, "out")
-    ctx = context(a.device)
+    ctx = context(a.get_device())
     with ctx.enqueue() as s:
         L.check(L.lib().fcirc_matvec(ctx.handle, _ptr(a), _ptr(x), _ptr(y), a.shape[0], C.byref(fv), ring, s),
                 "fcirc_matvec")
@@ -175,7 +178,7 @@ def matvec_any(a: torch.Tensor, x: torch.Tensor, f=None, p: int | None = None, o
     ring, fv = _ring_and_f(a, f, p)
     y = torch.empty_like(a) if out is None else out
     _need(y, "out")
-    ctx = context(a.device)
+    ctx = context(a.get_device())
     with ctx.enqueue() as s:
         L.check(L.lib().fcirc_matvec_any(ctx.handle, _ptr(a), _ptr(x), _ptr(y), a.numel(), C.byref(fv), ring, s),
                 "fcirc_matvec_any")
@@ -192,7 +195,7 @@ def toeplitz_matvec(row: torch.Tensor, col: torch.Tensor, x: torch.Tensor, p: in
     ring, _ = _ring_and_f(row, None, p)
     y = torch.empty_like(row) if out is None else out
     _need(y, "out")
-    ctx = context(row.device)
+    ctx = context(row.get_device())
     with ctx.enqueue() as s:
         L.check(L.lib().fcirc_toeplitz_matvec(ctx.handle, _ptr(row), _ptr(col), _ptr(x), _ptr(y), row.numel(), ring,
                                               s), "fcirc_toeplitz_matvec")
@@ -211,7 +214,7 @@ def matvec_many(a: torch.Tensor, x: torch.Tensor, f=None, p: int | None = None, 
     y = torch.empty_like(a) if out is None else out
     if a.shape[0] == 0:  # an empty batch: nothing to compute (empty tensors have null pointers)
         return y
-    ctx = context(a.device)
+    ctx = context(a.get_device())
     with ctx.enqueue() as s:
         L.check(L.lib().fcirc_matvec_many(ctx.handle, _ptr(a), _ptr(x), _ptr(y), a.shape[1], a.shape[0], C.byref(fv),
                                           ring, s), "fcirc_matvec_many")
@@ -225,7 +228,7 @@ def polymul_i64(a: torch.Tensor, b: torch.Tensor, out: torch.Tensor | None = Non
     if a.dtype != torch.int32 or b.dtype != torch.int32:
         raise TypeError("polymul_i64 takes int32 coefficient tensors")
     c = torch.empty(a.numel() + b.numel() - 1, dtype=torch.int64, device=a.device) if out is None else out
-    ctx = context(a.device)
+    ctx = context(a.get_device())
     with ctx.enqueue() as s:
         L.check(L.lib().fcirc_polymul_i64(ctx.handle, _ptr(a), a.numel(), _ptr(b), b.numel(), _ptr(c), s),
                 "fcirc_polymul_i64")
@@ -239,7 +242,7 @@ def bigint_mul(a: torch.Tensor, b: torch.Tensor, out: torch.Tensor | None = None
     if a.dtype not in (torch.uint16, torch.int16) or b.dtype != a.dtype:
         raise TypeError("bigint_mul takes uint16 (or int16-viewed) limb tensors")
     c = torch.empty(a.numel() + b.numel(), dtype=a.dtype, device=a.device) if out is None else out
-    ctx = context(a.device)
+    ctx = context(a.get_device())
     with ctx.enqueue() as s:
         L.check(L.lib().fcirc_bigint_mul(ctx.handle, _ptr(a), a.numel(), _ptr(b), b.numel(), _ptr(c), s),
                 "fcirc_bigint_mul")
@@ -259,7 +262,7 @@ def fermat_matvec(a: torch.Tensor, x: torch.Tensor, K: int, f_shift: int = 0, ou
         raise ValueError(f"elements of Z/(2^{K} + 1) take {K // 32 + 1} words")
     y = torch.empty_like(a) if out is None else out
     _need(y, "out")
-    ctx = context(a.device)
+    ctx = context(a.get_device())
     with ctx.enqueue() as s:
         L.check(L.lib().fcirc_fermat_matvec(ctx.handle, _ptr(a), _ptr(x), _ptr(y), a.shape[0], int(K), int(f_shift),
                                             s), "fcirc_fermat_matvec")
@@ -273,7 +276,7 @@ def bigint_mul_fermat(a: torch.Tensor, b: torch.Tensor, out: torch.Tensor | None
     if a.dtype not in (torch.int16, torch.uint16) or b.dtype != a.dtype:
         raise TypeError("bigint_mul_fermat takes uint16 (or int16-viewed) limb tensors")
     c = torch.empty(a.numel() + b.numel(), dtype=a.dtype, device=a.device) if out is None else out
-    ctx = context(a.device)
+    ctx = context(a.get_device())
     with ctx.enqueue() as s:
         L.check(L.lib().fcirc_bigint_mul_fermat(ctx.handle, _ptr(a), a.numel(), _ptr(b), b.numel(), _ptr(c), s),
                 "fcirc_bigint_mul_fermat")
@@ -408,7 +411,7 @@ def layer_forward(a: torch.Tensor, x: torch.Tensor) -> torch.Tensor:
     if x.dim() != 2 or a.dim() != 1 or x.shape[1] != a.shape[0] or x.dtype != a.dtype:
         raise ValueError("a must be (n,) and x (batch, n) of the same dtype")
     y = torch.empty_like(x)
-    ctx = context(a.device)
+    ctx = context(a.get_device())
     with ctx.enqueue() as s:
         L.check(L.lib().fcirc_matvec_fwd_shared(ctx.handle, _ptr(a), _ptr(x), _ptr(y), a.shape[0], x.shape[0],
                                                 _layer_ring(a), s), "fcirc_matvec_fwd_shared")
@@ -422,7 +425,7 @@ def layer_backward(a: torch.Tensor, x: torch.Tensor, gy: torch.Tensor, need_a: b
     _need(gy, "gy")
     ga = torch.empty_like(a) if need_a else None
     gx = torch.empty_like(x) if need_x else None
-    ctx = context(a.device)
+    ctx = context(a.get_device())
     with ctx.enqueue() as s:
         L.check(L.lib().fcirc_matvec_backward(ctx.handle, _ptr(a), _ptr(x), _ptr(gy),
                                               _ptr(ga) if ga is not None else None,
