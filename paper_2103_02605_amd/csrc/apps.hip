@@ -196,7 +196,7 @@ struct CoefCrt {  // unsigned coefficients: v3 must be 0, else the range flag is
 // Pass 1: u_j into `u`, and each workgroup's (G, P) summary. The block's coefficients
 // (plus 4 before it) are staged in LDS with coalesced loads; thread t computes u for limbs
 // t + 256 i (consecutive lanes, consecutive words), then takes the GP summary of its own
-// contiguous run of 16.
+// contiguous run of CARRY_PER_THREAD.
 template <class Coef>
 __global__ void __launch_bounds__(CARRY_NT) k_carry_scan1(Coef coef, uint64_t nl, uint32_t* __restrict__ u,
                                                           uint32_t* __restrict__ summ) {
@@ -204,7 +204,8 @@ __global__ void __launch_bounds__(CARRY_NT) k_carry_scan1(Coef coef, uint64_t nl
   __shared__ uint32_t su[CARRY_PAD];
   __shared__ uint32_t sh[CARRY_NT / 64];
   const uint64_t jb = (uint64_t)blockIdx.x * CARRY_BLOCK;
-  // sc[k] = c_(jb + k - 4), k < 4100: the 4 coefficients before the block, then its 4096;
+  // sc[k] = c_(jb + k - 4), k < CARRY_BLOCK + 4: the 4 coefficients before the block, then
+  // its CARRY_BLOCK;
   // thread t < 4 also stages c_(jb + t - 4) (zero before the first limb)
   const uint64_t kx = jb + threadIdx.x >= 4 ? jb + threadIdx.x - 4 : coef.nc;
   typename Coef::Raw raw[CARRY_PER_THREAD], rx;
