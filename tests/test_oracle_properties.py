@@ -68,3 +68,40 @@ def test_single_entry(p, L, phi, seed, i):
     n, f, a, x = _case(p, L, phi, seed)
     i %= n
     assert O.matvec_entry_modp(a, x, f, p, i) == int(O.levels_matvec_modp(a, x, f, p)[i])
+
+
+@SETTINGS
+@given(p=st.sampled_from(PRIMES), L=st.integers(2, 12), phi=st.integers(0, 2**40), phi2=st.integers(0, 2**40),
+       d0=st.integers(0, 11), blk=st.integers(0, 2**20))
+def test_block_factors_of_the_root_ladder(p, L, phi, phi2, d0, blk):
+    """Inside any block of the recursion (depth d0, index blk), the square root at local
+    level l and index g is the block's first root of that level times a factor that
+    depends on (l, g) only: not on the block, its depth, or f. The factors of level l are
+    the powers w_l^brev_l(g) of one primitive 2^(l+1)-th root of unity. (The GPU path
+    forms the roots of its block passes this way.)"""
+    n = 1 << L
+    d0 %= L
+    blk %= 1 << d0
+    fs = [pow(v % (p - 1) + 1, n, p) for v in (phi, phi2)]
+    ladders = [O.node_roots_modp(n, f, p) for f in fs]
+
+    def brev(g, l):
+        return int(format(g, f"0{l}b")[::-1], 2) if l else 0
+
+    for l in range(L - d0):
+        d = d0 + l
+        per_case = []
+        for gs in ladders:
+            for b in {blk, (blk + 1) % (1 << d0), 0}:
+                first = int(gs[d][b << l])
+                inv = pow(first, p - 2, p)
+                per_case.append([int(gs[d][(b << l) + g]) * inv % p for g in range(1 << l)])
+        for r in per_case[1:]:
+            assert r == per_case[0], (l, d0)
+        ratio = per_case[0]
+        if l == 0:
+            assert ratio == [1]
+            continue
+        w = ratio[brev(1, l)]  # the factor of exponent 1
+        assert pow(w, 1 << l, p) == p - 1  # primitive 2^(l+1)-th root of unity
+        assert ratio == [pow(w, brev(g, l), p) for g in range(1 << l)]
